@@ -1,0 +1,179 @@
+/*
+ * liblbf — MI355X (gfx950) coupled lattice Boltzmann freezing step.
+ *
+ * The method is the diffuse-interface freezing model of Huang, Zhan, Chai and
+ * Huang (arXiv 2510.18688): a pressure-based flow LB with surface tension, a
+ * mass source and a solid drag (Sec. 3.1), a modified phase-field LB
+ * (Sec. 3.2) and a total-enthalpy two-relaxation-time LB (Sec. 3.3, eq22)
+ * coupled through the enthalpy map (Sec. 2, eq. Hfl), the mixing rule for
+ * the properties (Sec. 2) and the chemical potential of the free energy eq44.
+ * One call of lbf_step advances the coupled D2Q9 lattice by whole time steps.
+ *
+ * Conventions shared by every entry point:
+ *  - A lattice has nx * ny nodes; node (x, y) of a 2D field is element
+ *    y * nx + x (row-major, x fastest).  Walls sit half-way, at y = -1/2 and
+ *    y = ny - 1/2 (and x = -1/2, x = nx - 1/2 when x is walled).
+ *  - Float fields are IEEE binary32.  Host pointers are read or written
+ *    synchronously; device pointers (on_device = 1) must be device memory
+ *    valid on the stream the simulation was created with.
+ *  - Every call returns LBF_OK (0) or a negative error code; the text of the
+ *    last error of the calling thread is lbf_last_error().  No call throws.
+ *  - Calls on one simulation are ordered on its HIP stream.  A simulation is
+ *    used by one host thread at a time.
+ */
+#ifndef LBF_H
+#define LBF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  LBF_OK = 0,
+  LBF_EINVAL = -1,    /* invalid argument or parameter set */
+  LBF_EHIP = -2,      /* a HIP runtime call failed */
+  LBF_ESTATE = -3,    /* call order: e.g. stepping before initialisation */
+  LBF_EUNSTABLE = -4, /* non-finite values or |u| above the stability bound */
+  LBF_ENOMEM = -5     /* workspace too small / allocation failed */
+};
+
+/* walls, in every per-wall array */
+enum { LBF_WALL_BOTTOM = 0, LBF_WALL_TOP = 1, LBF_WALL_LEFT = 2, LBF_WALL_RIGHT = 3 };
+enum { LBF_ADIABATIC = 0, LBF_DIRICHLET = 1 };
+
+/* read-out fields of lbf_read_field, all at the current time level */
+enum {
+  LBF_FIELD_PHI = 0,    /* order parameter phi (Sec. 3.2 recovery) */
+  LBF_FIELD_T = 1,      /* temperature (enthalpy map, Hfl) */
+  LBF_FIELD_FL = 2,     /* liquid fraction 1 - f_s at node level */
+  LBF_FIELD_FS = 3,     /* ice volume fraction f_s */
+  LBF_FIELD_UX = 4,     /* velocity u (Sec. 3.1 recovery, drag included) */
+  LBF_FIELD_UY = 5,
+  LBF_FIELD_P = 6,      /* pressure (Sec. 3.1 recovery) */
+  LBF_FIELD_RHOH = 7,   /* total enthalpy rho H */
+  LBF_FIELD_MU = 8,     /* chemical potential mu_phi (eq44 derivative) */
+  LBF_FIELD_C = 9,      /* liquid weight (1 - phi0 + phi_hat)/2, clamped */
+  LBF_FIELD_CHI = 10,   /* phase-change fraction of the node */
+  LBF_FIELD_RHO = 11,   /* density from the mixing rule */
+  LBF_FIELD_PHIHAT = 12,/* zeroth moment sum_i g_i */
+  LBF_NFIELDS = 13
+};
+
+/* entries of lbf_reduce's output (FP64, fixed-order reduction) */
+enum {
+  LBF_RED_SUM_G = 0,     /* sum over nodes and directions of g_i */
+  LBF_RED_SUM_H = 1,     /* sum of h_i (total energy) */
+  LBF_RED_SUM_FS = 2,    /* ice volume */
+  LBF_RED_SUM_LIQ = 3,   /* liquid PCM volume sum (chi - f_s) */
+  LBF_RED_UMAX = 4,      /* max |u| */
+  LBF_RED_NONFINITE = 5, /* count of nodes with a non-finite phi, T, u or p */
+  LBF_RED_SRC_PHI = 6,   /* last step: sum phi * mdot (phase-field source) */
+  LBF_RED_SRC_HEAT = 7,  /* last step: heat source of the TRT collision */
+  LBF_RED_WALL_FLUX = 8, /* last step: energy entering through Dirichlet walls */
+  LBF_RED_RESET = 9,     /* last step: energy change of isothermal-region resets */
+  LBF_RED_STEP = 10,     /* steps taken since initialisation */
+  LBF_NRED = 11
+};
+
+/* Physical and lattice parameters (lattice units, dx = dt = 1).
+ * Properties of the three phases enter the mixing rule of Sec. 2; the
+ * relaxation times follow from them as in Sec. 3.1-3.3. */
+typedef struct lbf_params {
+  int32_t nx, ny;              /* lattice size, each >= 1 */
+  int32_t periodic_x;          /* 1 periodic, 0 walls at x = -1/2, nx - 1/2 */
+  int32_t periodic_y;          /* 1 periodic, 0 walls at y = -1/2, ny - 1/2 */
+  int32_t thermal_bc[4];       /* per wall: LBF_ADIABATIC or LBF_DIRICHLET */
+  int32_t latch_fs;            /* 1: PCM fraction latched by the previous ice fraction */
+  int32_t h_src_tau_a;         /* 1: enthalpy source prefactor with tau_a, 0: tau_s */
+  int32_t substrate_fixed;     /* 1: nodes with phi0 >= 1/2 held at T_substrate */
+  int32_t reserved;
+  double rho_l, rho_g, rho_s;  /* densities */
+  double mu_l, mu_g, mu_s;     /* dynamic viscosities */
+  double lam_l, lam_g, lam_s;  /* thermal conductivities */
+  double cp_l, cp_g, cp_s;     /* specific heats */
+  double latent, T_m;          /* latent heat, melting temperature */
+  double sigma, eps;           /* surface tension, interface width */
+  double mobility;             /* Cahn-Hilliard mobility Mbar */
+  double cos_psi;              /* cosine of the water-ice contact angle */
+  double rho_ref;              /* reference density of the enthalpy LB */
+  double T_substrate;          /* temperature of held solid nodes */
+} lbf_params;
+
+typedef struct lbf_sim lbf_sim;
+
+/* Bytes of device workspace one simulation needs (distributions, lagged
+ * fields, static fields, reduction scratch), or 0 for invalid sizes. */
+size_t lbf_workspace_bytes(int32_t nx, int32_t ny);
+
+/* Create a simulation on HIP stream `stream` (a hipStream_t, NULL for the
+ * default stream).  `workspace` is caller-owned device memory of at least
+ * lbf_workspace_bytes(nx, ny) bytes, 256-byte aligned, that must outlive the
+ * simulation; with workspace == NULL the library allocates it with hipMalloc
+ * and frees it in lbf_destroy.  Rejects with LBF_EINVAL: non-positive sizes,
+ * non-positive densities, specific heats, viscosities or conductivities,
+ * eps <= 0, mobility <= 0, and rho_ref C_p,ref larger than the smallest
+ * possible nodal heat capacity (the enthalpy scheme is then unstable). */
+int lbf_create(const lbf_params* params, void* stream, void* workspace, size_t workspace_bytes,
+               lbf_sim** out);
+
+/* Geometry: the diffuse solid label phi0 in [0, 1] (Sec. 2, Omega_0) and the
+ * per-node cosine of the contact angle theta (eq44), nx * ny floats each.
+ * The static Laplacian of phi0 is computed on the device. */
+int lbf_set_geometry(lbf_sim* sim, const float* phi0, const float* cos_theta, int32_t on_device);
+
+/* Temperature profile of one wall, used by its anti-bounce-back rule when the
+ * wall is LBF_DIRICHLET: n = nx floats for bottom/top (indexed by x),
+ * n = ny floats for left/right (indexed by y). */
+int lbf_set_wall_temperature(lbf_sim* sim, int32_t wall, const float* Tw, int32_t n,
+                             int32_t on_device);
+
+/* Initial state from the order parameter phi and temperature T (nx * ny
+ * each): u = 0, p = 0, phase-field and enthalpy distributions at
+ * equilibrium, the phase-change material liquid.  Requires the geometry. */
+int lbf_init_fields(lbf_sim* sim, const float* phi, const float* T, int32_t on_device);
+
+/* Advance nsteps coupled time steps (nsteps >= 0).  Asynchronous on the
+ * simulation's stream. */
+int lbf_step(lbf_sim* sim, int32_t nsteps);
+
+/* Compute one read-out field (LBF_FIELD_*) of the current state into dst
+ * (nx * ny floats, host or device). */
+int lbf_read_field(lbf_sim* sim, int32_t field_id, float* dst, int32_t dst_on_device);
+
+/* Compute every read-out field into dst (LBF_NFIELDS * nx * ny floats,
+ * field-major). */
+int lbf_read_fields(lbf_sim* sim, float* dst, int32_t dst_on_device);
+
+/* FP64 global sums of the current state and the budget of the last step
+ * (LBF_RED_*), written to host memory out[LBF_NRED].  Synchronises the
+ * stream.  Returns LBF_EUNSTABLE (after filling out) if a node is
+ * non-finite or max |u| exceeds 0.3. */
+int lbf_reduce(lbf_sim* sim, double* out);
+
+/* Launch shape of the step kernel: threads per block along x (64, 128, 256)
+ * and rows per block along y (>= 1).  Defaults are chosen at creation. */
+int lbf_set_tile(lbf_sim* sim, int32_t tile_x, int32_t tile_y);
+int lbf_get_tile(const lbf_sim* sim, int32_t* tile_x, int32_t* tile_y);
+
+/* Bytes of the checkpointable dynamic state and copy of it to / from `buf`
+ * (device memory).  A loaded state continues bit-identically. */
+size_t lbf_state_bytes(const lbf_sim* sim);
+int lbf_save_state(lbf_sim* sim, void* dst_device, size_t cap);
+int lbf_load_state(lbf_sim* sim, const void* src_device, size_t bytes);
+
+/* Average duration in milliseconds of the step kernel over the launches of
+ * the last lbf_step call, from HIP events on the simulation's stream (0 if
+ * timing is off).  lbf_set_timing(sim, 1) brackets each launch with events. */
+int lbf_set_timing(lbf_sim* sim, int32_t on);
+double lbf_last_step_kernel_ms(const lbf_sim* sim);
+
+const char* lbf_last_error(void);
+void lbf_destroy(lbf_sim* sim);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,52 @@
+"""Tile-shape autotuner of the step kernel.
+
+For a lattice size it times every candidate launch shape (threads per block
+along x, rows per block along y) with HIP events on the simulation's stream
+and persists the fastest in tiles.json next to this file, keyed by "NXxNY".
+"""
+
+from __future__ import annotations
+
+import json
+import os
+from typing import Iterable, Optional, Sequence, Tuple
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+DB = os.path.join(HERE, "tiles.json")
+
+CANDIDATES: Tuple[Tuple[int, int], ...] = tuple(
+    (tx, ty) for tx in (64, 128, 256) for ty in (8, 16, 32, 64, 128))
+
+
+def _load() -> dict:
+    if os.path.exists(DB):
+        with open(DB) as f:
+            return json.load(f)
+    return {}
+
+
+def lookup(nx: int, ny: int) -> Optional[Tuple[int, int]]:
+    v = _load().get(f"{nx}x{ny}")
+    return tuple(v["tile"]) if v else None
+
+
+def tune(sim, steps: int = 20, candidates: Iterable[Sequence[int]] = CANDIDATES,
+         save: bool = True) -> Tuple[Tuple[int, int], dict]:
+    """Time each candidate on `sim` (its state advances) and keep the best."""
+    times = {}
+    sim.set_timing(True)
+    for tx, ty in candidates:
+        sim.set_tile(tx, ty)
+        sim.step(2)
+        sim.step(steps)
+        times[f"{tx}x{ty}"] = sim.last_step_kernel_ms()
+    sim.set_timing(False)
+    best = min(times, key=times.get)
+    tile = tuple(int(v) for v in best.split("x"))
+    sim.set_tile(*tile)
+    if save:
+        db = _load()
+        db[f"{sim.nx}x{sim.ny}"] = {"tile": list(tile), "ms": times[best], "all": times}
+        with open(DB, "w") as f:
+            json.dump(db, f, indent=1, sort_keys=True)
+    return tile, times

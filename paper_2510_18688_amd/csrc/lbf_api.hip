@@ -1,0 +1,606 @@
+// C ABI of liblbf (declarations and contracts in include/lbf.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "lbf.h"
+#include "lbf_device.hpp"
+#include "lbf_step.hpp"
+
+using namespace lbf;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                 \
+  do {                                                                                \
+    hipError_t e_ = (expr);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      return fail(LBF_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_));           \
+  } while (0)
+
+constexpr size_t kAlign = 256;
+
+size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Plane stride: nx * ny rounded up to 64 floats (256 bytes).
+long long plane_stride(int nx, int ny) { return (long long)round_up((size_t)nx * ny, 64); }
+
+// Worst-case number of per-block partial sums: 64-wide strips, 1 row each.
+size_t max_blocks(int nx, int ny) { return ((size_t)(nx + 63) / 64) * (size_t)ny; }
+
+struct Layout {
+  size_t dist[2], lag[2], stat, fields, wall, red[2], redfinal, total;
+  int wstride;
+};
+
+Layout make_layout(int nx, int ny) {
+  Layout L{};
+  const size_t P = (size_t)plane_stride(nx, ny) * sizeof(float);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = round_up(off + bytes, kAlign);
+    return o;
+  };
+  L.dist[0] = take(NDIST * P);
+  L.dist[1] = take(NDIST * P);
+  L.lag[0] = take(NLAG * P);
+  L.lag[1] = take(NLAG * P);
+  L.stat = take(NSTAT * P);
+  L.fields = take(NFIELD * P);
+  L.wstride = (int)round_up((size_t)std::max(nx, ny), 64);
+  L.wall = take(4 * (size_t)L.wstride * sizeof(float));
+  const size_t rb = max_blocks(nx, ny) * NRED * sizeof(double);
+  L.red[0] = take(rb);
+  L.red[1] = take(rb);
+  L.redfinal = take(2 * NRED * sizeof(double));
+  L.total = off;
+  return L;
+}
+
+}  // namespace
+
+struct lbf_sim {
+  lbf_params prm;
+  Geo G;
+  Phys ph;
+  Layout L;
+  hipStream_t stream;
+  char* ws;
+  bool owns_ws;
+  int cur;           // which distribution / lag buffer holds the current state
+  bool have_geo, have_init;
+  int tile_x, tile_y;
+  long long step;
+  bool have_budget;  // red[0] holds the budget of the last step
+  int budget_blocks;
+  bool timing;
+  double last_ms;
+  hipEvent_t ev0, ev1;
+  double* host_red;  // pinned host buffer for reductions
+};
+
+namespace {
+
+float* fptr(lbf_sim* s, size_t off) { return reinterpret_cast<float*>(s->ws + off); }
+double* dptr(lbf_sim* s, size_t off) { return reinterpret_cast<double*>(s->ws + off); }
+
+Bufs make_bufs(lbf_sim* s) {
+  Bufs B{};
+  B.din = fptr(s, s->L.dist[s->cur]);
+  B.dout = fptr(s, s->L.dist[1 - s->cur]);
+  B.lin = fptr(s, s->L.lag[s->cur]);
+  B.lout = fptr(s, s->L.lag[1 - s->cur]);
+  B.stat = fptr(s, s->L.stat);
+  B.wallT = fptr(s, s->L.wall);
+  B.wstride = s->L.wstride;
+  B.fields = fptr(s, s->L.fields);
+  B.red = nullptr;
+  return B;
+}
+
+int validate(const lbf_params* p) {
+  if (!p) return fail(LBF_EINVAL, "params is NULL");
+  if (p->nx < 1 || p->ny < 1) return fail(LBF_EINVAL, "lattice size %d x %d", p->nx, p->ny);
+  if ((long long)p->nx * p->ny > (1LL << 31) - 64)
+    return fail(LBF_EINVAL, "lattice of %d x %d nodes exceeds 2^31", p->nx, p->ny);
+  const double pos[] = {p->rho_l, p->rho_g, p->rho_s, p->mu_l, p->mu_g, p->mu_s, p->lam_l,
+                        p->lam_g, p->lam_s, p->cp_l, p->cp_g, p->cp_s, p->eps, p->mobility,
+                        p->rho_ref};
+  for (double v : pos)
+    if (!(v > 0.0) || !std::isfinite(v))
+      return fail(LBF_EINVAL, "densities, viscosities, conductivities, heat capacities, eps, "
+                              "mobility and rho_ref must be positive and finite");
+  if (!(p->latent >= 0.0) || !(p->sigma >= 0.0))
+    return fail(LBF_EINVAL, "latent heat and surface tension must be non-negative");
+  for (int w = 0; w < 4; ++w)
+    if (p->thermal_bc[w] != LBF_ADIABATIC && p->thermal_bc[w] != LBF_DIRICHLET)
+      return fail(LBF_EINVAL, "thermal_bc[%d] = %d", w, p->thermal_bc[w]);
+  const double cpref = 2.0 * p->cp_s * p->cp_l / (p->cp_s + p->cp_l);
+  const double kmin = std::min({p->rho_l, p->rho_g, p->rho_s}) *
+                      std::min({p->cp_l, p->cp_g, p->cp_s});
+  if (p->rho_ref * cpref > kmin * (1.0 + 1e-12))
+    return fail(LBF_EINVAL,
+                "rho_ref * C_p,ref = %g exceeds the smallest nodal heat capacity %g: the "
+                "enthalpy scheme would be unstable",
+                p->rho_ref * cpref, kmin);
+  return LBF_OK;
+}
+
+void fill_phys(const lbf_params* p, Phys& ph) {
+  ph.rho_l = (float)p->rho_l; ph.rho_g = (float)p->rho_g; ph.rho_s = (float)p->rho_s;
+  ph.mu_l = (float)p->mu_l; ph.mu_g = (float)p->mu_g; ph.mu_s = (float)p->mu_s;
+  ph.lam_l = (float)p->lam_l; ph.lam_g = (float)p->lam_g; ph.lam_s = (float)p->lam_s;
+  ph.cp_l = (float)p->cp_l; ph.cp_g = (float)p->cp_g; ph.cp_s = (float)p->cp_s;
+  ph.latent = (float)p->latent;
+  ph.T_m = (float)p->T_m;
+  ph.cos_psi = (float)p->cos_psi;
+  ph.T_sub = (float)p->T_substrate;
+  ph.a3 = (float)(3.0 * p->sigma / p->eps);
+  ph.kap = (float)(3.0 * p->eps * p->sigma / 8.0);
+  ph.tau_g = (float)(3.0 * p->mobility + 0.5);
+  const double Eref = p->rho_ref * 2.0 * p->cp_s * p->cp_l / (p->cp_s + p->cp_l);
+  ph.Eref = (float)Eref;
+  ph.three_over_Eref = (float)(3.0 / Eref);
+  ph.mdot_coef = (float)(1.0 - p->rho_s / p->rho_l);
+  ph.latch = p->latch_fs ? 1 : 0;
+  ph.src_tau_a = p->h_src_tau_a ? 1 : 0;
+  ph.subfix = p->substrate_fixed ? 1 : 0;
+}
+
+// ---------------------------------------------------------------- kernels
+__global__ void k_lap_static(Geo G, float* stat) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+  if (x >= G.nx || y >= G.ny) return;
+  const float* phi0 = stat + ST_PHI0 * G.P;
+  const float c = phi0[y * G.nx + x];
+  float lap = 0.0f;
+#pragma unroll
+  for (int i = 1; i < 9; ++i) {
+    const int xx = map_axis(x + cx(i), G.nx, G.px), yy = map_axis(y + cy(i), G.ny, G.py);
+    lap += wgt(i) * (phi0[yy * G.nx + xx] - c);
+  }
+  stat[ST_LAP0 * G.P + y * G.nx + x] = 6.0f * lap;
+}
+
+// Equilibrium populations of the initial state, in post-stream form, into
+// `tmp` (NDIST planes); `in` holds phi (plane 0) and T (plane 1).
+__global__ void k_init_eq(Geo G, Phys ph, const float* stat, const float* in, float* tmp) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+  if (x >= G.nx || y >= G.ny) return;
+  const long long P = G.P;
+  const int k = y * G.nx + x;
+  const float* phi = in;
+  const float* T0 = in + P;
+  const float pc = phi[k];
+  float lap = 0.0f;
+#pragma unroll
+  for (int i = 1; i < 9; ++i) {
+    const int xx = map_axis(x + cx(i), G.nx, G.px), yy = map_axis(y + cy(i), G.ny, G.py);
+    lap += wgt(i) * (phi[yy * G.nx + xx] - pc);
+  }
+  lap *= 6.0f;
+  const float phi0 = stat[ST_PHI0 * P + k];
+  const float mu = chem_pot(ph, pc, lap, phi0, stat[ST_CTH * P + k], stat[ST_LAP0 * P + k], 0.0f,
+                            0.0f);
+  const float C = clampf(0.5f * (1.0f - phi0 + pc), 0.0f, 1.0f);
+  const float chi = clampf(C, 0.0f, 1.0f - phi0);
+  const float Kliq = zeta(phi0, C, ph.rho_s, ph.rho_l, ph.rho_g) *
+                     zeta(phi0, C, ph.cp_s, ph.cp_l, ph.cp_g);
+  const float Tk = T0[k];
+  const float rhoH = Kliq * (Tk - ph.T_m) + Kliq * ph.T_m + chi * ph.rho_l * ph.latent;
+  const float ET = ph.Eref * Tk;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    tmp[i * P + k] = 0.0f;
+    tmp[(9 + i) * P + k] = (i == 0 ? pc : 0.0f) + (wgt(i) - (i == 0 ? 1.0f : 0.0f)) * mu;
+    tmp[(18 + i) * P + k] = (i == 0) ? rhoH - ET + wgt(0) * ET : wgt(i) * ET;
+  }
+}
+
+// Inverse of the pull: post-collision populations whose pull gives `tmp`.
+__global__ void k_unstream(Geo G, Phys ph, const float* tmp, float* dst, const float* wallT,
+                           int wstride) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+  if (x >= G.nx || y >= G.ny) return;
+  const long long P = G.P;
+  const int k = y * G.nx + x;
+#pragma unroll
+  for (int j = 0; j < 9; ++j) {
+    // destination of population j leaving (x, y)
+    int dx = x + cx(j), dy = y + cy(j), wall = -1;
+    if (dy < 0 || dy >= G.ny) {
+      if (G.py) dy = dy < 0 ? dy + G.ny : dy - G.ny;
+      else wall = dy < 0 ? 0 : 1;
+    }
+    if (wall < 0 && (dx < 0 || dx >= G.nx)) {
+      if (G.px) dx = dx < 0 ? dx + G.nx : dx - G.nx;
+      else wall = dx < 0 ? 2 : 3;
+    }
+    if (wall < 0) {
+      const int d = dy * G.nx + dx;
+      dst[j * P + k] = tmp[j * P + d];
+      dst[(9 + j) * P + k] = tmp[(9 + j) * P + d];
+      dst[(18 + j) * P + k] = tmp[(18 + j) * P + d];
+    } else {
+      const int i = opp(j);   // the population that node (x, y) pulls back
+      dst[j * P + k] = tmp[i * P + k];
+      dst[(9 + j) * P + k] = tmp[(9 + i) * P + k];
+      if (G.tbc[wall]) {
+        const float Tw = wallT[wall * wstride + (wall < 2 ? x : y)];
+        dst[(18 + j) * P + k] = 2.0f * wgt(i) * ph.Eref * Tw - tmp[(18 + i) * P + k];
+      } else {
+        dst[(18 + j) * P + k] = tmp[(18 + i) * P + k];
+      }
+    }
+  }
+}
+
+// Fixed-order sum of per-block partials (one block of 256 threads).
+__global__ void k_reduce_blocks(const double* part, int nblocks, double* out) {
+  __shared__ double s[256];
+  for (int j = 0; j < NRED; ++j) {
+    double v = (j == 4) ? 0.0 : 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += blockDim.x) {
+      const double t = part[(size_t)b * NRED + j];
+      v = (j == 4) ? fmax(v, t) : v + t;
+    }
+    s[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w)
+        s[threadIdx.x] = (j == 4) ? fmax(s[threadIdx.x], s[threadIdx.x + w])
+                                  : s[threadIdx.x] + s[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) out[j] = s[0];
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------ launches
+int grid_blocks(const lbf_sim* s, dim3& grid) {
+  grid = dim3((s->G.nx + s->tile_x - 1) / s->tile_x, (s->G.ny + s->tile_y - 1) / s->tile_y, 1);
+  return (int)(grid.x * grid.y);
+}
+
+template <int WX>
+int launch_wx(lbf_sim* s, int mode, bool red, Bufs B) {
+  dim3 grid;
+  grid_blocks(s, grid);
+  const dim3 block(WX);
+  if (mode == MODE_STEP && !red)
+    hipLaunchKernelGGL((step_kernel<WX, MODE_STEP, false>), grid, block, 0, s->stream, s->G,
+                       s->ph, B, s->tile_y);
+  else if (mode == MODE_STEP && red)
+    hipLaunchKernelGGL((step_kernel<WX, MODE_STEP, true>), grid, block, 0, s->stream, s->G,
+                       s->ph, B, s->tile_y);
+  else if (mode == MODE_FIELDS && !red)
+    hipLaunchKernelGGL((step_kernel<WX, MODE_FIELDS, false>), grid, block, 0, s->stream, s->G,
+                       s->ph, B, s->tile_y);
+  else
+    hipLaunchKernelGGL((step_kernel<WX, MODE_FIELDS, true>), grid, block, 0, s->stream, s->G,
+                       s->ph, B, s->tile_y);
+  HIP_TRY(hipGetLastError());
+  return LBF_OK;
+}
+
+int launch_step(lbf_sim* s, int mode, bool red, double* red_buf) {
+  Bufs B = make_bufs(s);
+  B.red = red_buf;
+  switch (s->tile_x) {
+    case 64: return launch_wx<64>(s, mode, red, B);
+    case 128: return launch_wx<128>(s, mode, red, B);
+    case 256: return launch_wx<256>(s, mode, red, B);
+    default: return fail(LBF_EINVAL, "tile_x %d", s->tile_x);
+  }
+}
+
+dim3 node_grid(const lbf_sim* s) { return dim3((s->G.nx + 255) / 256, s->G.ny, 1); }
+
+int copy_in(lbf_sim* s, void* dst, const void* src, size_t bytes, int on_device) {
+  HIP_TRY(hipMemcpyAsync(dst, src, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                         s->stream));
+  if (!on_device) HIP_TRY(hipStreamSynchronize(s->stream));
+  return LBF_OK;
+}
+
+}  // namespace
+
+// ================================================================ C ABI
+extern "C" {
+
+const char* lbf_last_error(void) { return g_err.c_str(); }
+
+size_t lbf_workspace_bytes(int32_t nx, int32_t ny) {
+  if (nx < 1 || ny < 1) return 0;
+  return make_layout(nx, ny).total;
+}
+
+int lbf_create(const lbf_params* params, void* stream, void* workspace, size_t workspace_bytes,
+               lbf_sim** out) {
+  if (!out) return fail(LBF_EINVAL, "out is NULL");
+  *out = nullptr;
+  int rc = validate(params);
+  if (rc) return rc;
+  lbf_sim* s = new lbf_sim();
+  s->prm = *params;
+  s->G.nx = params->nx;
+  s->G.ny = params->ny;
+  s->G.px = params->periodic_x ? 1 : 0;
+  s->G.py = params->periodic_y ? 1 : 0;
+  for (int w = 0; w < 4; ++w) s->G.tbc[w] = params->thermal_bc[w];
+  s->G.P = plane_stride(params->nx, params->ny);
+  fill_phys(params, s->ph);
+  s->L = make_layout(params->nx, params->ny);
+  s->stream = (hipStream_t)stream;
+  if (workspace) {
+    if (workspace_bytes < s->L.total) {
+      delete s;
+      return fail(LBF_ENOMEM, "workspace of %zu bytes, %zu needed", workspace_bytes, s->L.total);
+    }
+    if ((uintptr_t)workspace % kAlign) {
+      delete s;
+      return fail(LBF_EINVAL, "workspace not 256-byte aligned");
+    }
+    s->ws = (char*)workspace;
+    s->owns_ws = false;
+  } else {
+    if (hipMalloc((void**)&s->ws, s->L.total) != hipSuccess) {
+      delete s;
+      return fail(LBF_ENOMEM, "hipMalloc of %zu bytes failed", s->L.total);
+    }
+    s->owns_ws = true;
+  }
+  s->tile_x = params->nx >= 128 ? 128 : 64;
+  s->tile_y = 32;
+  if (hipHostMalloc((void**)&s->host_red, 2 * NRED * sizeof(double), hipHostMallocDefault) !=
+          hipSuccess ||
+      hipEventCreate(&s->ev0) != hipSuccess || hipEventCreate(&s->ev1) != hipSuccess) {
+    lbf_destroy(s);
+    return fail(LBF_EHIP, "host buffer / event creation failed");
+  }
+  // wall profiles start at zero
+  if (hipMemsetAsync(s->ws + s->L.wall, 0, 4 * (size_t)s->L.wstride * sizeof(float), s->stream) !=
+      hipSuccess) {
+    lbf_destroy(s);
+    return fail(LBF_EHIP, "hipMemsetAsync failed");
+  }
+  *out = s;
+  return LBF_OK;
+}
+
+void lbf_destroy(lbf_sim* s) {
+  if (!s) return;
+  if (s->stream) (void)hipStreamSynchronize(s->stream);
+  else (void)hipDeviceSynchronize();
+  if (s->owns_ws && s->ws) (void)hipFree(s->ws);
+  if (s->host_red) (void)hipHostFree(s->host_red);
+  if (s->ev0) (void)hipEventDestroy(s->ev0);
+  if (s->ev1) (void)hipEventDestroy(s->ev1);
+  delete s;
+}
+
+int lbf_set_geometry(lbf_sim* s, const float* phi0, const float* cos_theta, int32_t on_device) {
+  if (!s || !phi0 || !cos_theta) return fail(LBF_EINVAL, "NULL argument");
+  const size_t n = (size_t)s->G.nx * s->G.ny;
+  float* stat = fptr(s, s->L.stat);
+  int rc = copy_in(s, stat + ST_PHI0 * s->G.P, phi0, n * sizeof(float), on_device);
+  if (rc) return rc;
+  rc = copy_in(s, stat + ST_CTH * s->G.P, cos_theta, n * sizeof(float), on_device);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_lap_static, node_grid(s), dim3(256), 0, s->stream, s->G, stat);
+  HIP_TRY(hipGetLastError());
+  s->have_geo = true;
+  s->have_init = false;
+  return LBF_OK;
+}
+
+int lbf_set_wall_temperature(lbf_sim* s, int32_t wall, const float* Tw, int32_t n,
+                             int32_t on_device) {
+  if (!s || !Tw) return fail(LBF_EINVAL, "NULL argument");
+  if (wall < 0 || wall > 3) return fail(LBF_EINVAL, "wall %d", wall);
+  const int need = wall < 2 ? s->G.nx : s->G.ny;
+  if (n != need) return fail(LBF_EINVAL, "wall %d needs %d values, got %d", wall, need, n);
+  float* w = fptr(s, s->L.wall) + (size_t)wall * s->L.wstride;
+  return copy_in(s, w, Tw, (size_t)n * sizeof(float), on_device);
+}
+
+int lbf_init_fields(lbf_sim* s, const float* phi, const float* T, int32_t on_device) {
+  if (!s || !phi || !T) return fail(LBF_EINVAL, "NULL argument");
+  if (!s->have_geo) return fail(LBF_ESTATE, "lbf_set_geometry must precede lbf_init_fields");
+  const size_t n = (size_t)s->G.nx * s->G.ny;
+  float* stage = fptr(s, s->L.fields);
+  int rc = copy_in(s, stage, phi, n * sizeof(float), on_device);
+  if (rc) return rc;
+  rc = copy_in(s, stage + s->G.P, T, n * sizeof(float), on_device);
+  if (rc) return rc;
+  s->cur = 0;
+  float* tmp = fptr(s, s->L.dist[1]);
+  hipLaunchKernelGGL(k_init_eq, node_grid(s), dim3(256), 0, s->stream, s->G, s->ph,
+                     (const float*)fptr(s, s->L.stat), (const float*)stage, tmp);
+  HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(k_unstream, node_grid(s), dim3(256), 0, s->stream, s->G, s->ph,
+                     (const float*)tmp, fptr(s, s->L.dist[0]), (const float*)fptr(s, s->L.wall),
+                     s->L.wstride);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemsetAsync(fptr(s, s->L.lag[0]), 0, NLAG * (size_t)s->G.P * sizeof(float),
+                         s->stream));
+  s->step = 0;
+  s->have_budget = false;
+  s->have_init = true;
+  return LBF_OK;
+}
+
+int lbf_step(lbf_sim* s, int32_t nsteps) {
+  if (!s) return fail(LBF_EINVAL, "sim is NULL");
+  if (nsteps < 0) return fail(LBF_EINVAL, "nsteps %d", nsteps);
+  if (!s->have_init) return fail(LBF_ESTATE, "lbf_init_fields must precede lbf_step");
+  if (nsteps == 0) return LBF_OK;
+  if (s->timing) HIP_TRY(hipEventRecord(s->ev0, s->stream));
+  for (int it = 0; it < nsteps; ++it) {
+    const bool last = it == nsteps - 1;
+    int rc = launch_step(s, MODE_STEP, last, last ? dptr(s, s->L.red[0]) : nullptr);
+    if (rc) return rc;
+    s->cur = 1 - s->cur;
+    s->step++;
+  }
+  if (s->timing) {
+    HIP_TRY(hipEventRecord(s->ev1, s->stream));
+    HIP_TRY(hipEventSynchronize(s->ev1));
+    float ms = 0.0f;
+    HIP_TRY(hipEventElapsedTime(&ms, s->ev0, s->ev1));
+    s->last_ms = ms / nsteps;
+  }
+  dim3 grid;
+  s->budget_blocks = grid_blocks(s, grid);
+  s->have_budget = true;
+  return LBF_OK;
+}
+
+int lbf_read_fields(lbf_sim* s, float* dst, int32_t dst_on_device) {
+  if (!s || !dst) return fail(LBF_EINVAL, "NULL argument");
+  if (!s->have_init) return fail(LBF_ESTATE, "not initialised");
+  int rc = launch_step(s, MODE_FIELDS, false, nullptr);
+  if (rc) return rc;
+  const size_t n = (size_t)s->G.nx * s->G.ny;
+  const float* F = fptr(s, s->L.fields);
+  for (int f = 0; f < LBF_NFIELDS; ++f)
+    HIP_TRY(hipMemcpyAsync(dst + f * n, F + f * s->G.P, n * sizeof(float),
+                           dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                           s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  return LBF_OK;
+}
+
+int lbf_read_field(lbf_sim* s, int32_t field_id, float* dst, int32_t dst_on_device) {
+  if (!s || !dst) return fail(LBF_EINVAL, "NULL argument");
+  if (field_id < 0 || field_id >= LBF_NFIELDS) return fail(LBF_EINVAL, "field %d", field_id);
+  if (!s->have_init) return fail(LBF_ESTATE, "not initialised");
+  int rc = launch_step(s, MODE_FIELDS, false, nullptr);
+  if (rc) return rc;
+  const size_t n = (size_t)s->G.nx * s->G.ny;
+  HIP_TRY(hipMemcpyAsync(dst, fptr(s, s->L.fields) + field_id * s->G.P, n * sizeof(float),
+                         dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                         s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  return LBF_OK;
+}
+
+int lbf_reduce(lbf_sim* s, double* out) {
+  if (!s || !out) return fail(LBF_EINVAL, "NULL argument");
+  if (!s->have_init) return fail(LBF_ESTATE, "not initialised");
+  int rc = launch_step(s, MODE_FIELDS, true, dptr(s, s->L.red[1]));
+  if (rc) return rc;
+  dim3 grid;
+  const int nb = grid_blocks(s, grid);
+  double* fin = dptr(s, s->L.redfinal);
+  hipLaunchKernelGGL(k_reduce_blocks, dim3(1), dim3(256), 0, s->stream,
+                     (const double*)dptr(s, s->L.red[1]), nb, fin + NRED);
+  HIP_TRY(hipGetLastError());
+  if (s->have_budget) {
+    hipLaunchKernelGGL(k_reduce_blocks, dim3(1), dim3(256), 0, s->stream,
+                       (const double*)dptr(s, s->L.red[0]), s->budget_blocks, fin);
+    HIP_TRY(hipGetLastError());
+  }
+  HIP_TRY(hipMemcpyAsync(s->host_red, fin, 2 * NRED * sizeof(double), hipMemcpyDeviceToHost,
+                         s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  const double* cur = s->host_red + NRED;
+  const double* bud = s->host_red;
+  for (int j = 0; j < LBF_NRED; ++j) out[j] = cur[j];
+  out[LBF_RED_SRC_PHI] = s->have_budget ? bud[6] : 0.0;
+  out[LBF_RED_SRC_HEAT] = s->have_budget ? bud[7] : 0.0;
+  out[LBF_RED_RESET] = s->have_budget ? bud[9] : 0.0;
+  out[LBF_RED_WALL_FLUX] = s->step > 0 ? cur[8] : 0.0;
+  out[LBF_RED_STEP] = (double)s->step;
+  if (out[LBF_RED_NONFINITE] > 0 || !(out[LBF_RED_UMAX] <= 0.3))
+    return fail(LBF_EUNSTABLE, "unstable: %g non-finite nodes, max |u| = %g",
+                out[LBF_RED_NONFINITE], out[LBF_RED_UMAX]);
+  return LBF_OK;
+}
+
+int lbf_set_tile(lbf_sim* s, int32_t tile_x, int32_t tile_y) {
+  if (!s) return fail(LBF_EINVAL, "sim is NULL");
+  if (tile_x != 64 && tile_x != 128 && tile_x != 256)
+    return fail(LBF_EINVAL, "tile_x must be 64, 128 or 256 (got %d)", tile_x);
+  if (tile_y < 1) return fail(LBF_EINVAL, "tile_y must be >= 1 (got %d)", tile_y);
+  s->tile_x = tile_x;
+  s->tile_y = tile_y;
+  return LBF_OK;
+}
+
+int lbf_get_tile(const lbf_sim* s, int32_t* tile_x, int32_t* tile_y) {
+  if (!s || !tile_x || !tile_y) return fail(LBF_EINVAL, "NULL argument");
+  *tile_x = s->tile_x;
+  *tile_y = s->tile_y;
+  return LBF_OK;
+}
+
+size_t lbf_state_bytes(const lbf_sim* s) {
+  if (!s) return 0;
+  return (size_t)(NDIST + NLAG) * s->G.P * sizeof(float) + 64;
+}
+
+int lbf_save_state(lbf_sim* s, void* dst, size_t cap) {
+  if (!s || !dst) return fail(LBF_EINVAL, "NULL argument");
+  if (!s->have_init) return fail(LBF_ESTATE, "not initialised");
+  const size_t need = lbf_state_bytes(s);
+  if (cap < need) return fail(LBF_ENOMEM, "state needs %zu bytes", need);
+  char* d = (char*)dst;
+  const size_t db = NDIST * (size_t)s->G.P * sizeof(float), lb = NLAG * (size_t)s->G.P * sizeof(float);
+  HIP_TRY(hipMemcpyAsync(d, s->ws + s->L.dist[s->cur], db, hipMemcpyDeviceToDevice, s->stream));
+  HIP_TRY(hipMemcpyAsync(d + db, s->ws + s->L.lag[s->cur], lb, hipMemcpyDeviceToDevice, s->stream));
+  long long hdr[8] = {0x6c626673LL, s->step, s->G.nx, s->G.ny, 0, 0, 0, 0};
+  HIP_TRY(hipMemcpyAsync(d + db + lb, hdr, sizeof hdr, hipMemcpyHostToDevice, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  return LBF_OK;
+}
+
+int lbf_load_state(lbf_sim* s, const void* src, size_t bytes) {
+  if (!s || !src) return fail(LBF_EINVAL, "NULL argument");
+  const size_t need = lbf_state_bytes(s);
+  if (bytes < need) return fail(LBF_EINVAL, "state of %zu bytes, %zu needed", bytes, need);
+  const char* d = (const char*)src;
+  const size_t db = NDIST * (size_t)s->G.P * sizeof(float), lb = NLAG * (size_t)s->G.P * sizeof(float);
+  long long hdr[8];
+  HIP_TRY(hipMemcpyAsync(hdr, d + db + lb, sizeof hdr, hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  if (hdr[0] != 0x6c626673LL || hdr[2] != s->G.nx || hdr[3] != s->G.ny)
+    return fail(LBF_EINVAL, "state buffer does not match this lattice");
+  HIP_TRY(hipMemcpyAsync(s->ws + s->L.dist[s->cur], d, db, hipMemcpyDeviceToDevice, s->stream));
+  HIP_TRY(hipMemcpyAsync(s->ws + s->L.lag[s->cur], d + db, lb, hipMemcpyDeviceToDevice, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  s->step = hdr[1];
+  s->have_init = true;
+  s->have_budget = false;
+  return LBF_OK;
+}
+
+int lbf_set_timing(lbf_sim* s, int32_t on) {
+  if (!s) return fail(LBF_EINVAL, "sim is NULL");
+  s->timing = on != 0;
+  return LBF_OK;
+}
+
+double lbf_last_step_kernel_ms(const lbf_sim* s) { return s ? s->last_ms : 0.0; }
+
+}  // extern "C"

@@ -1,0 +1,372 @@
+// Device-side building blocks of the coupled D2Q9 freezing step (gfx950).
+//
+// Layout in HBM (structure of arrays, FP32, plane stride P floats):
+//   distributions  27 planes: f_0..f_8 (flow), g_0..g_8 (phase), h_0..h_8
+//                  (enthalpy), stored post-collision: a step pulls
+//                  X_i(x) = X_i*(x - c_i) and writes X_i*(x) of the next step
+//                  at the node itself, so every store is row-coalesced and
+//                  aligned and the pull loads are row-coalesced with a
+//                  +-1 element shift;
+//   lagged fields  5 planes: f_s, Q = rho C_p T mdot, (phi u)_x, (phi u)_y, p
+//                  of the previous step;
+//   static fields  3 planes: phi0, cos(theta), lap(phi0).
+// Both distributions and lagged fields are double-buffered (ping-pong).
+// All three populations are deviation-form about the rest state
+// (p = 0, u = 0, phi = 0, mu = 0, T = 0): f^eq vanishes at rest exactly, and
+// g, h carry only the O(1) order parameter and enthalpy.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbf {
+
+constexpr int NDIST = 27;
+constexpr int NLAG = 5;
+constexpr int NSTAT = 3;
+constexpr int NFIELD = 13;
+constexpr int NRED = 11;
+
+enum { LAG_FS = 0, LAG_Q = 1, LAG_JX = 2, LAG_JY = 3, LAG_P = 4 };
+enum { ST_PHI0 = 0, ST_CTH = 1, ST_LAP0 = 2 };
+enum { MODE_STEP = 0, MODE_FIELDS = 1 };
+
+// D2Q9 (Sec. 3.1): c_0 = 0, c_1..4 axis-aligned counter-clockwise from +x,
+// c_5..8 diagonal counter-clockwise from (1,1); weights 4/9, 1/9, 1/36.
+__host__ __device__ constexpr int cx(int i) {
+  return (i == 1 || i == 5 || i == 8) ? 1 : ((i == 3 || i == 6 || i == 7) ? -1 : 0);
+}
+__host__ __device__ constexpr int cy(int i) {
+  return (i == 2 || i == 5 || i == 6) ? 1 : ((i == 4 || i == 7 || i == 8) ? -1 : 0);
+}
+__host__ __device__ constexpr int opp(int i) {
+  return i == 0 ? 0 : (i <= 4 ? ((i + 1) % 4) + 1 : ((i - 3) % 4) + 5);
+}
+__host__ __device__ constexpr float wgt(int i) {
+  return i == 0 ? 4.0f / 9.0f : (i <= 4 ? 1.0f / 9.0f : 1.0f / 36.0f);
+}
+
+// Lattice geometry and boundary types.
+struct Geo {
+  int nx, ny;
+  int px, py;        // periodic flags
+  int tbc[4];        // per wall: 0 adiabatic, 1 Dirichlet (bottom, top, left, right)
+  long long P;       // plane stride in floats
+};
+
+// Physical constants in the form the kernels use them.
+struct Phys {
+  float rho_l, rho_g, rho_s, mu_l, mu_g, mu_s, lam_l, lam_g, lam_s, cp_l, cp_g, cp_s;
+  float latent, T_m, cos_psi, T_sub;
+  float a3;          // 3 sigma / eps
+  float kap;         // 3 eps sigma / 8
+  float tau_g;       // Mbar / c_s^2 + 1/2
+  float Eref;        // rho_ref C_p,ref
+  float three_over_Eref;
+  float mdot_coef;   // 1 - rho_s / rho_l
+  int latch, src_tau_a, subfix;
+};
+
+// Buffers of one lattice.
+struct Bufs {
+  const float* din;   // NDIST planes, post-collision of the previous step
+  float* dout;        // NDIST planes, written by a step
+  const float* lin;   // NLAG planes of the previous step
+  float* lout;        // NLAG planes, written by a step
+  const float* stat;  // NSTAT planes
+  const float* wallT; // 4 profiles, each `wstride` floats
+  int wstride;
+  float* fields;      // NFIELD planes (read-out mode)
+  double* red;        // per-block partial sums, NRED each
+};
+
+__device__ __forceinline__ float clampf(float v, float lo, float hi) {
+  return v < lo ? lo : (v > hi ? hi : v);
+}
+
+// Mixing rule (Sec. 2): zeta = s zeta_s + (1 - s)[C zeta_l + (1 - C) zeta_g].
+__device__ __forceinline__ float zeta(float s, float C, float zs, float zl, float zg) {
+  return s * zs + (1.0f - s) * (C * zl + (1.0f - C) * zg);
+}
+
+// Source node of the pull of population i at (x, y).  Returns the linear
+// node index, or -1 with `wall` set when the link crosses a wall; a link
+// through a bottom/top wall takes that wall even at a corner.
+__device__ __forceinline__ int pull_src(const Geo& G, int x, int y, int i, int& wall) {
+  int sx = x - cx(i), sy = y - cy(i);
+  if (sy < 0 || sy >= G.ny) {
+    if (G.py) {
+      sy = sy < 0 ? sy + G.ny : sy - G.ny;
+    } else {
+      wall = sy < 0 ? 0 : 1;
+      return -1;
+    }
+  }
+  if (sx < 0 || sx >= G.nx) {
+    if (G.px) {
+      sx = sx < 0 ? sx + G.nx : sx - G.nx;
+    } else {
+      wall = sx < 0 ? 2 : 3;
+      return -1;
+    }
+  }
+  return sy * G.nx + sx;
+}
+
+// Node index of a stencil neighbour: periodic wrap or mirror ghost.
+__device__ __forceinline__ int map_axis(int v, int n, int periodic) {
+  if (v < 0) return periodic ? v + n : 0;
+  if (v >= n) return periodic ? v - n : n - 1;
+  return v;
+}
+
+// Pull the phase-field and enthalpy populations of node (x, y), applying
+// bounce-back (g; h on adiabatic walls) and anti-bounce-back with the wall
+// temperature (h on Dirichlet walls).  `flux` gains the energy that the
+// Dirichlet links bring in.
+__device__ __forceinline__ void pull_gh(const Geo& G, const Phys& ph, const Bufs& B, int x,
+                                        int y, float* gv, float* hv, float& flux) {
+  const long long P = G.P;
+  const int k = y * G.nx + x;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    int wall = 0;
+    const int s = pull_src(G, x, y, i, wall);
+    if (s >= 0) {
+      gv[i] = B.din[(9 + i) * P + s];
+      hv[i] = B.din[(18 + i) * P + s];
+    } else {
+      const int j = opp(i);
+      gv[i] = B.din[(9 + j) * P + k];
+      const float hb = B.din[(18 + j) * P + k];
+      if (G.tbc[wall]) {
+        const float Tw = B.wallT[wall * B.wstride + (wall < 2 ? x : y)];
+        hv[i] = -hb + 2.0f * wgt(i) * ph.Eref * Tw;
+        flux += hv[i] - hb;
+      } else {
+        hv[i] = hb;
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ void pull_f(const Geo& G, const Bufs& B, int x, int y, float* fv) {
+  const long long P = G.P;
+  const int k = y * G.nx + x;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    int wall = 0;
+    const int s = pull_src(G, x, y, i, wall);
+    fv[i] = (s >= 0) ? B.din[i * P + s] : B.din[opp(i) * P + k];
+  }
+}
+
+// Node-local moments: liquid weight, phase-change fraction, total enthalpy,
+// enthalpy map, ice fraction, mass source, order parameter and density.
+struct Mom {
+  float C, chi, rhoH, T, fs, fstot, mdot, phi, rho, Ksol, Kliq;
+};
+
+__device__ __forceinline__ void moments(const Phys& ph, float sg, float sh, float fs_prev,
+                                        float Q_prev, float phi0, Mom& m) {
+  const float C = clampf(0.5f * (1.0f - phi0 + sg), 0.0f, 1.0f);
+  float chi = ph.latch ? fmaxf(C, fs_prev) : C;
+  chi = clampf(chi, 0.0f, 1.0f - phi0);
+  // total enthalpy with the lagged source (Sec. 3.3)
+  const float rhoH = sh + 0.5f * Q_prev;
+  // enthalpy map (Sec. 2, Hfl) for a node with phase-change fraction chi
+  const float s_sol = fminf(1.0f, phi0 + chi);
+  const float Kliq = zeta(phi0, C, ph.rho_s, ph.rho_l, ph.rho_g) *
+                     zeta(phi0, C, ph.cp_s, ph.cp_l, ph.cp_g);
+  const float Ksol = zeta(s_sol, C, ph.rho_s, ph.rho_l, ph.rho_g) *
+                     zeta(s_sol, C, ph.cp_s, ph.cp_l, ph.cp_g);
+  const float Es = Ksol * ph.T_m;
+  const float El = Kliq * ph.T_m + chi * ph.rho_l * ph.latent;
+  float T, fl;
+  if (rhoH < Es) {
+    fl = 0.0f;
+    T = rhoH / Ksol;
+  } else if (rhoH <= El) {
+    fl = (El > Es) ? (rhoH - Es) / (El - Es) : 1.0f;
+    T = ph.T_m;
+  } else {
+    fl = 1.0f;
+    T = ph.T_m + (rhoH - El) / Kliq;
+  }
+  const float fs = chi * (1.0f - fl);
+  const float fstot = fminf(1.0f, phi0 + fs);
+  const float mdot = ph.mdot_coef * (fs - fs_prev);   // eq1, backward difference
+  m.C = C;
+  m.chi = chi;
+  m.rhoH = rhoH;
+  m.T = T;
+  m.fs = fs;
+  m.fstot = fstot;
+  m.mdot = mdot;
+  m.phi = sg / (1.0f - 0.5f * mdot);                   // Sec. 3.2 with div u = mdot
+  m.rho = zeta(fstot, C, ph.rho_s, ph.rho_l, ph.rho_g);
+  m.Ksol = Ksol;
+  m.Kliq = Kliq;
+}
+
+// Chemical potential, derivative of the free energy eq44.
+__device__ __forceinline__ float chem_pot(const Phys& ph, float phi, float lap_phi, float phi0,
+                                          float cth, float lap_phi0, float fs, float lap_fs) {
+  const float a = ph.a3, k = ph.kap;
+  float m = a * phi * (phi * phi - 1.0f) - k * lap_phi;
+  m += 3.0f * a * phi0 * phi0 * phi + a * cth * phi0 * (3.0f * phi * phi + phi0 * phi0 - 1.0f) -
+       k * cth * lap_phi0;
+  m += 3.0f * a * fs * fs * phi + a * ph.cos_psi * fs * (3.0f * phi * phi + fs * fs - 1.0f) -
+       k * ph.cos_psi * lap_fs;
+  return m;
+}
+
+// Enthalpy of a node held at temperature Tw: frozen at or below T_m.
+__device__ __forceinline__ float enthalpy_at(const Phys& ph, float Tw, float Ksol, float Kliq,
+                                             float chi) {
+  if (Tw <= ph.T_m) return Ksol * Tw;
+  return Kliq * (Tw - ph.T_m) + Kliq * ph.T_m + chi * ph.rho_l * ph.latent;
+}
+
+// Stencil neighbourhood of one node: values of phi, f_s, rho and the lagged
+// p at the 9 lattice points x + c_i (ghosts already mapped).
+struct Stencil {
+  float phi[9], fs[9], rho[9], p[9];
+};
+
+// Outputs of the per-node collision.
+struct Post {
+  float ux, uy, p, mu, Q, jx, jy;
+  float heat_src, reset;
+};
+
+// Collision of the three populations at one node (Sec. 3.1-3.3), in place
+// on fv, gv, hv.  When `collide` is false only the diagnostics are filled.
+template <bool COLLIDE>
+__device__ __forceinline__ void collide_node(const Phys& ph, const Mom& m, const Stencil& S,
+                                             float phi0, float cth, float lap_phi0, float Q_prev,
+                                             float jx_prev, float jy_prev, float* fv, float* gv,
+                                             float* hv, Post& o) {
+  // isotropic stencils (factor 1/c_s^2 = 3 for the gradient, 2/c_s^2 = 6 for
+  // the Laplacian)
+  float gphx = 0, gphy = 0, lphi = 0, lfs = 0, grx = 0, gry = 0, gpx = 0, gpy = 0;
+#pragma unroll
+  for (int i = 1; i < 9; ++i) {
+    const float w = wgt(i);
+    gphx += w * cx(i) * S.phi[i];
+    gphy += w * cy(i) * S.phi[i];
+    lphi += w * (S.phi[i] - S.phi[0]);
+    lfs += w * (S.fs[i] - S.fs[0]);
+    grx += w * cx(i) * S.rho[i];
+    gry += w * cy(i) * S.rho[i];
+    gpx += w * cx(i) * S.p[i];
+    gpy += w * cy(i) * S.p[i];
+  }
+  gphx *= 3.0f; gphy *= 3.0f; lphi *= 6.0f; lfs *= 6.0f;
+  grx *= 3.0f; gry *= 3.0f; gpx *= 3.0f; gpy *= 3.0f;
+
+  const float phi = m.phi, rho = m.rho, C = m.C, fstot = m.fstot, mdot = m.mdot, T = m.T;
+  const float mu_v = zeta(fstot, C, ph.mu_s, ph.mu_l, ph.mu_g);
+  const float lam = zeta(fstot, C, ph.lam_s, ph.lam_l, ph.lam_g);
+  const float cp = zeta(fstot, C, ph.cp_s, ph.cp_l, ph.cp_g);
+  const float inv_rho = 1.0f / rho;
+  const float tau_f = 3.0f * mu_v * inv_rho + 0.5f;
+  const float tau_a = lam * ph.three_over_Eref + 0.5f;
+  const float inv_tau_a = 1.0f / tau_a;
+  const float inv_tau_s = 2.0f - inv_tau_a;           // 1/tau_s + 1/tau_a = 2
+
+  const float mu = chem_pot(ph, phi, lphi, phi0, cth, lap_phi0, m.fs, lfs);
+  const float Fx = mu * gphx, Fy = mu * gphy;         // F_s = mu grad phi, G = 0
+  float mx = 0, my = 0, sum_nz = 0;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    mx += cx(i) * fv[i];
+    my += cy(i) * fv[i];
+    if (i) sum_nz += fv[i];
+  }
+  const float usx = (mx + 0.5f * Fx) * inv_rho, usy = (my + 0.5f * Fy) * inv_rho;
+  const float fdx = -fstot * usx, fdy = -fstot * usy; // drag, u_s = 0
+  const float ux = usx + 0.5f * fdx, uy = usy + 0.5f * fdy;
+  const float Sm = rho * mdot + ux * grx + uy * gry;
+  const float Ftx = Fx - gpx + (1.0f / 3.0f) * grx, Fty = Fy - gpy + (1.0f / 3.0f) * gry;
+  const float uu = ux * ux + uy * uy;
+  const float uFt = ux * Ftx + uy * Fty;
+  const float F0 = wgt(0) * (Sm - 3.0f * uFt);
+  const float p = (1.0f / 3.0f) / (1.0f - wgt(0)) *
+                  (sum_nz + 0.5f * Sm + (tau_f - 0.5f) * F0 - 1.5f * wgt(0) * rho * uu);
+  o.ux = ux; o.uy = uy; o.p = p; o.mu = mu;
+  const float jx = phi * ux, jy = phi * uy;
+  o.jx = jx; o.jy = jy;
+  const float rhocp = rho * cp;
+  const float Q = rhocp * T * mdot;
+  o.Q = Q;
+  o.heat_src = 0.0f;
+  o.reset = 0.0f;
+  if (!COLLIDE) return;
+
+  // flow: pressure-based equilibrium and forcing (Sec. 3.1)
+  const float inv_tau_f = 1.0f / tau_f;
+  const float pf = 1.0f - 0.5f * inv_tau_f;
+  const float rfx = rho * fdx + Fx, rfy = rho * fdy + Fy;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const float cu = cx(i) * ux + cy(i) * uy;
+    const float cF = cx(i) * rfx + cy(i) * rfy;
+    const float cFt = cx(i) * Ftx + cy(i) * Fty;
+    const float feq = 3.0f * p * (wgt(i) - (i == 0 ? 1.0f : 0.0f)) +
+                      rho * wgt(i) * (3.0f * cu + 4.5f * cu * cu - 1.5f * uu);
+    const float Fi = wgt(i) * (Sm + 3.0f * cF + 9.0f * cu * cFt - 3.0f * uFt);
+    fv[i] = fv[i] - (fv[i] - feq) * inv_tau_f + pf * Fi;
+  }
+  // phase field (Sec. 3.2)
+  const float inv_tau_g = 1.0f / ph.tau_g;
+  const float pg = 1.0f - 0.5f * inv_tau_g;
+  const float djx = jx - jx_prev, djy = jy - jy_prev;
+  const float pm = phi * mdot;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const float cj = cx(i) * jx + cy(i) * jy;
+    const float geq = (i == 0 ? phi : 0.0f) + (wgt(i) - (i == 0 ? 1.0f : 0.0f)) * mu +
+                      3.0f * wgt(i) * cj;
+    const float Gi = wgt(i) * (3.0f * (cx(i) * djx + cy(i) * djy) + pm);
+    gv[i] = gv[i] - (gv[i] - geq) * inv_tau_g + pg * Gi;
+  }
+  // enthalpy, TRT (Sec. 3.3, eq22)
+  const float ET = ph.Eref * T;
+  const float cT = rhocp * T;
+  float heq[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const float cu = cx(i) * ux + cy(i) * uy;
+    heq[i] = (i == 0) ? m.rhoH - ET + wgt(0) * (ET - 1.5f * cT * uu)
+                      : wgt(i) * (ET + cT * (3.0f * cu + 4.5f * cu * cu - 1.5f * uu));
+  }
+  const float ps = ph.src_tau_a ? (1.0f - 0.5f * inv_tau_a) : (1.0f - 0.5f * inv_tau_s);
+  float hn[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const int j = opp(i);
+    const float ha = 0.5f * (hv[i] - hv[j]), hs = 0.5f * (hv[i] + hv[j]);
+    const float ea = 0.5f * (heq[i] - heq[j]), es = 0.5f * (heq[i] + heq[j]);
+    hn[i] = hv[i] - (ha - ea) * inv_tau_a - (hs - es) * inv_tau_s + ps * wgt(i) * Q;
+  }
+  o.heat_src = 0.5f * Q_prev * inv_tau_s + ps * Q;
+  if (ph.subfix && phi0 >= 0.5f) {
+    // isothermal solid region: reset to the equilibrium at the held temperature
+    const float Tw = ph.T_sub;
+    const float rH = enthalpy_at(ph, Tw, m.Ksol, m.Kliq, m.chi);
+    const float EW = ph.Eref * Tw;
+    float before = 0.0f, after = 0.0f;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      before += hn[i];
+      const float e = (i == 0) ? rH - EW + wgt(0) * EW : wgt(i) * EW;
+      after += e;
+      hn[i] = e;
+    }
+    o.reset = after - before;
+  }
+#pragma unroll
+  for (int i = 0; i < 9; ++i) hv[i] = hn[i];
+}
+
+}  // namespace lbf

@@ -1,0 +1,241 @@
+"""Python binding of liblbf (argument marshalling only).
+
+Every step of the coupled update runs in the HIP kernels of liblbf.so; this
+module converts arrays and tensors to pointers and sizes and raises on error
+codes.  PyTorch provides device memory (the simulation workspace) and the
+HIP stream.  There is no CPU fallback: without the built library, or
+without a HIP device, every entry point raises.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Dict, Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblbf.so")
+
+FIELDS = ["phi", "T", "fl", "fs", "ux", "uy", "p", "rhoH", "mu", "C", "chi", "rho", "phihat"]
+REDS = ["sum_g", "sum_h", "sum_fs", "sum_liq", "umax", "nonfinite", "src_phi", "src_heat",
+        "wall_flux", "reset", "step"]
+EXPORTS = ["lbf_workspace_bytes", "lbf_create", "lbf_set_geometry", "lbf_set_wall_temperature",
+           "lbf_init_fields", "lbf_step", "lbf_read_field", "lbf_read_fields", "lbf_reduce",
+           "lbf_set_tile", "lbf_get_tile", "lbf_state_bytes", "lbf_save_state",
+           "lbf_load_state", "lbf_set_timing", "lbf_last_step_kernel_ms", "lbf_last_error",
+           "lbf_destroy"]
+
+ERRORS = {-1: "LBF_EINVAL", -2: "LBF_EHIP", -3: "LBF_ESTATE", -4: "LBF_EUNSTABLE",
+          -5: "LBF_ENOMEM"}
+
+
+class LbfError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Params(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("periodic_x", C.c_int32),
+                ("periodic_y", C.c_int32), ("thermal_bc", C.c_int32 * 4),
+                ("latch_fs", C.c_int32), ("h_src_tau_a", C.c_int32),
+                ("substrate_fixed", C.c_int32), ("reserved", C.c_int32)] + [
+        (k, C.c_double) for k in (
+            "rho_l", "rho_g", "rho_s", "mu_l", "mu_g", "mu_s", "lam_l", "lam_g", "lam_s",
+            "cp_l", "cp_g", "cp_s", "latent", "T_m", "sigma", "eps", "mobility", "cos_psi",
+            "rho_ref", "T_substrate")]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load liblbf.so and declare its signatures (no GPU needed)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"liblbf.so not built ({path}); run python -m paper_2510_18688_amd.build")
+    L = C.CDLL(path)
+    vp, i32, f_p, d_p = C.c_void_p, C.c_int32, C.POINTER(C.c_float), C.POINTER(C.c_double)
+    L.lbf_workspace_bytes.restype = C.c_size_t
+    L.lbf_workspace_bytes.argtypes = [i32, i32]
+    L.lbf_create.argtypes = [C.POINTER(Params), vp, vp, C.c_size_t, C.POINTER(vp)]
+    L.lbf_set_geometry.argtypes = [vp, vp, vp, i32]
+    L.lbf_set_wall_temperature.argtypes = [vp, i32, vp, i32, i32]
+    L.lbf_init_fields.argtypes = [vp, vp, vp, i32]
+    L.lbf_step.argtypes = [vp, i32]
+    L.lbf_read_field.argtypes = [vp, i32, vp, i32]
+    L.lbf_read_fields.argtypes = [vp, vp, i32]
+    L.lbf_reduce.argtypes = [vp, d_p]
+    L.lbf_set_tile.argtypes = [vp, i32, i32]
+    L.lbf_get_tile.argtypes = [vp, C.POINTER(i32), C.POINTER(i32)]
+    L.lbf_state_bytes.restype = C.c_size_t
+    L.lbf_state_bytes.argtypes = [vp]
+    L.lbf_save_state.argtypes = [vp, vp, C.c_size_t]
+    L.lbf_load_state.argtypes = [vp, vp, C.c_size_t]
+    L.lbf_set_timing.argtypes = [vp, i32]
+    L.lbf_last_step_kernel_ms.restype = C.c_double
+    L.lbf_last_step_kernel_ms.argtypes = [vp]
+    L.lbf_last_error.restype = C.c_char_p
+    L.lbf_destroy.argtypes = [vp]
+    for name in EXPORTS:
+        getattr(L, name)
+    _lib = L
+    return L
+
+
+def check(rc: int) -> None:
+    if rc != 0:
+        raise LbfError(rc, _lib.lbf_last_error().decode())
+
+
+def make_params(case) -> Params:
+    p = Params()
+    p.nx, p.ny = case.nx, case.ny
+    p.periodic_x, p.periodic_y = int(case.periodic_x), int(case.periodic_y)
+    for w in range(4):
+        p.thermal_bc[w] = int(case.thermal_bc[w])
+    m = case.mat
+    p.latch_fs, p.h_src_tau_a = int(m.latch_fs), int(m.h_src_tau_a)
+    p.substrate_fixed = int(case.substrate_fixed)
+    for k in ("rho_l", "rho_g", "rho_s", "mu_l", "mu_g", "mu_s", "lam_l", "lam_g", "lam_s",
+              "cp_l", "cp_g", "cp_s", "latent", "T_m", "sigma", "eps", "mobility", "cos_psi",
+              "rho_ref"):
+        setattr(p, k, float(getattr(m, k)))
+    p.T_substrate = float(case.T_substrate)
+    return p
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("liblbf needs a HIP device; none is visible")
+    return torch
+
+
+def _f32_host(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+class Sim:
+    """One lattice on the current HIP device; workspace owned by a torch tensor."""
+
+    def __init__(self, case, tile: Optional[Sequence[int]] = None, device: str = "cuda",
+                 stream=None):
+        torch = _torch()
+        L = load()
+        self.case = case
+        self.nx, self.ny = case.nx, case.ny
+        self.params = make_params(case)
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        nbytes = L.lbf_workspace_bytes(self.nx, self.ny)
+        if nbytes == 0:
+            raise LbfError(-1, "bad lattice size")
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        h = C.c_void_p()
+        check(L.lbf_create(C.byref(self.params), C.c_void_p(self.stream.cuda_stream),
+                           C.c_void_p(self.workspace.data_ptr()), nbytes, C.byref(h)))
+        self.h = h
+        if tile is not None:
+            self.set_tile(*tile)
+        self.set_geometry(case.phi0, case.cos_theta)
+        for w in range(4):
+            self.set_wall_temperature(w, case.wall_profile(w))
+        self.init_fields(case.phi, case.T)
+
+    def close(self) -> None:
+        if getattr(self, "h", None) is not None and self.h.value:
+            _lib.lbf_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- marshalling helpers
+    def _ptr_in(self, a):
+        """(pointer, on_device, keep-alive) for a host array or a device tensor."""
+        try:
+            import torch
+            if isinstance(a, torch.Tensor):
+                if a.device.type != "cuda" or a.dtype != torch.float32 or not a.is_contiguous():
+                    raise LbfError(-1, "tensor inputs must be contiguous float32 on the device")
+                return C.c_void_p(a.data_ptr()), 1, a
+        except ImportError:
+            pass
+        arr = _f32_host(a)
+        return C.c_void_p(arr.ctypes.data), 0, arr
+
+    def set_geometry(self, phi0, cos_theta) -> None:
+        a, d, k1 = self._ptr_in(phi0)
+        b, d2, k2 = self._ptr_in(cos_theta)
+        if d != d2:
+            raise LbfError(-1, "phi0 and cos_theta must both be host or both device")
+        check(_lib.lbf_set_geometry(self.h, a, b, d))
+
+    def set_wall_temperature(self, wall: int, Tw) -> None:
+        a, d, k = self._ptr_in(Tw)
+        n = self.nx if wall in (0, 1) else self.ny
+        check(_lib.lbf_set_wall_temperature(self.h, wall, a, n, d))
+
+    def init_fields(self, phi, T) -> None:
+        a, d, k1 = self._ptr_in(phi)
+        b, d2, k2 = self._ptr_in(T)
+        if d != d2:
+            raise LbfError(-1, "phi and T must both be host or both device")
+        check(_lib.lbf_init_fields(self.h, a, b, d))
+
+    def set_tile(self, tx: int, ty: int) -> None:
+        check(_lib.lbf_set_tile(self.h, int(tx), int(ty)))
+
+    def tile(self):
+        a, b = C.c_int32(), C.c_int32()
+        check(_lib.lbf_get_tile(self.h, C.byref(a), C.byref(b)))
+        return a.value, b.value
+
+    def step(self, n: int = 1) -> None:
+        check(_lib.lbf_step(self.h, int(n)))
+
+    def set_timing(self, on: bool) -> None:
+        check(_lib.lbf_set_timing(self.h, int(bool(on))))
+
+    def last_step_kernel_ms(self) -> float:
+        return float(_lib.lbf_last_step_kernel_ms(self.h))
+
+    def fields(self) -> Dict[str, np.ndarray]:
+        n = self.nx * self.ny
+        out = np.empty(len(FIELDS) * n, dtype=np.float32)
+        check(_lib.lbf_read_fields(self.h, C.c_void_p(out.ctypes.data), 0))
+        return {k: out[i * n:(i + 1) * n].reshape(self.ny, self.nx) for i, k in enumerate(FIELDS)}
+
+    def field(self, name: str, out=None):
+        """One read-out field into a new host array, or into a device tensor `out`."""
+        fid = FIELDS.index(name)
+        if out is not None:
+            check(_lib.lbf_read_field(self.h, fid, C.c_void_p(out.data_ptr()), 1))
+            return out
+        arr = np.empty((self.ny, self.nx), dtype=np.float32)
+        check(_lib.lbf_read_field(self.h, fid, C.c_void_p(arr.ctypes.data), 0))
+        return arr
+
+    def reduce(self, check_stable: bool = True) -> Dict[str, float]:
+        out = (C.c_double * len(REDS))()
+        rc = _lib.lbf_reduce(self.h, out)
+        if rc != 0 and (check_stable or rc != -4):
+            check(rc)
+        return dict(zip(REDS, list(out)))
+
+    def state_bytes(self) -> int:
+        return int(_lib.lbf_state_bytes(self.h))
+
+    def save_state(self, buf) -> None:
+        check(_lib.lbf_save_state(self.h, C.c_void_p(buf.data_ptr()), buf.numel() * buf.element_size()))
+
+    def load_state(self, buf) -> None:
+        check(_lib.lbf_load_state(self.h, C.c_void_p(buf.data_ptr()), buf.numel() * buf.element_size()))

@@ -1,0 +1,100 @@
+"""Host-side checks of the C ABI (no GPU): the library loads, exports every
+entry point that include/lbf.h declares, its parameter struct matches the
+binding's, and parameter validation rejects bad sets before touching a
+device."""
+
+import ctypes as C
+import os
+import re
+import subprocess
+import tempfile
+
+import pytest
+
+from paper_2510_18688_amd import lbf, workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lbf.h")
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2510_18688_amd import build
+    if build.stale():
+        build.build(verbose=False)
+    return lbf.load()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbf_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol(L):
+    names = declared_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(lbf.EXPORTS) <= set(names)
+
+
+def test_params_layout_matches_header(tmp_path):
+    src = tmp_path / "sz.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "lbf.h"\n'
+                   'int main(void){printf("%zu %zu %zu %zu\\n", sizeof(lbf_params),'
+                   ' offsetof(lbf_params, rho_l), offsetof(lbf_params, T_substrate),'
+                   ' offsetof(lbf_params, thermal_bc));return 0;}\n')
+    exe = tmp_path / "sz"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()
+    P = lbf.Params
+    assert int(out[0]) == C.sizeof(P)
+    assert int(out[1]) == P.rho_l.offset
+    assert int(out[2]) == P.T_substrate.offset
+    assert int(out[3]) == P.thermal_bc.offset
+
+
+def test_workspace_bytes(L):
+    assert L.lbf_workspace_bytes(0, 5) == 0
+    small = L.lbf_workspace_bytes(64, 48)
+    big = L.lbf_workspace_bytes(2048, 2048)
+    assert small > 64 * 48 * 4 * (27 * 2 + 5 * 2 + 3)
+    # 67 resident state planes + 13 read-out planes + reduction scratch
+    assert 2048 * 2048 * 4 * 80 <= big <= 2048 * 2048 * 4 * 84
+
+
+def _create_rc(L, case):
+    p = lbf.make_params(case)
+    h = C.c_void_p()
+    rc = L.lbf_create(C.byref(p), None, None, 0, C.byref(h))
+    return rc, L.lbf_last_error().decode()
+
+
+@pytest.mark.parametrize("mutate,needle", [
+    (lambda c: setattr(c, "nx", 0), "lattice size"),
+    (lambda c: setattr(c.mat, "rho_ref", 1.0), "unstable"),
+    (lambda c: setattr(c.mat, "mu_g", 0.0), "positive"),
+    (lambda c: setattr(c.mat, "eps", -4.0), "positive"),
+    (lambda c: setattr(c, "thermal_bc", [2, 0, 0, 0]), "thermal_bc"),
+])
+def test_invalid_params_rejected_on_host(L, mutate, needle):
+    case = W.sessile_drop(nx=16, ny=8)
+    mutate(case)
+    rc, msg = _create_rc(L, case)
+    assert rc == -1 and needle in msg
+
+
+def test_null_arguments(L):
+    assert L.lbf_step(None, 1) == -1
+    assert L.lbf_reduce(None, None) == -1
+    assert L.lbf_read_field(None, 0, None, 0) == -1
+    L.lbf_destroy(None)
+
+
+def test_binding_refuses_without_device(monkeypatch):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a device is present")
+    with pytest.raises(RuntimeError, match="HIP device"):
+        lbf.Sim(W.sessile_drop(nx=16, ny=8))
