@@ -22,9 +22,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # Algorithmic HBM bytes per lattice-node update of the step kernel: 27
-# distributions and 5 lagged fields read and written (FP32), 3 static planes
-# read.
-BYTES_PER_LU = (27 + 5) * 2 * 4 + 3 * 4
+# distributions and 7 lagged planes read and written (FP32: f_s, Q, phi u,
+# p and the high parts of g_0, h_0), 3 static planes read (phi0, cos theta,
+# lap phi0).
+BYTES_PER_LU = (27 + 7) * 2 * 4 + 3 * 4
 HBM_PEAK_GBS = 8000.0
 
 

@@ -100,6 +100,9 @@ typedef struct lbf_params {
   double cos_psi;              /* cosine of the water-ice contact angle */
   double rho_ref;              /* reference density of the enthalpy LB */
   double T_substrate;          /* temperature of held solid nodes */
+  double pcm_floor;            /* liquid weight below which a node holds no phase-change
+                                  material, in [0, 1) (0.01 keeps gas fluctuations from
+                                  freezing) */
 } lbf_params;
 
 typedef struct lbf_sim lbf_sim;
@@ -134,6 +137,15 @@ int lbf_set_wall_temperature(lbf_sim* sim, int32_t wall, const float* Tw, int32_
  * each): u = 0, p = 0, phase-field and enthalpy distributions at
  * equilibrium, the phase-change material liquid.  Requires the geometry. */
 int lbf_init_fields(lbf_sim* sim, const float* phi, const float* T, int32_t on_device);
+
+/* Replace the state by an externally given one at time level `step`: the
+ * post-streaming distributions (27 planes of nx * ny floats: f_0..f_8,
+ * g_0..g_8, h_0..h_8, the populations each node holds at the start of a
+ * step) and the lagged fields of the previous step (5 planes: f_s,
+ * rho C_p T mdot, (phi u)_x, (phi u)_y, p).  Geometry and wall temperatures
+ * must be set; they define the wall links that the state is mapped through. */
+int lbf_set_poststream_state(lbf_sim* sim, const float* dist, const float* lag, int64_t step,
+                             int32_t on_device);
 
 /* Advance nsteps coupled time steps (nsteps >= 0).  Asynchronous on the
  * simulation's stream. */

@@ -51,6 +51,7 @@ typedef struct {
   double rho_l, rho_g, rho_s, mu_l, mu_g, mu_s, lam_l, lam_g, lam_s;
   double cp_l, cp_g, cp_s;
   double latent, T_m, sigma, eps, mobility, cos_psi, rho_ref, T_substrate;
+  double pcm_floor;           /* R45 */
 } orc_params;
 
 enum { WB = 0, WT = 1, WL = 2, WR = 3 };
@@ -71,6 +72,7 @@ typedef struct {
   double *ux, *uy, *pr, *mu;
   double budget[4];             /* sum phi*mdot, heat source, wall flux, reset */
   long step;
+  int store_f32;                /* conditioning probe: round the state to binary32 each step */
 } orc_sim;
 
 /* --------------------------------------------------------- small helpers */
@@ -316,8 +318,10 @@ static void pass1(orc_sim* s) {
       double phi0 = s->phi0[k];
       /* liquid weight of the mixing rule (Sec. 2) from the raw zeroth moment */
       double C = clampd(0.5 * (1.0 - phi0 + sg), 0.0, 1.0);
-      /* R1, R3: phase-change fraction, latched by the previous ice fraction */
-      double chi = p->latch_fs ? fmax(C, s->fs_prev[k]) : C;
+      /* R1, R3, R45: phase-change fraction from the liquid weight above a
+       * small floor, latched by the previous ice fraction */
+      double Cp = clampd((C - p->pcm_floor) / (1.0 - p->pcm_floor), 0.0, 1.0);
+      double chi = p->latch_fs ? fmax(Cp, s->fs_prev[k]) : Cp;
       chi = clampd(chi, 0.0, 1.0 - phi0);
       /* total enthalpy (Sec. 3.3) with the source lagged one step (R14) */
       double rhoH = sh + 0.5 * s->Q_prev[k];
@@ -528,12 +532,28 @@ static void swap_lagged(orc_sim* s) {
   t = s->p_prev; s->p_prev = s->p_new; s->p_new = t;
 }
 
+/* Conditioning probe (off by default): with store_f32 set, the state is
+ * rounded to IEEE binary32 after every step while all arithmetic stays in
+ * binary64.  The divergence from the unrounded run measures how much any
+ * binary32-storage implementation must differ from this oracle. */
+static void round_state_f32(orc_sim* s) {
+  double* arrs[] = {s->f, s->g, s->h};
+  for (int a = 0; a < 3; ++a)
+    for (size_t k = 0; k < 9 * s->n; ++k) arrs[a][k] = (double)(float)arrs[a][k];
+  double* lag[] = {s->fs_prev, s->Q_prev, s->phiux_prev, s->phiuy_prev, s->p_prev};
+  for (int a = 0; a < 5; ++a)
+    for (size_t k = 0; k < s->n; ++k) lag[a][k] = (double)(float)lag[a][k];
+}
+
+void orc_set_store_f32(orc_sim* s, int on) { s->store_f32 = on; }
+
 void orc_step(orc_sim* s, int nsteps) {
   for (int it = 0; it < nsteps; ++it) {
     pass1(s);
     pass2(s, 1);
     stream(s);
     swap_lagged(s);
+    if (s->store_f32) round_state_f32(s);
     s->step++;
   }
 }
@@ -582,7 +602,8 @@ int orc_init(orc_sim* s, const double* phi0, const double* cth, const double* ph
       double geq[9], heq[9];
       orc_geq(phi[k], mu, 0.0, 0.0, geq);
       double C = clampd(0.5 * (1.0 - phi0[k] + phi[k]), 0.0, 1.0);
-      double chi = clampd(C, 0.0, 1.0 - phi0[k]);
+      double Cp = clampd((C - p->pcm_floor) / (1.0 - p->pcm_floor), 0.0, 1.0);
+      double chi = clampd(Cp, 0.0, 1.0 - phi0[k]);
       double Kliq = zeta(phi0[k], C, p->rho_s, p->rho_l, p->rho_g) *
                     zeta(phi0[k], C, p->cp_s, p->cp_l, p->cp_g);
       double rhoH = Kliq * (T0[k] - p->T_m) + Kliq * p->T_m + chi * p->rho_l * p->latent;

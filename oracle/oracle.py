@@ -32,7 +32,7 @@ class OrcParams(C.Structure):
         (k, C.c_double) for k in (
             "rho_l", "rho_g", "rho_s", "mu_l", "mu_g", "mu_s", "lam_l", "lam_g", "lam_s",
             "cp_l", "cp_g", "cp_s", "latent", "T_m", "sigma", "eps", "mobility",
-            "cos_psi", "rho_ref", "T_substrate")]
+            "cos_psi", "rho_ref", "T_substrate", "pcm_floor")]
 
 
 def build(force: bool = False) -> str:
@@ -74,6 +74,7 @@ def lib():
         L.orc_stencil.argtypes = [C.c_int] * 4 + [dp, dp, dp, dp]
         L.orc_set_threads.argtypes = [C.c_int]
         L.orc_max_threads.restype = C.c_int
+        L.orc_set_store_f32.argtypes = [C.c_void_p, C.c_int]
         L.orc_step_count.restype = C.c_long
         L.orc_step_count.argtypes = [C.c_void_p]
         _lib = L
@@ -100,7 +101,7 @@ def make_params(case) -> OrcParams:
     p.substrate_fixed = int(case.substrate_fixed)
     for k in ("rho_l", "rho_g", "rho_s", "mu_l", "mu_g", "mu_s", "lam_l", "lam_g",
               "lam_s", "cp_l", "cp_g", "cp_s", "latent", "T_m", "sigma", "eps",
-              "mobility", "cos_psi", "rho_ref"):
+              "mobility", "cos_psi", "rho_ref", "pcm_floor"):
         setattr(p, k, float(getattr(m, k)))
     p.T_substrate = float(case.T_substrate)
     return p
@@ -131,6 +132,10 @@ class Oracle:
 
     def step(self, n: int = 1) -> None:
         lib().orc_step(self.h, int(n))
+
+    def set_store_f32(self, on: bool) -> None:
+        """Conditioning probe: round the state to binary32 after every step."""
+        lib().orc_set_store_f32(self.h, int(bool(on)))
 
     def set_wall_T(self, wall: int, prof) -> None:
         lib().orc_set_wall_T(self.h, wall, _ptr(_f64(prof)))

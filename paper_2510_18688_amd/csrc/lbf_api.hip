@@ -43,6 +43,10 @@ size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 // Plane stride: nx * ny rounded up to 64 floats (256 bytes).
 long long plane_stride(int nx, int ny) { return (long long)round_up((size_t)nx * ny, 64); }
 
+// Kernels address each block of planes with 32-bit byte offsets: the 27
+// distribution planes must span less than 4 GiB.
+constexpr long long kMaxPlane = (0xFFFFFFFFLL / (4LL * 27)) / 64 * 64;
+
 // Worst-case number of per-block partial sums: 64-wide strips, 1 row each.
 size_t max_blocks(int nx, int ny) { return ((size_t)(nx + 63) / 64) * (size_t)ny; }
 
@@ -103,8 +107,8 @@ namespace {
 float* fptr(lbf_sim* s, size_t off) { return reinterpret_cast<float*>(s->ws + off); }
 double* dptr(lbf_sim* s, size_t off) { return reinterpret_cast<double*>(s->ws + off); }
 
-Bufs make_bufs(lbf_sim* s) {
-  Bufs B{};
+BufArgs make_args(lbf_sim* s) {
+  BufArgs B{};
   B.din = fptr(s, s->L.dist[s->cur]);
   B.dout = fptr(s, s->L.dist[1 - s->cur]);
   B.lin = fptr(s, s->L.lag[s->cur]);
@@ -120,8 +124,9 @@ Bufs make_bufs(lbf_sim* s) {
 int validate(const lbf_params* p) {
   if (!p) return fail(LBF_EINVAL, "params is NULL");
   if (p->nx < 1 || p->ny < 1) return fail(LBF_EINVAL, "lattice size %d x %d", p->nx, p->ny);
-  if ((long long)p->nx * p->ny > (1LL << 31) - 64)
-    return fail(LBF_EINVAL, "lattice of %d x %d nodes exceeds 2^31", p->nx, p->ny);
+  if (plane_stride(p->nx, p->ny) > kMaxPlane)
+    return fail(LBF_EINVAL, "lattice of %d x %d nodes exceeds the %lld-node limit", p->nx, p->ny,
+                kMaxPlane);
   const double pos[] = {p->rho_l, p->rho_g, p->rho_s, p->mu_l, p->mu_g, p->mu_s, p->lam_l,
                         p->lam_g, p->lam_s, p->cp_l, p->cp_g, p->cp_s, p->eps, p->mobility,
                         p->rho_ref};
@@ -129,6 +134,8 @@ int validate(const lbf_params* p) {
     if (!(v > 0.0) || !std::isfinite(v))
       return fail(LBF_EINVAL, "densities, viscosities, conductivities, heat capacities, eps, "
                               "mobility and rho_ref must be positive and finite");
+  if (!(p->pcm_floor >= 0.0 && p->pcm_floor < 1.0))
+    return fail(LBF_EINVAL, "pcm_floor must be in [0, 1) (got %g)", p->pcm_floor);
   if (!(p->latent >= 0.0) || !(p->sigma >= 0.0))
     return fail(LBF_EINVAL, "latent heat and surface tension must be non-negative");
   for (int w = 0; w < 4; ++w)
@@ -157,10 +164,14 @@ void fill_phys(const lbf_params* p, Phys& ph) {
   ph.a3 = (float)(3.0 * p->sigma / p->eps);
   ph.kap = (float)(3.0 * p->eps * p->sigma / 8.0);
   ph.tau_g = (float)(3.0 * p->mobility + 0.5);
+  ph.inv_tau_g = (float)(1.0 / (3.0 * p->mobility + 0.5));
+  ph.pg = (float)(1.0 - 0.5 / (3.0 * p->mobility + 0.5));
   const double Eref = p->rho_ref * 2.0 * p->cp_s * p->cp_l / (p->cp_s + p->cp_l);
   ph.Eref = (float)Eref;
   ph.three_over_Eref = (float)(3.0 / Eref);
   ph.mdot_coef = (float)(1.0 - p->rho_s / p->rho_l);
+  ph.pcm_floor = (float)p->pcm_floor;
+  ph.inv_pcm_span = (float)(1.0 / (1.0 - p->pcm_floor));
   ph.latch = p->latch_fs ? 1 : 0;
   ph.src_tau_a = p->h_src_tau_a ? 1 : 0;
   ph.subfix = p->substrate_fixed ? 1 : 0;
@@ -202,7 +213,8 @@ __global__ void k_init_eq(Geo G, Phys ph, const float* stat, const float* in, fl
   const float mu = chem_pot(ph, pc, lap, phi0, stat[ST_CTH * P + k], stat[ST_LAP0 * P + k], 0.0f,
                             0.0f);
   const float C = clampf(0.5f * (1.0f - phi0 + pc), 0.0f, 1.0f);
-  const float chi = clampf(C, 0.0f, 1.0f - phi0);
+  const float Cp = clampf((C - ph.pcm_floor) * ph.inv_pcm_span, 0.0f, 1.0f);
+  const float chi = clampf(Cp, 0.0f, 1.0f - phi0);
   const float Kliq = zeta(phi0, C, ph.rho_s, ph.rho_l, ph.rho_g) *
                      zeta(phi0, C, ph.cp_s, ph.cp_l, ph.cp_g);
   const float Tk = T0[k];
@@ -217,14 +229,21 @@ __global__ void k_init_eq(Geo G, Phys ph, const float* stat, const float* in, fl
 }
 
 // Inverse of the pull: post-collision populations whose pull gives `tmp`.
-__global__ void k_unstream(Geo G, Phys ph, const float* tmp, float* dst, const float* wallT,
-                           int wstride) {
+// The rest populations g_0, h_0 (which do not move) become the high parts
+// (lagged planes) of their float-float storage, with zero low parts.
+__global__ void k_unstream(Geo G, Phys ph, const float* tmp, float* dst, float* stat, float* lag,
+                           const float* wallT, int wstride) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
   if (x >= G.nx || y >= G.ny) return;
   const long long P = G.P;
   const int k = y * G.nx + x;
+  dst[k] = tmp[k];
+  lag[LAG_GHI * P + k] = tmp[9 * P + k];
+  lag[LAG_HHI * P + k] = tmp[18 * P + k];
+  dst[9 * P + k] = 0.0f;
+  dst[18 * P + k] = 0.0f;
 #pragma unroll
-  for (int j = 0; j < 9; ++j) {
+  for (int j = 1; j < 9; ++j) {
     // destination of population j leaving (x, y)
     int dx = x + cx(j), dy = y + cy(j), wall = -1;
     if (dy < 0 || dy >= G.ny) {
@@ -244,7 +263,7 @@ __global__ void k_unstream(Geo G, Phys ph, const float* tmp, float* dst, const f
       const int i = opp(j);   // the population that node (x, y) pulls back
       dst[j * P + k] = tmp[i * P + k];
       dst[(9 + j) * P + k] = tmp[(9 + i) * P + k];
-      if (G.tbc[wall]) {
+      if ((G.tmask >> wall) & 1) {
         const float Tw = wallT[wall * wstride + (wall < 2 ? x : y)];
         dst[(18 + j) * P + k] = 2.0f * wgt(i) * ph.Eref * Tw - tmp[(18 + i) * P + k];
       } else {
@@ -283,7 +302,7 @@ int grid_blocks(const lbf_sim* s, dim3& grid) {
 }
 
 template <int WX>
-int launch_wx(lbf_sim* s, int mode, bool red, Bufs B) {
+int launch_wx(lbf_sim* s, int mode, bool red, BufArgs B) {
   dim3 grid;
   grid_blocks(s, grid);
   const dim3 block(WX);
@@ -304,7 +323,7 @@ int launch_wx(lbf_sim* s, int mode, bool red, Bufs B) {
 }
 
 int launch_step(lbf_sim* s, int mode, bool red, double* red_buf) {
-  Bufs B = make_bufs(s);
+  BufArgs B = make_args(s);
   B.red = red_buf;
   switch (s->tile_x) {
     case 64: return launch_wx<64>(s, mode, red, B);
@@ -347,8 +366,12 @@ int lbf_create(const lbf_params* params, void* stream, void* workspace, size_t w
   s->G.ny = params->ny;
   s->G.px = params->periodic_x ? 1 : 0;
   s->G.py = params->periodic_y ? 1 : 0;
-  for (int w = 0; w < 4; ++w) s->G.tbc[w] = params->thermal_bc[w];
-  s->G.P = plane_stride(params->nx, params->ny);
+  s->G.tmask = 0;
+  for (int w = 0; w < 4; ++w) {
+    s->G.tbc[w] = params->thermal_bc[w];
+    if (params->thermal_bc[w] == LBF_DIRICHLET) s->G.tmask |= 1 << w;
+  }
+  s->G.P = (int)plane_stride(params->nx, params->ny);
   fill_phys(params, s->ph);
   s->L = make_layout(params->nx, params->ny);
   s->stream = (hipStream_t)stream;
@@ -438,13 +461,39 @@ int lbf_init_fields(lbf_sim* s, const float* phi, const float* T, int32_t on_dev
   hipLaunchKernelGGL(k_init_eq, node_grid(s), dim3(256), 0, s->stream, s->G, s->ph,
                      (const float*)fptr(s, s->L.stat), (const float*)stage, tmp);
   HIP_TRY(hipGetLastError());
-  hipLaunchKernelGGL(k_unstream, node_grid(s), dim3(256), 0, s->stream, s->G, s->ph,
-                     (const float*)tmp, fptr(s, s->L.dist[0]), (const float*)fptr(s, s->L.wall),
-                     s->L.wstride);
-  HIP_TRY(hipGetLastError());
   HIP_TRY(hipMemsetAsync(fptr(s, s->L.lag[0]), 0, NLAG * (size_t)s->G.P * sizeof(float),
                          s->stream));
+  hipLaunchKernelGGL(k_unstream, node_grid(s), dim3(256), 0, s->stream, s->G, s->ph,
+                     (const float*)tmp, fptr(s, s->L.dist[0]), fptr(s, s->L.stat),
+                     fptr(s, s->L.lag[0]), (const float*)fptr(s, s->L.wall), s->L.wstride);
+  HIP_TRY(hipGetLastError());
   s->step = 0;
+  s->have_budget = false;
+  s->have_init = true;
+  return LBF_OK;
+}
+
+int lbf_set_poststream_state(lbf_sim* s, const float* dist, const float* lag, int64_t step,
+                              int32_t on_device) {
+  if (!s || !dist || !lag) return fail(LBF_EINVAL, "NULL argument");
+  if (!s->have_geo) return fail(LBF_ESTATE, "lbf_set_geometry must precede the state");
+  const size_t n = (size_t)s->G.nx * s->G.ny;
+  float* tmp = fptr(s, s->L.dist[1 - s->cur]);
+  for (int pl = 0; pl < NDIST; ++pl) {
+    int rc = copy_in(s, tmp + (size_t)pl * s->G.P, dist + pl * n, n * sizeof(float), on_device);
+    if (rc) return rc;
+  }
+  float* lg = fptr(s, s->L.lag[s->cur]);
+  for (int pl = 0; pl < LAG_GHI; ++pl) {   // the high parts come from dist
+    int rc = copy_in(s, lg + (size_t)pl * s->G.P, lag + pl * n, n * sizeof(float), on_device);
+    if (rc) return rc;
+  }
+  hipLaunchKernelGGL(k_unstream, node_grid(s), dim3(256), 0, s->stream, s->G, s->ph,
+                     (const float*)tmp, fptr(s, s->L.dist[s->cur]), fptr(s, s->L.stat),
+                     fptr(s, s->L.lag[s->cur]), (const float*)fptr(s, s->L.wall), s->L.wstride);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  s->step = step;
   s->have_budget = false;
   s->have_init = true;
   return LBF_OK;
@@ -542,7 +591,8 @@ int lbf_set_tile(lbf_sim* s, int32_t tile_x, int32_t tile_y) {
   if (!s) return fail(LBF_EINVAL, "sim is NULL");
   if (tile_x != 64 && tile_x != 128 && tile_x != 256)
     return fail(LBF_EINVAL, "tile_x must be 64, 128 or 256 (got %d)", tile_x);
-  if (tile_y < 1) return fail(LBF_EINVAL, "tile_y must be >= 1 (got %d)", tile_y);
+  if (tile_y < 1 || tile_y > CY_MAX)
+    return fail(LBF_EINVAL, "tile_y must be in [1, %d] (got %d)", CY_MAX, tile_y);
   s->tile_x = tile_x;
   s->tile_y = tile_y;
   return LBF_OK;
@@ -566,7 +616,8 @@ int lbf_save_state(lbf_sim* s, void* dst, size_t cap) {
   const size_t need = lbf_state_bytes(s);
   if (cap < need) return fail(LBF_ENOMEM, "state needs %zu bytes", need);
   char* d = (char*)dst;
-  const size_t db = NDIST * (size_t)s->G.P * sizeof(float), lb = NLAG * (size_t)s->G.P * sizeof(float);
+  const size_t pb = (size_t)s->G.P * sizeof(float);
+  const size_t db = NDIST * pb, lb = NLAG * pb;
   HIP_TRY(hipMemcpyAsync(d, s->ws + s->L.dist[s->cur], db, hipMemcpyDeviceToDevice, s->stream));
   HIP_TRY(hipMemcpyAsync(d + db, s->ws + s->L.lag[s->cur], lb, hipMemcpyDeviceToDevice, s->stream));
   long long hdr[8] = {0x6c626673LL, s->step, s->G.nx, s->G.ny, 0, 0, 0, 0};
@@ -580,12 +631,14 @@ int lbf_load_state(lbf_sim* s, const void* src, size_t bytes) {
   const size_t need = lbf_state_bytes(s);
   if (bytes < need) return fail(LBF_EINVAL, "state of %zu bytes, %zu needed", bytes, need);
   const char* d = (const char*)src;
-  const size_t db = NDIST * (size_t)s->G.P * sizeof(float), lb = NLAG * (size_t)s->G.P * sizeof(float);
+  const size_t pb = (size_t)s->G.P * sizeof(float);
+  const size_t db = NDIST * pb, lb = NLAG * pb;
   long long hdr[8];
   HIP_TRY(hipMemcpyAsync(hdr, d + db + lb, sizeof hdr, hipMemcpyDeviceToHost, s->stream));
   HIP_TRY(hipStreamSynchronize(s->stream));
   if (hdr[0] != 0x6c626673LL || hdr[2] != s->G.nx || hdr[3] != s->G.ny)
     return fail(LBF_EINVAL, "state buffer does not match this lattice");
+  if (!s->have_geo) return fail(LBF_ESTATE, "lbf_set_geometry must precede lbf_load_state");
   HIP_TRY(hipMemcpyAsync(s->ws + s->L.dist[s->cur], d, db, hipMemcpyDeviceToDevice, s->stream));
   HIP_TRY(hipMemcpyAsync(s->ws + s->L.lag[s->cur], d + db, lb, hipMemcpyDeviceToDevice, s->stream));
   HIP_TRY(hipStreamSynchronize(s->stream));

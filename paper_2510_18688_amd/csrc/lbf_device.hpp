@@ -7,13 +7,17 @@
 //                  at the node itself, so every store is row-coalesced and
 //                  aligned and the pull loads are row-coalesced with a
 //                  +-1 element shift;
-//   lagged fields  5 planes: f_s, Q = rho C_p T mdot, (phi u)_x, (phi u)_y, p
-//                  of the previous step;
+//   lagged fields  7 planes: f_s, Q = rho C_p T mdot, (phi u)_x, (phi u)_y, p
+//                  of the previous step, and the high parts of g_0 and h_0;
 //   static fields  3 planes: phi0, cos(theta), lap(phi0).
 // Both distributions and lagged fields are double-buffered (ping-pong).
-// All three populations are deviation-form about the rest state
-// (p = 0, u = 0, phi = 0, mu = 0, T = 0): f^eq vanishes at rest exactly, and
-// g, h carry only the O(1) order parameter and enthalpy.
+// Storage is deviation-form: f^eq vanishes at the rest state (p = 0, u = 0)
+// exactly; the moving g_i, h_i (i > 0) carry only O(mu) and O(rho_ref C_p T)
+// values.  The rest populations g_0 ~ phi and h_0 ~ rho H hold the O(1) part
+// and never move: each is an unevaluated float-float sum hi + lo (hi in a
+// lagged plane, lo in the distribution plane) renormalised every step with an
+// exact two-sum, so the order parameter and the enthalpy are carried to ~48
+// bits while every sum and relaxation is formed from small deviations.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -21,12 +25,15 @@
 namespace lbf {
 
 constexpr int NDIST = 27;
-constexpr int NLAG = 5;
+constexpr int NLAG = 7;
 constexpr int NSTAT = 3;
 constexpr int NFIELD = 13;
 constexpr int NRED = 11;
 
-enum { LAG_FS = 0, LAG_Q = 1, LAG_JX = 2, LAG_JY = 3, LAG_P = 4 };
+// lagged planes: f_s, Q = rho C_p T mdot, (phi u)_x, (phi u)_y, p of the
+// previous step, and the high parts of the rest populations g_0, h_0
+enum { LAG_FS = 0, LAG_Q = 1, LAG_JX = 2, LAG_JY = 3, LAG_P = 4, LAG_GHI = 5, LAG_HHI = 6 };
+// static planes: phi0, cos(theta), lap(phi0)
 enum { ST_PHI0 = 0, ST_CTH = 1, ST_LAP0 = 2 };
 enum { MODE_STEP = 0, MODE_FIELDS = 1 };
 
@@ -50,7 +57,8 @@ struct Geo {
   int nx, ny;
   int px, py;        // periodic flags
   int tbc[4];        // per wall: 0 adiabatic, 1 Dirichlet (bottom, top, left, right)
-  long long P;       // plane stride in floats
+  int tmask;         // bit w set when wall w is Dirichlet
+  int P;             // plane stride in floats (every byte offset fits 32 bits)
 };
 
 // Physical constants in the form the kernels use them.
@@ -60,24 +68,93 @@ struct Phys {
   float a3;          // 3 sigma / eps
   float kap;         // 3 eps sigma / 8
   float tau_g;       // Mbar / c_s^2 + 1/2
+  float inv_tau_g;   // 1 / tau_g
+  float pg;          // 1 - 1 / (2 tau_g)
   float Eref;        // rho_ref C_p,ref
   float three_over_Eref;
   float mdot_coef;   // 1 - rho_s / rho_l
+  float pcm_floor;   // liquid weight below which a node holds no phase-change material
+  float inv_pcm_span; // 1 / (1 - pcm_floor)
   int latch, src_tau_a, subfix;
 };
 
-// Buffers of one lattice.
+// Buffers of one lattice.  Device arrays are addressed through buffer
+// resources: a lane supplies the 32-bit byte offset of its node and the
+// plane offset rides in a scalar register, so no 64-bit address arithmetic
+// is spent per access (and out-of-range offsets read zero instead of
+// faulting).
+typedef __amdgpu_buffer_rsrc_t Rsrc;
+
 struct Bufs {
-  const float* din;   // NDIST planes, post-collision of the previous step
-  float* dout;        // NDIST planes, written by a step
-  const float* lin;   // NLAG planes of the previous step
-  float* lout;        // NLAG planes, written by a step
-  const float* stat;  // NSTAT planes
+  Rsrc din;           // NDIST planes, post-collision of the previous step
+  Rsrc dout;          // NDIST planes, written by a step
+  Rsrc lin;           // NLAG planes of the previous step
+  Rsrc lout;          // NLAG planes, written by a step
+  Rsrc stat;          // NSTAT planes
+  Rsrc fields;        // NFIELD planes (read-out mode)
   const float* wallT; // 4 profiles, each `wstride` floats
   int wstride;
-  float* fields;      // NFIELD planes (read-out mode)
   double* red;        // per-block partial sums, NRED each
 };
+
+__device__ __forceinline__ Rsrc make_rsrc(const void* p, uint32_t bytes) {
+  // gfx9 family: raw 32-bit data, offset addressing
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, (int)bytes, 0x00020000);
+}
+
+// Plain pointers of one lattice, as the host passes them.
+struct BufArgs {
+  const float* din;
+  float* dout;
+  const float* lin;
+  float* lout;
+  const float* stat;
+  float* fields;
+  const float* wallT;
+  int wstride;
+  double* red;
+};
+
+__device__ __forceinline__ Bufs make_bufs(const BufArgs& a, int P) {
+  const uint32_t pb = (uint32_t)P * 4u;
+  Bufs B;
+  B.din = make_rsrc(a.din, NDIST * pb);
+  B.dout = make_rsrc(a.dout, NDIST * pb);
+  B.lin = make_rsrc(a.lin, NLAG * pb);
+  B.lout = make_rsrc(a.lout, NLAG * pb);
+  B.stat = make_rsrc(a.stat, NSTAT * pb);
+  B.fields = make_rsrc(a.fields, a.fields ? NFIELD * pb : 0u);
+  B.wallT = a.wallT;
+  B.wstride = a.wstride;
+  B.red = a.red;
+  return B;
+}
+
+// load plane `plane` at node index `k`
+__device__ __forceinline__ float ldp(Rsrc r, int plane, int P, int k) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
+                                       r, (uint32_t)k * 4u, (uint32_t)plane * (uint32_t)P * 4u, 0));
+}
+// load at an absolute element index
+__device__ __forceinline__ float lda(Rsrc r, uint32_t elem) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, elem * 4u, 0, 0));
+}
+__device__ __forceinline__ void stp(Rsrc r, int plane, int P, int k, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (uint32_t)k * 4u,
+                                        (uint32_t)plane * (uint32_t)P * 4u, 0);
+}
+
+// Reciprocal with the hardware approximation (1 ulp), used for every per-node
+// division: the FP32 path's accuracy is set by its storage, not by this.
+__device__ __forceinline__ float rcp(float v) { return __builtin_amdgcn_rcpf(v); }
+
+// Exact two-sum: hi + d = s + err with s = fl(hi + d) (no reassociation of
+// these additions is allowed, and none involves a product to contract).
+__device__ __forceinline__ void two_sum(float hi, float d, float& s, float& err) {
+  s = hi + d;
+  const float bb = s - hi;
+  err = (hi - (s - bb)) + (d - bb);
+}
 
 __device__ __forceinline__ float clampf(float v, float lo, float hi) {
   return v < lo ? lo : (v > hi ? hi : v);
@@ -88,30 +165,6 @@ __device__ __forceinline__ float zeta(float s, float C, float zs, float zl, floa
   return s * zs + (1.0f - s) * (C * zl + (1.0f - C) * zg);
 }
 
-// Source node of the pull of population i at (x, y).  Returns the linear
-// node index, or -1 with `wall` set when the link crosses a wall; a link
-// through a bottom/top wall takes that wall even at a corner.
-__device__ __forceinline__ int pull_src(const Geo& G, int x, int y, int i, int& wall) {
-  int sx = x - cx(i), sy = y - cy(i);
-  if (sy < 0 || sy >= G.ny) {
-    if (G.py) {
-      sy = sy < 0 ? sy + G.ny : sy - G.ny;
-    } else {
-      wall = sy < 0 ? 0 : 1;
-      return -1;
-    }
-  }
-  if (sx < 0 || sx >= G.nx) {
-    if (G.px) {
-      sx = sx < 0 ? sx + G.nx : sx - G.nx;
-    } else {
-      wall = sx < 0 ? 2 : 3;
-      return -1;
-    }
-  }
-  return sy * G.nx + sx;
-}
-
 // Node index of a stencil neighbour: periodic wrap or mirror ghost.
 __device__ __forceinline__ int map_axis(int v, int n, int periodic) {
   if (v < 0) return periodic ? v + n : 0;
@@ -119,60 +172,128 @@ __device__ __forceinline__ int map_axis(int v, int n, int periodic) {
   return v;
 }
 
-// Pull the phase-field and enthalpy populations of node (x, y), applying
-// bounce-back (g; h on adiabatic walls) and anti-bounce-back with the wall
-// temperature (h on Dirichlet walls).  `flux` gains the energy that the
+// Source coordinate of a pull along one axis: v - c for c in {-1, 0, 1};
+// periodic wrap, or -1 when the link crosses a wall.
+__device__ __forceinline__ int pull_axis(int v, int c, int n, int periodic) {
+  int s = v - c;
+  if (s < 0) return periodic ? s + n : -1;
+  if (s >= n) return periodic ? s - n : -1;
+  return s;
+}
+
+// Pull sources of one node: for each axis the source coordinate for
+// c = +1, 0, -1 (index c + 1 holds v - c).
+struct PullNbr {
+  int sx[3], sy[3];
+};
+
+__device__ __forceinline__ void pull_nbr(const Geo& G, int x, int y, PullNbr& n) {
+  n.sx[0] = pull_axis(x, -1, G.nx, G.px);
+  n.sx[1] = x;
+  n.sx[2] = pull_axis(x, 1, G.nx, G.px);
+  n.sy[0] = pull_axis(y, -1, G.ny, G.py);
+  n.sy[1] = y;
+  n.sy[2] = pull_axis(y, 1, G.ny, G.py);
+}
+
+// Element index (plane base + node) of the pull of population `i` of the
+// block of planes starting at `base`; across a wall the opposite
+// population of the node itself (bounce-back).  A link that crosses a
+// bottom/top wall takes that wall even at a corner; `wall` reports it.
+template <int I>
+__device__ __forceinline__ uint32_t pull_elem(const Geo& G, const PullNbr& n, int k, int base,
+                                              int& wall) {
+  const int sy = n.sy[cy(I) + 1], sx = n.sx[cx(I) + 1];
+  const bool wy = sy < 0, wx = sx < 0;
+  wall = wy ? (cy(I) > 0 ? 0 : 1) : (wx ? (cx(I) > 0 ? 2 : 3) : -1);
+  const uint32_t bb = (uint32_t)(base + opp(I)) * (uint32_t)G.P + (uint32_t)k;
+  const uint32_t st = (uint32_t)(base + I) * (uint32_t)G.P + (uint32_t)(sy * G.nx + sx);
+  return (wy || wx) ? bb : st;
+}
+
+template <int I>
+__device__ __forceinline__ void pull_one_gh(const Geo& G, const Phys& ph, const Bufs& B,
+                                            const PullNbr& n, int x, int y, int k, float* gv,
+                                            float* hv, float& flux) {
+  int wall;
+  const uint32_t eg = pull_elem<I>(G, n, k, 9, wall);
+  const uint32_t eh = eg + 9u * (uint32_t)G.P;
+  gv[I] = lda(B.din, eg);
+  float h = lda(B.din, eh);
+  if (wall >= 0 && ((G.tmask >> wall) & 1)) {
+    const float Tw = B.wallT[wall * B.wstride + (wall < 2 ? x : y)];
+    const float v = -h + 2.0f * wgt(I) * ph.Eref * Tw;
+    flux += v - h;
+    h = v;
+  }
+  hv[I] = h;
+}
+
+// Pull the phase-field and enthalpy populations of node (x, y): bounce-back
+// for g and for h on adiabatic walls, anti-bounce-back with the wall
+// temperature for h on Dirichlet walls.  `flux` gains the energy that the
 // Dirichlet links bring in.
 __device__ __forceinline__ void pull_gh(const Geo& G, const Phys& ph, const Bufs& B, int x,
                                         int y, float* gv, float* hv, float& flux) {
-  const long long P = G.P;
+  PullNbr n;
+  pull_nbr(G, x, y, n);
   const int k = y * G.nx + x;
-#pragma unroll
-  for (int i = 0; i < 9; ++i) {
-    int wall = 0;
-    const int s = pull_src(G, x, y, i, wall);
-    if (s >= 0) {
-      gv[i] = B.din[(9 + i) * P + s];
-      hv[i] = B.din[(18 + i) * P + s];
-    } else {
-      const int j = opp(i);
-      gv[i] = B.din[(9 + j) * P + k];
-      const float hb = B.din[(18 + j) * P + k];
-      if (G.tbc[wall]) {
-        const float Tw = B.wallT[wall * B.wstride + (wall < 2 ? x : y)];
-        hv[i] = -hb + 2.0f * wgt(i) * ph.Eref * Tw;
-        flux += hv[i] - hb;
-      } else {
-        hv[i] = hb;
-      }
-    }
-  }
+  pull_one_gh<0>(G, ph, B, n, x, y, k, gv, hv, flux);
+  pull_one_gh<1>(G, ph, B, n, x, y, k, gv, hv, flux);
+  pull_one_gh<2>(G, ph, B, n, x, y, k, gv, hv, flux);
+  pull_one_gh<3>(G, ph, B, n, x, y, k, gv, hv, flux);
+  pull_one_gh<4>(G, ph, B, n, x, y, k, gv, hv, flux);
+  pull_one_gh<5>(G, ph, B, n, x, y, k, gv, hv, flux);
+  pull_one_gh<6>(G, ph, B, n, x, y, k, gv, hv, flux);
+  pull_one_gh<7>(G, ph, B, n, x, y, k, gv, hv, flux);
+  pull_one_gh<8>(G, ph, B, n, x, y, k, gv, hv, flux);
+}
+
+template <int I>
+__device__ __forceinline__ void pull_one_f(const Geo& G, const Bufs& B, const PullNbr& n, int k,
+                                           float* fv) {
+  int wall;
+  fv[I] = lda(B.din, pull_elem<I>(G, n, k, 0, wall));
 }
 
 __device__ __forceinline__ void pull_f(const Geo& G, const Bufs& B, int x, int y, float* fv) {
-  const long long P = G.P;
+  PullNbr n;
+  pull_nbr(G, x, y, n);
   const int k = y * G.nx + x;
-#pragma unroll
-  for (int i = 0; i < 9; ++i) {
-    int wall = 0;
-    const int s = pull_src(G, x, y, i, wall);
-    fv[i] = (s >= 0) ? B.din[i * P + s] : B.din[opp(i) * P + k];
-  }
+  pull_one_f<0>(G, B, n, k, fv);
+  pull_one_f<1>(G, B, n, k, fv);
+  pull_one_f<2>(G, B, n, k, fv);
+  pull_one_f<3>(G, B, n, k, fv);
+  pull_one_f<4>(G, B, n, k, fv);
+  pull_one_f<5>(G, B, n, k, fv);
+  pull_one_f<6>(G, B, n, k, fv);
+  pull_one_f<7>(G, B, n, k, fv);
+  pull_one_f<8>(G, B, n, k, fv);
 }
 
 // Node-local moments: liquid weight, phase-change fraction, total enthalpy,
 // enthalpy map, ice fraction, mass source, order parameter and density.
+// dphi = phi - ref_g and dH = rho H - ref_h keep the small parts.
 struct Mom {
-  float C, chi, rhoH, T, fs, fstot, mdot, phi, rho, Ksol, Kliq;
+  float C, chi, rhoH, T, fs, fstot, mdot, phi, rho, Ksol, Kliq, dphi, dH;
+  float ref_g, sg, sh;   // references and stored sums (for exact global sums)
 };
 
-__device__ __forceinline__ void moments(const Phys& ph, float sg, float sh, float fs_prev,
-                                        float Q_prev, float phi0, Mom& m) {
-  const float C = clampf(0.5f * (1.0f - phi0 + sg), 0.0f, 1.0f);
-  float chi = ph.latch ? fmaxf(C, fs_prev) : C;
+// ref_g, ref_h: references of the rest populations; sg, sh: sums of the
+// stored populations (rest population as its deviation).
+__device__ __forceinline__ void moments(const Phys& ph, float ref_g, float sg, float ref_h,
+                                        float sh, float fs_prev, float Q_prev, float phi0,
+                                        Mom& m) {
+  const float phihat = ref_g + sg;
+  const float C = clampf(0.5f * (1.0f - phi0 + phihat), 0.0f, 1.0f);
+  // phase-change fraction: liquid weight above the floor, latched by the
+  // previous ice fraction, at most the non-solid fraction
+  const float Cp = clampf((C - ph.pcm_floor) * ph.inv_pcm_span, 0.0f, 1.0f);
+  float chi = ph.latch ? fmaxf(Cp, fs_prev) : Cp;
   chi = clampf(chi, 0.0f, 1.0f - phi0);
   // total enthalpy with the lagged source (Sec. 3.3)
-  const float rhoH = sh + 0.5f * Q_prev;
+  const float dH = sh + 0.5f * Q_prev;
+  const float rhoH = ref_h + dH;
   // enthalpy map (Sec. 2, Hfl) for a node with phase-change fraction chi
   const float s_sol = fminf(1.0f, phi0 + chi);
   const float Kliq = zeta(phi0, C, ph.rho_s, ph.rho_l, ph.rho_g) *
@@ -184,13 +305,13 @@ __device__ __forceinline__ void moments(const Phys& ph, float sg, float sh, floa
   float T, fl;
   if (rhoH < Es) {
     fl = 0.0f;
-    T = rhoH / Ksol;
+    T = rhoH * rcp(Ksol);
   } else if (rhoH <= El) {
-    fl = (El > Es) ? (rhoH - Es) / (El - Es) : 1.0f;
+    fl = (El > Es) ? (rhoH - Es) * rcp(El - Es) : 1.0f;
     T = ph.T_m;
   } else {
     fl = 1.0f;
-    T = ph.T_m + (rhoH - El) / Kliq;
+    T = ph.T_m + (rhoH - El) * rcp(Kliq);
   }
   const float fs = chi * (1.0f - fl);
   const float fstot = fminf(1.0f, phi0 + fs);
@@ -202,7 +323,14 @@ __device__ __forceinline__ void moments(const Phys& ph, float sg, float sh, floa
   m.fs = fs;
   m.fstot = fstot;
   m.mdot = mdot;
-  m.phi = sg / (1.0f - 0.5f * mdot);                   // Sec. 3.2 with div u = mdot
+  // Sec. 3.2 with div u = mdot: phi = phihat / (1 - mdot/2), formed on the
+  // deviation from the reference
+  m.dphi = (sg + 0.5f * mdot * ref_g) * rcp(1.0f - 0.5f * mdot);
+  m.phi = ref_g + m.dphi;
+  m.dH = dH;
+  m.ref_g = ref_g;
+  m.sg = sg;
+  m.sh = sh;
   m.rho = zeta(fstot, C, ph.rho_s, ph.rho_l, ph.rho_g);
   m.Ksol = Ksol;
   m.Kliq = Kliq;
@@ -237,15 +365,18 @@ struct Stencil {
 struct Post {
   float ux, uy, p, mu, Q, jx, jy;
   float heat_src, reset;
+  float ghi;    // new high part of g_0 (gv[0] holds the low part)
+  float hhi;    // new high part of h_0 (hv[0] holds the low part)
 };
 
 // Collision of the three populations at one node (Sec. 3.1-3.3), in place
-// on fv, gv, hv.  When `collide` is false only the diagnostics are filled.
+// on fv, gv, hv (gv[0], hv[0] as deviations from the node's references).
+// When `collide` is false only the diagnostics are filled.
 template <bool COLLIDE>
 __device__ __forceinline__ void collide_node(const Phys& ph, const Mom& m, const Stencil& S,
                                              float phi0, float cth, float lap_phi0, float Q_prev,
-                                             float jx_prev, float jy_prev, float* fv, float* gv,
-                                             float* hv, Post& o) {
+                                             float jx_prev, float jy_prev, float ref_h, float* fv,
+                                             float* gv, float* hv, Post& o) {
   // isotropic stencils (factor 1/c_s^2 = 3 for the gradient, 2/c_s^2 = 6 for
   // the Laplacian)
   float gphx = 0, gphy = 0, lphi = 0, lfs = 0, grx = 0, gry = 0, gpx = 0, gpy = 0;
@@ -268,10 +399,10 @@ __device__ __forceinline__ void collide_node(const Phys& ph, const Mom& m, const
   const float mu_v = zeta(fstot, C, ph.mu_s, ph.mu_l, ph.mu_g);
   const float lam = zeta(fstot, C, ph.lam_s, ph.lam_l, ph.lam_g);
   const float cp = zeta(fstot, C, ph.cp_s, ph.cp_l, ph.cp_g);
-  const float inv_rho = 1.0f / rho;
+  const float inv_rho = rcp(rho);
   const float tau_f = 3.0f * mu_v * inv_rho + 0.5f;
   const float tau_a = lam * ph.three_over_Eref + 0.5f;
-  const float inv_tau_a = 1.0f / tau_a;
+  const float inv_tau_a = rcp(tau_a);
   const float inv_tau_s = 2.0f - inv_tau_a;           // 1/tau_s + 1/tau_a = 2
 
   const float mu = chem_pot(ph, phi, lphi, phi0, cth, lap_phi0, m.fs, lfs);
@@ -304,7 +435,7 @@ __device__ __forceinline__ void collide_node(const Phys& ph, const Mom& m, const
   if (!COLLIDE) return;
 
   // flow: pressure-based equilibrium and forcing (Sec. 3.1)
-  const float inv_tau_f = 1.0f / tau_f;
+  const float inv_tau_f = rcp(tau_f);
   const float pf = 1.0f - 0.5f * inv_tau_f;
   const float rfx = rho * fdx + Fx, rfy = rho * fdy + Fy;
 #pragma unroll
@@ -318,18 +449,21 @@ __device__ __forceinline__ void collide_node(const Phys& ph, const Mom& m, const
     fv[i] = fv[i] - (fv[i] - feq) * inv_tau_f + pf * Fi;
   }
   // phase field (Sec. 3.2)
-  const float inv_tau_g = 1.0f / ph.tau_g;
-  const float pg = 1.0f - 0.5f * inv_tau_g;
+  const float inv_tau_g = ph.inv_tau_g;
+  const float pg = ph.pg;
   const float djx = jx - jx_prev, djy = jy - jy_prev;
   const float pm = phi * mdot;
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
     const float cj = cx(i) * jx + cy(i) * jy;
-    const float geq = (i == 0 ? phi : 0.0f) + (wgt(i) - (i == 0 ? 1.0f : 0.0f)) * mu +
+    // rest population: equilibrium relative to the node's reference
+    const float geq = (i == 0 ? m.dphi : 0.0f) + (wgt(i) - (i == 0 ? 1.0f : 0.0f)) * mu +
                       3.0f * wgt(i) * cj;
     const float Gi = wgt(i) * (3.0f * (cx(i) * djx + cy(i) * djy) + pm);
     gv[i] = gv[i] - (gv[i] - geq) * inv_tau_g + pg * Gi;
   }
+  // renormalise g_0 = hi + lo: hi' = fl(hi + d), lo' = the exact residual
+  two_sum(m.ref_g, gv[0], o.ghi, gv[0]);
   // enthalpy, TRT (Sec. 3.3, eq22)
   const float ET = ph.Eref * T;
   const float cT = rhocp * T;
@@ -337,7 +471,8 @@ __device__ __forceinline__ void collide_node(const Phys& ph, const Mom& m, const
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
     const float cu = cx(i) * ux + cy(i) * uy;
-    heq[i] = (i == 0) ? m.rhoH - ET + wgt(0) * (ET - 1.5f * cT * uu)
+    // rest population relative to the node's reference: rhoH - ref_h = dH
+    heq[i] = (i == 0) ? m.dH - (1.0f - wgt(0)) * ET - 1.5f * wgt(0) * cT * uu
                       : wgt(i) * (ET + cT * (3.0f * cu + 4.5f * cu * cu - 1.5f * uu));
   }
   const float ps = ph.src_tau_a ? (1.0f - 0.5f * inv_tau_a) : (1.0f - 0.5f * inv_tau_s);
@@ -351,7 +486,8 @@ __device__ __forceinline__ void collide_node(const Phys& ph, const Mom& m, const
   }
   o.heat_src = 0.5f * Q_prev * inv_tau_s + ps * Q;
   if (ph.subfix && phi0 >= 0.5f) {
-    // isothermal solid region: reset to the equilibrium at the held temperature
+    // isothermal solid region: reset to the equilibrium at the held
+    // temperature (rest population relative to its reference)
     const float Tw = ph.T_sub;
     const float rH = enthalpy_at(ph, Tw, m.Ksol, m.Kliq, m.chi);
     const float EW = ph.Eref * Tw;
@@ -359,14 +495,16 @@ __device__ __forceinline__ void collide_node(const Phys& ph, const Mom& m, const
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
       before += hn[i];
-      const float e = (i == 0) ? rH - EW + wgt(0) * EW : wgt(i) * EW;
+      const float e = (i == 0) ? (rH - ref_h) - (1.0f - wgt(0)) * EW : wgt(i) * EW;
       after += e;
       hn[i] = e;
     }
     o.reset = after - before;
   }
 #pragma unroll
-  for (int i = 0; i < 9; ++i) hv[i] = hn[i];
+  for (int i = 1; i < 9; ++i) hv[i] = hn[i];
+  // renormalise h_0 = hi + lo
+  two_sum(ref_h, hn[0], o.hhi, hv[0]);
 }
 
 }  // namespace lbf

@@ -23,7 +23,7 @@ REDS = ["sum_g", "sum_h", "sum_fs", "sum_liq", "umax", "nonfinite", "src_phi", "
         "wall_flux", "reset", "step"]
 EXPORTS = ["lbf_workspace_bytes", "lbf_create", "lbf_set_geometry", "lbf_set_wall_temperature",
            "lbf_init_fields", "lbf_step", "lbf_read_field", "lbf_read_fields", "lbf_reduce",
-           "lbf_set_tile", "lbf_get_tile", "lbf_state_bytes", "lbf_save_state",
+           "lbf_set_poststream_state", "lbf_set_tile", "lbf_get_tile", "lbf_state_bytes", "lbf_save_state",
            "lbf_load_state", "lbf_set_timing", "lbf_last_step_kernel_ms", "lbf_last_error",
            "lbf_destroy"]
 
@@ -45,17 +45,21 @@ class Params(C.Structure):
         (k, C.c_double) for k in (
             "rho_l", "rho_g", "rho_s", "mu_l", "mu_g", "mu_s", "lam_l", "lam_g", "lam_s",
             "cp_l", "cp_g", "cp_s", "latent", "T_m", "sigma", "eps", "mobility", "cos_psi",
-            "rho_ref", "T_substrate")]
+            "rho_ref", "T_substrate", "pcm_floor")]
 
 
 _lib = None
 
 
 def load(path: str = LIB_PATH):
-    """Load liblbf.so and declare its signatures (no GPU needed)."""
+    """Load liblbf.so and declare its signatures (no GPU needed).
+
+    torch is imported first so that the HIP runtime it carries is the one
+    liblbf binds to (two runtimes in one process do not share devices)."""
     global _lib
     if _lib is not None:
         return _lib
+    import torch  # noqa: F401
     if not os.path.exists(path):
         raise RuntimeError(f"liblbf.so not built ({path}); run python -m paper_2510_18688_amd.build")
     L = C.CDLL(path)
@@ -66,6 +70,7 @@ def load(path: str = LIB_PATH):
     L.lbf_set_geometry.argtypes = [vp, vp, vp, i32]
     L.lbf_set_wall_temperature.argtypes = [vp, i32, vp, i32, i32]
     L.lbf_init_fields.argtypes = [vp, vp, vp, i32]
+    L.lbf_set_poststream_state.argtypes = [vp, vp, vp, C.c_int64, i32]
     L.lbf_step.argtypes = [vp, i32]
     L.lbf_read_field.argtypes = [vp, i32, vp, i32]
     L.lbf_read_fields.argtypes = [vp, vp, i32]
@@ -103,7 +108,7 @@ def make_params(case) -> Params:
     p.substrate_fixed = int(case.substrate_fixed)
     for k in ("rho_l", "rho_g", "rho_s", "mu_l", "mu_g", "mu_s", "lam_l", "lam_g", "lam_s",
               "cp_l", "cp_g", "cp_s", "latent", "T_m", "sigma", "eps", "mobility", "cos_psi",
-              "rho_ref"):
+              "rho_ref", "pcm_floor"):
         setattr(p, k, float(getattr(m, k)))
     p.T_substrate = float(case.T_substrate)
     return p
@@ -190,6 +195,14 @@ class Sim:
         if d != d2:
             raise LbfError(-1, "phi and T must both be host or both device")
         check(_lib.lbf_init_fields(self.h, a, b, d))
+
+    def set_poststream_state(self, f, g, h, lag, step: int = 0) -> None:
+        """Load post-streaming distributions (9 planes each) and lagged fields (5)."""
+        dist = np.ascontiguousarray(np.concatenate([np.reshape(f, (9, -1)), np.reshape(g, (9, -1)),
+                                                    np.reshape(h, (9, -1))]), dtype=np.float32)
+        lg = np.ascontiguousarray(np.reshape(lag, (5, -1)), dtype=np.float32)
+        check(_lib.lbf_set_poststream_state(self.h, C.c_void_p(dist.ctypes.data),
+                                            C.c_void_p(lg.ctypes.data), int(step), 0))
 
     def set_tile(self, tx: int, ty: int) -> None:
         check(_lib.lbf_set_tile(self.h, int(tx), int(ty)))

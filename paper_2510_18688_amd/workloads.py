@@ -59,6 +59,7 @@ class Material:
     mobility: float = 0.1
     cos_psi: float = 0.0
     rho_ref: float = 0.1
+    pcm_floor: float = 0.01
     latch_fs: int = 1
     h_src_tau_a: int = 0
 

@@ -59,9 +59,9 @@ def test_workspace_bytes(L):
     assert L.lbf_workspace_bytes(0, 5) == 0
     small = L.lbf_workspace_bytes(64, 48)
     big = L.lbf_workspace_bytes(2048, 2048)
-    assert small > 64 * 48 * 4 * (27 * 2 + 5 * 2 + 3)
-    # 67 resident state planes + 13 read-out planes + reduction scratch
-    assert 2048 * 2048 * 4 * 80 <= big <= 2048 * 2048 * 4 * 84
+    assert small > 64 * 48 * 4 * (27 * 2 + 7 * 2 + 3)
+    # 71 resident state planes + 13 read-out planes + reduction scratch
+    assert 2048 * 2048 * 4 * 84 <= big <= 2048 * 2048 * 4 * 88
 
 
 def _create_rc(L, case):
@@ -76,6 +76,7 @@ def _create_rc(L, case):
     (lambda c: setattr(c.mat, "rho_ref", 1.0), "unstable"),
     (lambda c: setattr(c.mat, "mu_g", 0.0), "positive"),
     (lambda c: setattr(c.mat, "eps", -4.0), "positive"),
+    (lambda c: setattr(c.mat, "pcm_floor", 1.0), "pcm_floor"),
     (lambda c: setattr(c, "thermal_bc", [2, 0, 0, 0]), "thermal_bc"),
 ])
 def test_invalid_params_rejected_on_host(L, mutate, needle):
