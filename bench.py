@@ -37,6 +37,9 @@ def parse():
     ap.add_argument("--tile", type=str, default="", help="TXxTY, e.g. 128x32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="first run an elementwise copy of MIB MiB (read + write), the "
+                         "reference kernel for scaling HBM byte counters")
     return ap.parse_args()
 
 
@@ -68,6 +71,15 @@ def main():
         sys.exit(2)
     import torch
     from paper_2510_18688_amd import lbf, workloads as W
+
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            torch.add(a, 1.0, out=b)
+        torch.cuda.synchronize()
+        del a, b
 
     case = W.curved_substrate()
     sim = lbf.Sim(case)

@@ -26,8 +26,17 @@ def _load() -> dict:
 
 
 def lookup(nx: int, ny: int) -> Optional[Tuple[int, int]]:
-    v = _load().get(f"{nx}x{ny}")
-    return tuple(v["tile"]) if v else None
+    """Best known tile for a lattice size: measured, else the nearest size measured."""
+    db = _load()
+    v = db.get(f"{nx}x{ny}")
+    if v:
+        return tuple(v["tile"])
+    if not db:
+        return None
+    def dist(key):
+        a, b = (int(t) for t in key.split("x"))
+        return abs(a * b - nx * ny)
+    return tuple(db[min(db, key=dist)]["tile"])
 
 
 def tune(sim, steps: int = 20, candidates: Iterable[Sequence[int]] = CANDIDATES,

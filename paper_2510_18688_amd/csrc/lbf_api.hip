@@ -303,21 +303,22 @@ int grid_blocks(const lbf_sim* s, dim3& grid) {
 
 template <int WX>
 int launch_wx(lbf_sim* s, int mode, bool red, BufArgs B) {
-  dim3 grid;
-  grid_blocks(s, grid);
-  const dim3 block(WX);
+  dim3 g2;
+  const int nt = grid_blocks(s, g2);
+  const int nbx = (int)g2.x;
+  const dim3 grid(nt), block(WX);
   if (mode == MODE_STEP && !red)
     hipLaunchKernelGGL((step_kernel<WX, MODE_STEP, false>), grid, block, 0, s->stream, s->G,
-                       s->ph, B, s->tile_y);
+                       s->ph, B, s->tile_y, nbx, nt);
   else if (mode == MODE_STEP && red)
     hipLaunchKernelGGL((step_kernel<WX, MODE_STEP, true>), grid, block, 0, s->stream, s->G,
-                       s->ph, B, s->tile_y);
+                       s->ph, B, s->tile_y, nbx, nt);
   else if (mode == MODE_FIELDS && !red)
     hipLaunchKernelGGL((step_kernel<WX, MODE_FIELDS, false>), grid, block, 0, s->stream, s->G,
-                       s->ph, B, s->tile_y);
+                       s->ph, B, s->tile_y, nbx, nt);
   else
     hipLaunchKernelGGL((step_kernel<WX, MODE_FIELDS, true>), grid, block, 0, s->stream, s->G,
-                       s->ph, B, s->tile_y);
+                       s->ph, B, s->tile_y, nbx, nt);
   HIP_TRY(hipGetLastError());
   return LBF_OK;
 }

@@ -86,8 +86,10 @@ struct Phys {
 typedef __amdgpu_buffer_rsrc_t Rsrc;
 
 struct Bufs {
-  Rsrc din;           // NDIST planes, post-collision of the previous step
-  Rsrc dout;          // NDIST planes, written by a step
+  // distributions, one resource per population block of 9 planes, so that
+  // the plane offsets (scalar operands) are shared by f, g and h
+  Rsrc fin, gin, hin;    // post-collision of the previous step
+  Rsrc fout, gout, hout; // written by a step
   Rsrc lin;           // NLAG planes of the previous step
   Rsrc lout;          // NLAG planes, written by a step
   Rsrc stat;          // NSTAT planes
@@ -118,8 +120,12 @@ struct BufArgs {
 __device__ __forceinline__ Bufs make_bufs(const BufArgs& a, int P) {
   const uint32_t pb = (uint32_t)P * 4u;
   Bufs B;
-  B.din = make_rsrc(a.din, NDIST * pb);
-  B.dout = make_rsrc(a.dout, NDIST * pb);
+  B.fin = make_rsrc(a.din, 9 * pb);
+  B.gin = make_rsrc(a.din + 9 * (size_t)P, 9 * pb);
+  B.hin = make_rsrc(a.din + 18 * (size_t)P, 9 * pb);
+  B.fout = make_rsrc(a.dout, 9 * pb);
+  B.gout = make_rsrc(a.dout + 9 * (size_t)P, 9 * pb);
+  B.hout = make_rsrc(a.dout + 18 * (size_t)P, 9 * pb);
   B.lin = make_rsrc(a.lin, NLAG * pb);
   B.lout = make_rsrc(a.lout, NLAG * pb);
   B.stat = make_rsrc(a.stat, NSTAT * pb);
@@ -139,9 +145,12 @@ __device__ __forceinline__ float ldp(Rsrc r, int plane, int P, int k) {
 __device__ __forceinline__ float lda(Rsrc r, uint32_t elem) {
   return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, elem * 4u, 0, 0));
 }
+#ifndef LBF_STORE_POLICY
+#define LBF_STORE_POLICY 2   // non-temporal: the new state is not re-read in this pass
+#endif
 __device__ __forceinline__ void stp(Rsrc r, int plane, int P, int k, float v) {
   __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (uint32_t)k * 4u,
-                                        (uint32_t)plane * (uint32_t)P * 4u, 0);
+                                        (uint32_t)plane * (uint32_t)P * 4u, LBF_STORE_POLICY);
 }
 
 // Reciprocal with the hardware approximation (1 ulp), used for every per-node
@@ -181,94 +190,83 @@ __device__ __forceinline__ int pull_axis(int v, int c, int n, int periodic) {
   return s;
 }
 
-// Pull sources of one node: for each axis the source coordinate for
-// c = +1, 0, -1 (index c + 1 holds v - c).
-struct PullNbr {
-  int sx[3], sy[3];
+// Pull sources of one node: the byte offset of x - c_i for each direction
+// (the node itself when the link crosses a wall) and masks of the wall
+// links.  Every population plane uses the same nine offsets; the plane
+// offset is a scalar operand of the load.
+struct Pull9 {
+  uint32_t off[9];
+  uint32_t k4;      // byte offset of the node itself
+  uint32_t wmask;   // bit i: link i crosses a wall
+  uint32_t ymask;   // bit i: the crossing is through a bottom/top wall
 };
 
-__device__ __forceinline__ void pull_nbr(const Geo& G, int x, int y, PullNbr& n) {
-  n.sx[0] = pull_axis(x, -1, G.nx, G.px);
-  n.sx[1] = x;
-  n.sx[2] = pull_axis(x, 1, G.nx, G.px);
-  n.sy[0] = pull_axis(y, -1, G.ny, G.py);
-  n.sy[1] = y;
-  n.sy[2] = pull_axis(y, 1, G.ny, G.py);
-}
-
-// Element index (plane base + node) of the pull of population `i` of the
-// block of planes starting at `base`; across a wall the opposite
-// population of the node itself (bounce-back).  A link that crosses a
-// bottom/top wall takes that wall even at a corner; `wall` reports it.
-template <int I>
-__device__ __forceinline__ uint32_t pull_elem(const Geo& G, const PullNbr& n, int k, int base,
-                                              int& wall) {
-  const int sy = n.sy[cy(I) + 1], sx = n.sx[cx(I) + 1];
-  const bool wy = sy < 0, wx = sx < 0;
-  wall = wy ? (cy(I) > 0 ? 0 : 1) : (wx ? (cx(I) > 0 ? 2 : 3) : -1);
-  const uint32_t bb = (uint32_t)(base + opp(I)) * (uint32_t)G.P + (uint32_t)k;
-  const uint32_t st = (uint32_t)(base + I) * (uint32_t)G.P + (uint32_t)(sy * G.nx + sx);
-  return (wy || wx) ? bb : st;
-}
-
-template <int I>
-__device__ __forceinline__ void pull_one_gh(const Geo& G, const Phys& ph, const Bufs& B,
-                                            const PullNbr& n, int x, int y, int k, float* gv,
-                                            float* hv, float& flux) {
-  int wall;
-  const uint32_t eg = pull_elem<I>(G, n, k, 9, wall);
-  const uint32_t eh = eg + 9u * (uint32_t)G.P;
-  gv[I] = lda(B.din, eg);
-  float h = lda(B.din, eh);
-  if (wall >= 0 && ((G.tmask >> wall) & 1)) {
-    const float Tw = B.wallT[wall * B.wstride + (wall < 2 ? x : y)];
-    const float v = -h + 2.0f * wgt(I) * ph.Eref * Tw;
-    flux += v - h;
-    h = v;
+__device__ __forceinline__ void pull9(const Geo& G, int x, int y, Pull9& p) {
+  const int sx[3] = {pull_axis(x, -1, G.nx, G.px), x, pull_axis(x, 1, G.nx, G.px)};
+  const int sy[3] = {pull_axis(y, -1, G.ny, G.py), y, pull_axis(y, 1, G.ny, G.py)};
+  const int k = y * G.nx + x;
+  p.k4 = (uint32_t)k * 4u;
+  p.wmask = 0u;
+  p.ymask = 0u;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const int xs = sx[cx(i) + 1], ys = sy[cy(i) + 1];
+    const bool wy = ys < 0, w = wy || xs < 0;
+    p.off[i] = w ? p.k4 : (uint32_t)(ys * G.nx + xs) * 4u;
+    p.wmask |= (uint32_t)w << i;
+    p.ymask |= (uint32_t)wy << i;
   }
-  hv[I] = h;
+}
+
+__device__ __forceinline__ float ldo(Rsrc r, uint32_t voff, int plane, int P) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
+                                       r, voff, (uint32_t)plane * (uint32_t)P * 4u, 0));
 }
 
 // Pull the phase-field and enthalpy populations of node (x, y): bounce-back
 // for g and for h on adiabatic walls, anti-bounce-back with the wall
-// temperature for h on Dirichlet walls.  `flux` gains the energy that the
+// temperature for h on Dirichlet walls (a link through a bottom/top wall
+// takes that wall even at a corner).  `flux` gains the energy that the
 // Dirichlet links bring in.
 __device__ __forceinline__ void pull_gh(const Geo& G, const Phys& ph, const Bufs& B, int x,
                                         int y, float* gv, float* hv, float& flux) {
-  PullNbr n;
-  pull_nbr(G, x, y, n);
-  const int k = y * G.nx + x;
-  pull_one_gh<0>(G, ph, B, n, x, y, k, gv, hv, flux);
-  pull_one_gh<1>(G, ph, B, n, x, y, k, gv, hv, flux);
-  pull_one_gh<2>(G, ph, B, n, x, y, k, gv, hv, flux);
-  pull_one_gh<3>(G, ph, B, n, x, y, k, gv, hv, flux);
-  pull_one_gh<4>(G, ph, B, n, x, y, k, gv, hv, flux);
-  pull_one_gh<5>(G, ph, B, n, x, y, k, gv, hv, flux);
-  pull_one_gh<6>(G, ph, B, n, x, y, k, gv, hv, flux);
-  pull_one_gh<7>(G, ph, B, n, x, y, k, gv, hv, flux);
-  pull_one_gh<8>(G, ph, B, n, x, y, k, gv, hv, flux);
-}
-
-template <int I>
-__device__ __forceinline__ void pull_one_f(const Geo& G, const Bufs& B, const PullNbr& n, int k,
-                                           float* fv) {
-  int wall;
-  fv[I] = lda(B.din, pull_elem<I>(G, n, k, 0, wall));
+  Pull9 n;
+  pull9(G, x, y, n);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    gv[i] = ldo(B.gin, n.off[i], i, G.P);
+    hv[i] = ldo(B.hin, n.off[i], i, G.P);
+  }
+  if (n.wmask) {
+#pragma unroll
+    for (int i = 1; i < 9; ++i) {
+      if ((n.wmask >> i) & 1u) {
+        const int j = opp(i);
+        gv[i] = ldo(B.gin, n.k4, j, G.P);
+        const float hb = ldo(B.hin, n.k4, j, G.P);
+        const int wall = ((n.ymask >> i) & 1u) ? (cy(i) > 0 ? 0 : 1) : (cx(i) > 0 ? 2 : 3);
+        if ((G.tmask >> wall) & 1) {
+          const float Tw = B.wallT[wall * B.wstride + (wall < 2 ? x : y)];
+          hv[i] = -hb + 2.0f * wgt(i) * ph.Eref * Tw;
+          flux += hv[i] - hb;
+        } else {
+          hv[i] = hb;
+        }
+      }
+    }
+  }
 }
 
 __device__ __forceinline__ void pull_f(const Geo& G, const Bufs& B, int x, int y, float* fv) {
-  PullNbr n;
-  pull_nbr(G, x, y, n);
-  const int k = y * G.nx + x;
-  pull_one_f<0>(G, B, n, k, fv);
-  pull_one_f<1>(G, B, n, k, fv);
-  pull_one_f<2>(G, B, n, k, fv);
-  pull_one_f<3>(G, B, n, k, fv);
-  pull_one_f<4>(G, B, n, k, fv);
-  pull_one_f<5>(G, B, n, k, fv);
-  pull_one_f<6>(G, B, n, k, fv);
-  pull_one_f<7>(G, B, n, k, fv);
-  pull_one_f<8>(G, B, n, k, fv);
+  Pull9 n;
+  pull9(G, x, y, n);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) fv[i] = ldo(B.fin, n.off[i], i, G.P);
+  if (n.wmask) {
+#pragma unroll
+    for (int i = 1; i < 9; ++i)
+      if ((n.wmask >> i) & 1u) fv[i] = ldo(B.fin, n.k4, opp(i), G.P);
+  }
 }
 
 // Node-local moments: liquid weight, phase-change fraction, total enthalpy,
@@ -302,17 +300,12 @@ __device__ __forceinline__ void moments(const Phys& ph, float ref_g, float sg, f
                      zeta(s_sol, C, ph.cp_s, ph.cp_l, ph.cp_g);
   const float Es = Ksol * ph.T_m;
   const float El = Kliq * ph.T_m + chi * ph.rho_l * ph.latent;
-  float T, fl;
-  if (rhoH < Es) {
-    fl = 0.0f;
-    T = rhoH * rcp(Ksol);
-  } else if (rhoH <= El) {
-    fl = (El > Es) ? (rhoH - Es) * rcp(El - Es) : 1.0f;
-    T = ph.T_m;
-  } else {
-    fl = 1.0f;
-    T = ph.T_m + (rhoH - El) * rcp(Kliq);
-  }
+  // three branches (solid below E_s, liquid above E_l, mushy between; an
+  // empty mushy interval counts as liquid), evaluated without divergence
+  const bool sol = rhoH < Es, liq = !sol && rhoH > El;
+  const float fl_m = (El > Es) ? (rhoH - Es) * rcp(El - Es) : 1.0f;
+  const float fl = sol ? 0.0f : (liq ? 1.0f : fl_m);
+  const float T = sol ? rhoH * rcp(Ksol) : (liq ? ph.T_m + (rhoH - El) * rcp(Kliq) : ph.T_m);
   const float fs = chi * (1.0f - fl);
   const float fstot = fminf(1.0f, phi0 + fs);
   const float mdot = ph.mdot_coef * (fs - fs_prev);   // eq1, backward difference

@@ -23,31 +23,55 @@ struct StepShared {
   double red[WX / 64][NRED];
 };
 
-// Moments of node (xx, yy): pulled g and h, liquid weight, enthalpy map,
-// mass source, order parameter and density; the four stencil inputs are
-// returned in st[].
-__device__ __forceinline__ void node_moments(const Geo& G, const Phys& ph, const Bufs& B, int xx,
-                                             int yy, float* gv, float* hv, Mom& m, float& flux,
-                                             float& Qp, float& ref_h, float* st) {
-  pull_gh(G, ph, B, xx, yy, gv, hv, flux);
+// Everything a node's moments read from memory.
+struct NodeIn {
+  float g[9], h[9];
+  float flux, fsp, Qp, phi0, ghi, hhi, pprev;
+};
+
+__device__ __forceinline__ void node_load(const Geo& G, const Phys& ph, const Bufs& B, int xx,
+                                          int yy, NodeIn& in) {
+  in.flux = 0.0f;
+  pull_gh(G, ph, B, xx, yy, in.g, in.h, in.flux);
+  const int k = yy * G.nx + xx;
+  in.fsp = ldp(B.lin, LAG_FS, G.P, k);
+  in.Qp = ldp(B.lin, LAG_Q, G.P, k);
+  in.phi0 = ldp(B.stat, ST_PHI0, G.P, k);
+  in.ghi = ldp(B.lin, LAG_GHI, G.P, k);
+  in.hhi = ldp(B.lin, LAG_HHI, G.P, k);
+  in.pprev = ldp(B.lin, LAG_P, G.P, k);
+}
+
+// Moments of a loaded node: liquid weight, enthalpy map, mass source, order
+// parameter and density; the four stencil inputs are returned in st[].
+__device__ __forceinline__ void node_finish(const Phys& ph, const NodeIn& in, Mom& m, float* st) {
   // sums of the small stored values first (rest populations are deviations)
-  float sg = gv[0], shh = hv[0];
+  float sg = in.g[0], shh = in.h[0];
 #pragma unroll
   for (int i = 1; i < 9; ++i) {
-    sg += gv[i];
-    shh += hv[i];
+    sg += in.g[i];
+    shh += in.h[i];
   }
-  const int k = yy * G.nx + xx;
-  const float fsp = ldp(B.lin, LAG_FS, G.P, k);
-  Qp = ldp(B.lin, LAG_Q, G.P, k);
-  const float phi0 = ldp(B.stat, ST_PHI0, G.P, k);
-  const float ref_g = ldp(B.lin, LAG_GHI, G.P, k);
-  ref_h = ldp(B.lin, LAG_HHI, G.P, k);
-  moments(ph, ref_g, sg, ref_h, shh, fsp, Qp, phi0, m);
+  moments(ph, in.ghi, sg, in.hhi, shh, in.fsp, in.Qp, in.phi0, m);
   st[0] = m.phi;
   st[1] = m.fs;
   st[2] = m.rho;
-  st[3] = ldp(B.lin, LAG_P, G.P, k);
+  st[3] = in.pprev;
+}
+
+// Flow populations and node data the collision reads.
+struct FlowIn {
+  float f[9];
+  float cth, lap0, jxp, jyp;
+};
+
+__device__ __forceinline__ void flow_load(const Geo& G, const Bufs& B, int x, int y, FlowIn& in) {
+  pull_f(G, B, x, y, in.f);
+  const int k = y * G.nx + x;
+  in.cth = ldp(B.stat, ST_CTH, G.P, k);
+  in.lap0 = ldp(B.stat, ST_LAP0, G.P, k);
+  in.jxp = ldp(B.lin, LAG_JX, G.P, k);
+  in.jyp = ldp(B.lin, LAG_JY, G.P, k);
 }
 
 // One strip (bx, by) of the lattice.  MODE_STEP writes the next state;
@@ -55,7 +79,8 @@ __device__ __forceinline__ void node_moments(const Geo& G, const Phys& ph, const
 // per-block FP64 partial sums go to `red_out` (NRED doubles).
 template <int WX, int MODE, bool RED, bool RECOMP>
 __device__ __forceinline__ void step_strip(const Geo& G, const Phys& ph, const Bufs& B, int bx,
-                                           int by, int CY, double* red_out, StepShared<WX>& sh) {
+                                           int by, int CY, int dir, double* red_out,
+                                           StepShared<WX>& sh) {
   const int l = threadIdx.x;
   const int x0 = bx * WX;
   const int x = x0 + l;
@@ -64,6 +89,7 @@ __device__ __forceinline__ void step_strip(const Geo& G, const Phys& ph, const B
   const int y0 = by * CY;
   const int y1 = min(y0 + CY, G.ny);
   const int P = G.P;
+  (void)RECOMP;
 
   double a_sg = 0, a_sh = 0, a_fs = 0, a_liq = 0, a_umax = 0, a_bad = 0;
   double a_sphi = 0, a_heat = 0, a_flux = 0, a_reset = 0;
@@ -75,27 +101,38 @@ __device__ __forceinline__ void step_strip(const Geo& G, const Phys& ph, const B
     const int nh = 2 * (y1 - y0 + 2);
     for (int t = l; t < nh; t += WX) {
       const int side = t & 1, r = t >> 1;
-      float gv[9], hv[9], fl = 0.0f, q, rh, st[4];
+      NodeIn in;
       Mom m;
-      node_moments(G, ph, B, side ? xr : xl, map_axis(y0 - 1 + r, G.ny, G.py), gv, hv, m, fl,
-                   q, rh, st);
+      float st[4];
+      node_load(G, ph, B, side ? xr : xl, map_axis(y0 - 1 + r, G.ny, G.py), in);
+      node_finish(ph, in, m, st);
 #pragma unroll
       for (int f = 0; f < 4; ++f) sh.halo[f][side][r] = st[f];
     }
   }
 
-  float cg[9], ch[9], cflux = 0.0f, cQp = 0.0f, crh = 0.0f;
+  // March from ys in direction dir (+1 up, -1 down).  Software pipeline:
+  // the populations of the row two ahead and the flow populations of the
+  // next row are requested one iteration before they are used.
+  const int ys = dir > 0 ? y0 : y1 - 1;
+  const int nrow = y1 - y0;
+  NodeIn cin, ain;   // current row; row ahead (in flight)
+  FlowIn fin;        // flow data of the current row (in flight)
   Mom cm;
-  // own columns of rows y0 - 1 (halo row) and y0
   if (act) {
-    float gv[9], hv[9], fl = 0.0f, q, rh, st[4];
+    NodeIn bin;
     Mom m;
-    node_moments(G, ph, B, x, map_axis(y0 - 1, G.ny, G.py), gv, hv, m, fl, q, rh, st);
+    float st[4];
+    node_load(G, ph, B, x, map_axis(ys - dir, G.ny, G.py), bin);
+    node_load(G, ph, B, x, ys, cin);
+    node_load(G, ph, B, x, map_axis(ys + dir, G.ny, G.py), ain);
+    flow_load(G, B, x, ys, fin);
+    node_finish(ph, bin, m, st);
 #pragma unroll
-    for (int f = 0; f < 4; ++f) sh.v[f][(y0 + 3) & 3][l + 1] = st[f];
-    node_moments(G, ph, B, x, y0, cg, ch, cm, cflux, cQp, crh, st);
+    for (int f = 0; f < 4; ++f) sh.v[f][(ys - dir) & 3][l + 1] = st[f];
+    node_finish(ph, cin, cm, st);
 #pragma unroll
-    for (int f = 0; f < 4; ++f) sh.v[f][y0 & 3][l + 1] = st[f];
+    for (int f = 0; f < 4; ++f) sh.v[f][ys & 3][l + 1] = st[f];
   }
   __syncthreads();
   // lane 0 places the left halo column, the last active lane the right one
@@ -103,38 +140,37 @@ __device__ __forceinline__ void step_strip(const Geo& G, const Phys& ph, const B
   if (l == 0) {
 #pragma unroll
     for (int f = 0; f < 4; ++f) {
-      sh.v[f][(y0 + 3) & 3][0] = sh.halo[f][0][0];
-      sh.v[f][y0 & 3][0] = sh.halo[f][0][1];
+      sh.v[f][(ys - dir) & 3][0] = sh.halo[f][0][ys - dir - (y0 - 1)];
+      sh.v[f][ys & 3][0] = sh.halo[f][0][ys - (y0 - 1)];
     }
   }
   if (l == lastl) {
 #pragma unroll
     for (int f = 0; f < 4; ++f) {
-      sh.v[f][(y0 + 3) & 3][lastl + 2] = sh.halo[f][1][0];
-      sh.v[f][y0 & 3][lastl + 2] = sh.halo[f][1][1];
+      sh.v[f][(ys - dir) & 3][lastl + 2] = sh.halo[f][1][ys - dir - (y0 - 1)];
+      sh.v[f][ys & 3][lastl + 2] = sh.halo[f][1][ys - (y0 - 1)];
     }
   }
 
-  for (int y = y0; y < y1; ++y) {
-    // moments of the row above, one iteration ahead (with RECOMP only its
-    // stencil inputs are kept; the row's own moments are recomputed when it
-    // collides, trading L2 re-reads for registers)
-    float ng[9], nh[9], nflux = 0.0f, nQp = 0.0f, nrh = 0.0f;
-    Mom nm;
-    const int slot_n = (y + 1) & 3;
+  for (int it = 0; it < nrow; ++it) {
+    const int y = ys + it * dir;
+    const int ya = y + dir;
+    const int slot_n = ya & 3;
+    const bool more = it + 1 < nrow;
+    // moments of the row ahead from the data requested last iteration, then
+    // the request for the row after it
+    Mom am;
+    NodeIn next_c;
     if (act) {
       float st[4];
-      node_moments(G, ph, B, x, map_axis(y + 1, G.ny, G.py), ng, nh, nm, nflux, nQp, nrh, st);
+      node_finish(ph, ain, am, st);
 #pragma unroll
       for (int f = 0; f < 4; ++f) sh.v[f][slot_n][l + 1] = st[f];
-    }
-    if (RECOMP && act && y > y0) {
-      float st[4];
-      cflux = 0.0f;
-      node_moments(G, ph, B, x, y, cg, ch, cm, cflux, cQp, crh, st);
+      next_c = ain;
+      if (more) node_load(G, ph, B, x, map_axis(ya + dir, G.ny, G.py), ain);
     }
     if (l == 0 || l == lastl) {
-      const int r = y + 1 - (y0 - 1);
+      const int r = ya - (y0 - 1);
 #pragma unroll
       for (int f = 0; f < 4; ++f) {
         if (l == 0) sh.v[f][slot_n][0] = sh.halo[f][0][r];
@@ -145,7 +181,7 @@ __device__ __forceinline__ void step_strip(const Geo& G, const Phys& ph, const B
     if (act) {
       const int k = y * G.nx + x;
       Stencil S;
-      const int sm1 = (y + 3) & 3, s0 = y & 3, sp1 = (y + 1) & 3;
+      const int sm1 = (y - 1) & 3, s0 = y & 3, sp1 = (y + 1) & 3;
 #pragma unroll
       for (int i = 0; i < 9; ++i) {
         const int slot = cy(i) == 0 ? s0 : (cy(i) > 0 ? sp1 : sm1);
@@ -155,29 +191,26 @@ __device__ __forceinline__ void step_strip(const Geo& G, const Phys& ph, const B
         S.rho[i] = sh.v[2][slot][col];
         S.p[i] = sh.v[3][slot][col];
       }
-      float fv[9];
-      pull_f(G, B, x, y, fv);
-      const float phi0 = ldp(B.stat, ST_PHI0, P, k);
-      const float cth = ldp(B.stat, ST_CTH, P, k);
-      const float lap0 = ldp(B.stat, ST_LAP0, P, k);
-      const float jxp = ldp(B.lin, LAG_JX, P, k);
-      const float jyp = ldp(B.lin, LAG_JY, P, k);
+      float* fv = fin.f;
+      float* cg = cin.g;
+      float* ch = cin.h;
+      const float phi0 = cin.phi0, cQp = cin.Qp, crh = cin.hhi;
       if (RED) {
-        // node totals: reference plus the small stored sums
         a_sg += (double)cm.ref_g + (double)cm.sg;
         a_sh += (double)crh + (double)cm.sh;
-        a_flux += cflux;
+        a_flux += cin.flux;
         a_fs += cm.fs;
         a_liq += cm.chi - cm.fs;
       }
       Post o;
       if (MODE == MODE_STEP) {
-        collide_node<true>(ph, cm, S, phi0, cth, lap0, cQp, jxp, jyp, crh, fv, cg, ch, o);
+        collide_node<true>(ph, cm, S, phi0, fin.cth, fin.lap0, cQp, fin.jxp, fin.jyp, crh, fv, cg,
+                           ch, o);
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
-          stp(B.dout, i, P, k, fv[i]);
-          stp(B.dout, 9 + i, P, k, cg[i]);
-          stp(B.dout, 18 + i, P, k, ch[i]);
+          stp(B.fout, i, P, k, fv[i]);
+          stp(B.gout, i, P, k, cg[i]);
+          stp(B.hout, i, P, k, ch[i]);
         }
         stp(B.lout, LAG_FS, P, k, cm.fs);
         stp(B.lout, LAG_Q, P, k, o.Q);
@@ -192,8 +225,8 @@ __device__ __forceinline__ void step_strip(const Geo& G, const Phys& ph, const B
           a_reset += o.reset;
         }
       } else {
-        collide_node<false>(ph, cm, S, phi0, cth, lap0, cQp, jxp, jyp, crh, fv, cg, ch, o);
-        const float sg = cm.ref_g + cm.sg;
+        collide_node<false>(ph, cm, S, phi0, fin.cth, fin.lap0, cQp, fin.jxp, fin.jyp, crh, fv,
+                            cg, ch, o);
         stp(B.fields, 0, P, k, cm.phi);
         stp(B.fields, 1, P, k, cm.T);
         stp(B.fields, 2, P, k, 1.0f - cm.fs);
@@ -206,25 +239,17 @@ __device__ __forceinline__ void step_strip(const Geo& G, const Phys& ph, const B
         stp(B.fields, 9, P, k, cm.C);
         stp(B.fields, 10, P, k, cm.chi);
         stp(B.fields, 11, P, k, cm.rho);
-        stp(B.fields, 12, P, k, sg);
+        stp(B.fields, 12, P, k, cm.ref_g + cm.sg);
       }
       if (RED) {
         const float um = sqrtf(o.ux * o.ux + o.uy * o.uy);
         a_umax = fmax(a_umax, (double)um);
         if (!isfinite(cm.phi) || !isfinite(cm.T) || !isfinite(um) || !isfinite(o.p)) a_bad += 1;
       }
-    }
-    if (!RECOMP) {
-      // rotate the row registers
-#pragma unroll
-      for (int i = 0; i < 9; ++i) {
-        cg[i] = ng[i];
-        ch[i] = nh[i];
-      }
-      cm = nm;
-      cflux = nflux;
-      cQp = nQp;
-      crh = nrh;
+      // request the next row's flow data; rotate the row registers
+      if (more) flow_load(G, B, x, ya, fin);
+      cin = next_c;
+      cm = am;
     }
   }
 
@@ -261,15 +286,28 @@ __device__ __forceinline__ void step_strip(const Geo& G, const Phys& ph, const B
 #define LBF_WAVES 2
 #endif
 
-// Single-lattice step kernel: grid (ceil(nx / WX), ceil(ny / CY)).
+// Tile of a workgroup: workgroups are dealt to the 8 XCDs round-robin, so
+// workgroup w runs on XCD w % 8; tiles are handed out so that each XCD
+// owns a contiguous band of ntiles / 8 tiles (row-major: strips side by side,
+// then up the lattice), keeping the columns and rows that neighbouring
+// strips share inside one L2.
+__device__ __forceinline__ int xcd_tile(int w, int ntiles) {
+  const int xcd = w & 7, local = w >> 3;
+  return xcd * (ntiles >> 3) + min(xcd, ntiles & 7) + local;
+}
+
+// Single-lattice step kernel: 1D grid of nbx * nby workgroups.  Strips in
+// even tile rows march up, odd ones down, so two strips that share halo rows
+// reach them at the same time.
 template <int WX, int MODE, bool RED>
 __global__ __launch_bounds__(WX) __attribute__((amdgpu_waves_per_eu(LBF_WAVES, 8))) void
-step_kernel(Geo G, Phys ph, BufArgs A, int CY) {
+step_kernel(Geo G, Phys ph, BufArgs A, int CY, int nbx, int ntiles) {
   __shared__ StepShared<WX> sh;
   const Bufs B = make_bufs(A, G.P);
-  const int bx = blockIdx.x, by = blockIdx.y;
-  double* red = RED ? A.red + (size_t)(by * gridDim.x + bx) * NRED : nullptr;
-  step_strip<WX, MODE, RED, LBF_RECOMP != 0>(G, ph, B, bx, by, CY, red, sh);
+  const int t = xcd_tile(blockIdx.x, ntiles);
+  const int bx = t % nbx, by = t / nbx;
+  double* red = RED ? A.red + (size_t)t * NRED : nullptr;
+  step_strip<WX, MODE, RED, LBF_RECOMP != 0>(G, ph, B, bx, by, CY, (by & 1) ? -1 : 1, red, sh);
 }
 
 }  // namespace lbf
