@@ -37,6 +37,8 @@ def parse():
     ap.add_argument("--tile", type=str, default="", help="TXxTY, e.g. 128x32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--batch-steps", type=int, default=320,
+                    help="steps of the 64-lattice batched workload (0 skips it)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run an elementwise copy of MIB MiB (read + write), the "
                          "reference kernel for scaling HBM byte counters")
@@ -61,6 +63,44 @@ def cpu_baseline(case, seconds):
     return {"value": case.nodes * steps / dt / 1e6, "unit": "MLUPS", "cores": threads,
             "kind": "oracle",
             "sample": f"{steps} whole-lattice FP64 steps of {case.name} ({dt:.1f} s)"}
+
+
+def batched(lbf, W, torch, steps):
+    """64 uneven droplet lattices: one persistent launch per step (graph
+    replays) against the same lattices stepped one after another with their
+    own launches."""
+    from paper_2510_18688_amd import autotune
+    cases = W.batch_instances(64, seed=4)
+    nodes = sum(c.nodes for c in cases)
+    sims = [lbf.Sim(c) for c in cases]
+    for s, c in zip(sims, cases):
+        t = autotune.lookup(c.nx, c.ny)
+        if t:
+            s.set_tile(*t)
+    tile = autotune.lookup_batch(len(cases), nodes) or (128, 32)
+    batch = lbf.Batch(sims, tile=tile)
+    batch.step(64)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    batch.step(steps)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    for s in sims:
+        s.step(8)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in sims:
+        s.step(steps)
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - t0
+    red = [s.reduce(check_stable=False) for s in sims[:3]]
+    return {"workload": "64 droplet lattices, sides log-uniform in [64, 512]",
+            "lattices": len(cases), "nodes": nodes, "steps": steps,
+            "tile": f"{tile[0]}x{tile[1]}", "work_items": batch.items(),
+            "batched_mlups": round(nodes * steps / tb / 1e6, 1),
+            "serial_mlups": round(nodes * steps / ts / 1e6, 1),
+            "speedup": round(ts / tb, 2),
+            "nonfinite": sum(r["nonfinite"] for r in red)}
 
 
 def main():
@@ -133,6 +173,9 @@ def main():
                      "kernel_ms": round(kms, 5), "bytes_per_lu": BYTES_PER_LU},
         "checks": {"nonfinite": red["nonfinite"], "umax": red["umax"]},
     }
+    if args.batch_steps > 0:
+        del sim
+        out["batched"] = batched(lbf, W, torch, args.batch_steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(case, args.cpu_seconds)
     print(json.dumps(out), flush=True)

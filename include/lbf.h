@@ -185,6 +185,41 @@ double lbf_last_step_kernel_ms(const lbf_sim* sim);
 const char* lbf_last_error(void);
 void lbf_destroy(lbf_sim* sim);
 
+/* ---- batches: many lattices advanced by one persistent launch per step ----
+ * A batch groups n initialised simulations that share one HIP stream (the
+ * simulations stay owned by the caller and must outlive the batch).  Each
+ * step is one launch of a fixed grid (two workgroups per compute unit) that
+ * walks the work list of every lattice's tiles; runs of 32 steps are
+ * captured once in a HIP graph and replayed.  Every lattice is advanced
+ * exactly as lbf_step would advance it (same arithmetic, bit-identical
+ * states).  Budget tracking (the step budget entries of lbf_reduce) is not
+ * kept for batched steps. */
+typedef struct lbf_batch lbf_batch;
+
+/* Rejects (LBF_EINVAL) empty batches, NULL or repeated simulations and
+ * simulations on different streams; LBF_ESTATE if one is not initialised. */
+int lbf_batch_create(lbf_sim* const* sims, int32_t n, lbf_batch** out);
+
+/* Tile shape shared by every lattice of the batch (tile_x in {64, 128, 256},
+ * 1 <= tile_y <= 256); the default is 128 x 32. */
+int lbf_batch_set_tile(lbf_batch* batch, int32_t tile_x, int32_t tile_y);
+
+/* Advance every lattice of the batch by nsteps (asynchronous unless timing
+ * is on).  A simulation stepped on its own in between is picked up at its
+ * current state. */
+int lbf_batch_step(lbf_batch* batch, int32_t nsteps);
+
+/* With timing on, lbf_batch_step brackets its launches with HIP events and
+ * lbf_batch_last_step_ms returns the average milliseconds per step. */
+int lbf_batch_set_timing(lbf_batch* batch, int32_t on);
+double lbf_batch_last_step_ms(const lbf_batch* batch);
+
+/* Number of (lattice, tile) work items of the current tile shape (0 before
+ * the first step). */
+int32_t lbf_batch_items(const lbf_batch* batch);
+
+void lbf_batch_destroy(lbf_batch* batch);
+
 #ifdef __cplusplus
 }
 #endif

@@ -658,3 +658,241 @@ int lbf_set_timing(lbf_sim* s, int32_t on) {
 double lbf_last_step_kernel_ms(const lbf_sim* s) { return s ? s->last_ms : 0.0; }
 
 }  // extern "C"
+
+// ================================================================ batch
+struct lbf_batch {
+  std::vector<lbf_sim*> sims;
+  hipStream_t stream;
+  int tile_x, tile_y;
+  int grid;                      // persistent workgroups
+  InstDesc* d_desc;
+  int2* d_items;
+  int nitems;
+  std::vector<InstDesc> h_desc;  // host copy (source of the uploads)
+  std::vector<int> desc_cur;     // sims' parity the descriptors were built for
+  bool built;                    // work list, grid and graph match the tile shape
+  hipGraphExec_t graph;          // kGraphSteps launches, parities alternating
+  bool have_graph;
+  hipStream_t capture;           // private stream the graph is recorded on (the
+                                 // legacy default stream cannot be captured)
+  bool timing;
+  double last_ms;
+  hipEvent_t ev0, ev1;
+};
+
+namespace {
+
+constexpr int kGraphSteps = 32;
+
+void batch_free_graph(lbf_batch* b) {
+  if (b->have_graph) (void)hipGraphExecDestroy(b->graph);
+  b->have_graph = false;
+}
+
+// Descriptors for the sims' current parities (A[0] steps the current state).
+int batch_upload_desc(lbf_batch* b) {
+  const int n = (int)b->sims.size();
+  b->h_desc.assign(n, InstDesc{});
+  for (int i = 0; i < n; ++i) {
+    lbf_sim* s = b->sims[i];
+    InstDesc& d = b->h_desc[i];
+    d.G = s->G;
+    d.ph = s->ph;
+    for (int p = 0; p < 2; ++p) {
+      const int c = s->cur ^ p;
+      BufArgs A{};
+      A.din = fptr(s, s->L.dist[c]);
+      A.dout = fptr(s, s->L.dist[1 - c]);
+      A.lin = fptr(s, s->L.lag[c]);
+      A.lout = fptr(s, s->L.lag[1 - c]);
+      A.stat = fptr(s, s->L.stat);
+      A.wallT = fptr(s, s->L.wall);
+      A.wstride = s->L.wstride;
+      d.A[p] = A;
+    }
+    d.CY = b->tile_y;
+    d.nbx = (s->G.nx + b->tile_x - 1) / b->tile_x;
+    b->desc_cur[i] = s->cur;
+  }
+  HIP_TRY(hipMemcpyAsync(b->d_desc, b->h_desc.data(), n * sizeof(InstDesc),
+                         hipMemcpyHostToDevice, b->stream));
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  return LBF_OK;
+}
+
+// Work list (tiles of every lattice, larger lattices first) and grid for the
+// current tile shape.
+int batch_build(lbf_batch* b) {
+  const int n = (int)b->sims.size();
+  std::vector<int> order(n);
+  for (int i = 0; i < n; ++i) order[i] = i;
+  std::sort(order.begin(), order.end(), [&](int a, int c) {
+    return (long long)b->sims[a]->G.nx * b->sims[a]->G.ny >
+           (long long)b->sims[c]->G.nx * b->sims[c]->G.ny;
+  });
+  std::vector<int2> items;
+  for (int i : order) {
+    const int nbx = (b->sims[i]->G.nx + b->tile_x - 1) / b->tile_x;
+    const int nby = (b->sims[i]->G.ny + b->tile_y - 1) / b->tile_y;
+    for (int t = 0; t < nbx * nby; ++t) items.push_back(make_int2(i, t));
+  }
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  batch_free_graph(b);
+  if (b->d_items) (void)hipFree(b->d_items);
+  b->d_items = nullptr;
+  if (!b->d_desc) HIP_TRY(hipMalloc((void**)&b->d_desc, n * sizeof(InstDesc)));
+  HIP_TRY(hipMalloc((void**)&b->d_items, items.size() * sizeof(int2)));
+  HIP_TRY(hipMemcpyAsync(b->d_items, items.data(), items.size() * sizeof(int2),
+                         hipMemcpyHostToDevice, b->stream));
+  b->nitems = (int)items.size();
+  int dev = 0, ncu = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  // two workgroups per CU, never many more than there are items
+  b->grid = std::max(8, std::min(2 * ncu, (b->nitems + 7) / 8 * 8));
+  b->grid = (b->grid + 7) / 8 * 8;
+  b->built = true;
+  return batch_upload_desc(b);
+}
+
+template <int WX>
+void batch_launch_wx(lbf_batch* b, int parity, hipStream_t st) {
+  hipLaunchKernelGGL((batch_step_kernel<WX>), dim3(b->grid), dim3(WX), 0, st,
+                     (const InstDesc*)b->d_desc, (const int2*)b->d_items, b->nitems, parity);
+}
+
+int batch_launch(lbf_batch* b, int parity, hipStream_t st) {
+  switch (b->tile_x) {
+    case 64: batch_launch_wx<64>(b, parity, st); break;
+    case 128: batch_launch_wx<128>(b, parity, st); break;
+    default: batch_launch_wx<256>(b, parity, st); break;
+  }
+  HIP_TRY(hipGetLastError());
+  return LBF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbf_batch_create(lbf_sim* const* sims, int32_t n, lbf_batch** out) {
+  if (!out) return fail(LBF_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!sims || n < 1) return fail(LBF_EINVAL, "a batch needs at least one simulation");
+  for (int i = 0; i < n; ++i) {
+    if (!sims[i]) return fail(LBF_EINVAL, "simulation %d is NULL", i);
+    if (!sims[i]->have_init) return fail(LBF_ESTATE, "simulation %d is not initialised", i);
+    if (sims[i]->stream != sims[0]->stream)
+      return fail(LBF_EINVAL, "all simulations of a batch must share one stream");
+    for (int j = 0; j < i; ++j)
+      if (sims[j] == sims[i]) return fail(LBF_EINVAL, "simulation %d appears twice", i);
+  }
+  lbf_batch* b = new lbf_batch();
+  b->sims.assign(sims, sims + n);
+  b->desc_cur.assign(n, -1);
+  b->stream = sims[0]->stream;
+  b->tile_x = 128;
+  b->tile_y = 32;
+  if (hipEventCreate(&b->ev0) != hipSuccess || hipEventCreate(&b->ev1) != hipSuccess ||
+      hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking) != hipSuccess) {
+    lbf_batch_destroy(b);
+    return fail(LBF_EHIP, "event / stream creation failed");
+  }
+  *out = b;
+  return LBF_OK;
+}
+
+int lbf_batch_set_tile(lbf_batch* b, int32_t tile_x, int32_t tile_y) {
+  if (!b) return fail(LBF_EINVAL, "batch is NULL");
+  if (tile_x != 64 && tile_x != 128 && tile_x != 256)
+    return fail(LBF_EINVAL, "tile_x must be 64, 128 or 256 (got %d)", tile_x);
+  if (tile_y < 1 || tile_y > CY_MAX)
+    return fail(LBF_EINVAL, "tile_y must be in [1, %d] (got %d)", CY_MAX, tile_y);
+  if (tile_x != b->tile_x || tile_y != b->tile_y) b->built = false;
+  b->tile_x = tile_x;
+  b->tile_y = tile_y;
+  return LBF_OK;
+}
+
+int lbf_batch_step(lbf_batch* b, int32_t nsteps) {
+  if (!b) return fail(LBF_EINVAL, "batch is NULL");
+  if (nsteps < 0) return fail(LBF_EINVAL, "nsteps %d", nsteps);
+  if (nsteps == 0) return LBF_OK;
+  if (!b->built) {
+    int rc = batch_build(b);
+    if (rc) return rc;
+  } else {
+    for (size_t i = 0; i < b->sims.size(); ++i)
+      if (b->sims[i]->cur != b->desc_cur[i]) {
+        int rc = batch_upload_desc(b);
+        if (rc) return rc;
+        break;
+      }
+  }
+  if (b->timing) HIP_TRY(hipEventRecord(b->ev0, b->stream));
+  int done = 0;
+  if (nsteps >= kGraphSteps) {
+    if (!b->have_graph) {
+      // one graph of kGraphSteps persistent launches, parities alternating
+      hipGraph_t g;
+      HIP_TRY(hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal));
+      for (int k = 0; k < kGraphSteps; ++k) {
+        int rc = batch_launch(b, k & 1, b->capture);
+        if (rc) {
+          (void)hipStreamEndCapture(b->capture, &g);
+          return rc;
+        }
+      }
+      HIP_TRY(hipStreamEndCapture(b->capture, &g));
+      HIP_TRY(hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0));
+      HIP_TRY(hipGraphDestroy(g));
+      b->have_graph = true;
+    }
+    // kGraphSteps is even: each replay leaves every parity where it started
+    while (nsteps - done >= kGraphSteps) {
+      HIP_TRY(hipGraphLaunch(b->graph, b->stream));
+      done += kGraphSteps;
+    }
+  }
+  for (int k = 0; done < nsteps; ++k, ++done) {
+    int rc = batch_launch(b, k & 1, b->stream);
+    if (rc) return rc;
+  }
+  if (b->timing) {
+    HIP_TRY(hipEventRecord(b->ev1, b->stream));
+    HIP_TRY(hipEventSynchronize(b->ev1));
+    float ms = 0.0f;
+    HIP_TRY(hipEventElapsedTime(&ms, b->ev0, b->ev1));
+    b->last_ms = ms / nsteps;
+  }
+  for (lbf_sim* s : b->sims) {
+    s->cur ^= nsteps & 1;
+    s->step += nsteps;
+    s->have_budget = false;
+  }
+  return LBF_OK;
+}
+
+int lbf_batch_set_timing(lbf_batch* b, int32_t on) {
+  if (!b) return fail(LBF_EINVAL, "batch is NULL");
+  b->timing = on != 0;
+  return LBF_OK;
+}
+
+double lbf_batch_last_step_ms(const lbf_batch* b) { return b ? b->last_ms : 0.0; }
+
+int32_t lbf_batch_items(const lbf_batch* b) { return b && b->built ? b->nitems : 0; }
+
+void lbf_batch_destroy(lbf_batch* b) {
+  if (!b) return;
+  (void)hipStreamSynchronize(b->stream);
+  batch_free_graph(b);
+  if (b->d_desc) (void)hipFree(b->d_desc);
+  if (b->d_items) (void)hipFree(b->d_items);
+  if (b->ev0) (void)hipEventDestroy(b->ev0);
+  if (b->ev1) (void)hipEventDestroy(b->ev1);
+  if (b->capture) (void)hipStreamDestroy(b->capture);
+  delete b;
+}
+
+}  // extern "C"

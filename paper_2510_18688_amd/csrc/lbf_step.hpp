@@ -311,3 +311,43 @@ step_kernel(Geo G, Phys ph, BufArgs A, int CY, int nbx, int ntiles) {
 }
 
 }  // namespace lbf
+
+namespace lbf {
+
+// One lattice of a batch: geometry, constants, and its buffers for both
+// ping-pong parities (A[p] steps the state that parity p reads).
+struct InstDesc {
+  Geo G;
+  Phys ph;
+  BufArgs A[2];
+  int CY, nbx;
+};
+
+// Persistent batched step: a fixed grid walks the work list of (instance,
+// tile) items of every lattice of the batch.  In round r workgroup b takes
+// item r * gridDim.x + xcd_tile(b, gridDim.x), so each XCD receives a
+// contiguous run of items (neighbouring tiles of one lattice) per round.
+template <int WX>
+__global__ __launch_bounds__(WX) __attribute__((amdgpu_waves_per_eu(LBF_WAVES, 8))) void
+batch_step_kernel(const InstDesc* __restrict__ D, const int2* __restrict__ items, int nitems,
+                  int parity) {
+  __shared__ StepShared<WX> sh;
+  const int G = gridDim.x;
+  const int slot = xcd_tile(blockIdx.x, G);
+  for (int base = 0; base < nitems; base += G) {
+    const int w = base + slot;
+    if (w >= nitems) break;
+    const int2 item = items[w];
+    const Geo geo = D[item.x].G;
+    const Phys ph = D[item.x].ph;
+    const BufArgs args = D[item.x].A[parity];
+    const int CY = D[item.x].CY, nbx = D[item.x].nbx;
+    const Bufs B = make_bufs(args, geo.P);
+    const int bx = item.y % nbx, by = item.y / nbx;
+    __syncthreads();   // the LDS ring of the previous item is free
+    step_strip<WX, MODE_STEP, false, false>(geo, ph, B, bx, by, CY, (by & 1) ? -1 : 1, nullptr,
+                                            sh);
+  }
+}
+
+}  // namespace lbf

@@ -25,7 +25,9 @@ EXPORTS = ["lbf_workspace_bytes", "lbf_create", "lbf_set_geometry", "lbf_set_wal
            "lbf_init_fields", "lbf_step", "lbf_read_field", "lbf_read_fields", "lbf_reduce",
            "lbf_set_poststream_state", "lbf_set_tile", "lbf_get_tile", "lbf_state_bytes", "lbf_save_state",
            "lbf_load_state", "lbf_set_timing", "lbf_last_step_kernel_ms", "lbf_last_error",
-           "lbf_destroy"]
+           "lbf_destroy", "lbf_batch_create", "lbf_batch_set_tile", "lbf_batch_step",
+           "lbf_batch_set_timing", "lbf_batch_last_step_ms", "lbf_batch_items",
+           "lbf_batch_destroy"]
 
 ERRORS = {-1: "LBF_EINVAL", -2: "LBF_EHIP", -3: "LBF_ESTATE", -4: "LBF_EUNSTABLE",
           -5: "LBF_ENOMEM"}
@@ -86,6 +88,15 @@ def load(path: str = LIB_PATH):
     L.lbf_last_step_kernel_ms.argtypes = [vp]
     L.lbf_last_error.restype = C.c_char_p
     L.lbf_destroy.argtypes = [vp]
+    L.lbf_batch_create.argtypes = [C.POINTER(vp), i32, C.POINTER(vp)]
+    L.lbf_batch_set_tile.argtypes = [vp, i32, i32]
+    L.lbf_batch_step.argtypes = [vp, i32]
+    L.lbf_batch_set_timing.argtypes = [vp, i32]
+    L.lbf_batch_last_step_ms.restype = C.c_double
+    L.lbf_batch_last_step_ms.argtypes = [vp]
+    L.lbf_batch_items.restype = i32
+    L.lbf_batch_items.argtypes = [vp]
+    L.lbf_batch_destroy.argtypes = [vp]
     for name in EXPORTS:
         getattr(L, name)
     _lib = L
@@ -252,3 +263,47 @@ class Sim:
 
     def load_state(self, buf) -> None:
         check(_lib.lbf_load_state(self.h, C.c_void_p(buf.data_ptr()), buf.numel() * buf.element_size()))
+
+
+class Batch:
+    """Many lattices advanced together by one persistent launch per step."""
+
+    def __init__(self, sims: Sequence[Sim], tile: Optional[Sequence[int]] = None):
+        L = load()
+        self.sims = list(sims)
+        arr = (C.c_void_p * len(self.sims))(*[s.h.value for s in self.sims])
+        h = C.c_void_p()
+        check(L.lbf_batch_create(arr, len(self.sims), C.byref(h)))
+        self.h = h
+        if tile is not None:
+            self.set_tile(*tile)
+
+    def set_tile(self, tx: int, ty: int) -> None:
+        check(_lib.lbf_batch_set_tile(self.h, int(tx), int(ty)))
+
+    def step(self, n: int = 1) -> None:
+        check(_lib.lbf_batch_step(self.h, int(n)))
+
+    def set_timing(self, on: bool) -> None:
+        check(_lib.lbf_batch_set_timing(self.h, int(bool(on))))
+
+    def last_step_ms(self) -> float:
+        return float(_lib.lbf_batch_last_step_ms(self.h))
+
+    def items(self) -> int:
+        return int(_lib.lbf_batch_items(self.h))
+
+    @property
+    def nodes(self) -> int:
+        return sum(s.nx * s.ny for s in self.sims)
+
+    def close(self) -> None:
+        if getattr(self, "h", None) is not None and self.h.value:
+            _lib.lbf_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

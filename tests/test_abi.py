@@ -91,6 +91,11 @@ def test_null_arguments(L):
     assert L.lbf_reduce(None, None) == -1
     assert L.lbf_read_field(None, 0, None, 0) == -1
     L.lbf_destroy(None)
+    out = C.c_void_p()
+    assert L.lbf_batch_create(None, 0, C.byref(out)) == -1
+    assert L.lbf_batch_step(None, 1) == -1
+    assert L.lbf_batch_set_tile(None, 64, 8) == -1
+    L.lbf_batch_destroy(None)
 
 
 def test_binding_refuses_without_device(monkeypatch):
