@@ -126,9 +126,12 @@ class Oracle:
         L.orc_init(self.h, *[_ptr(a) for a in self._keep])
 
     def __del__(self):
-        if getattr(self, "h", None):
-            lib().orc_destroy(self.h)
-            self.h = None
+        try:
+            if getattr(self, "h", None):
+                lib().orc_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
 
     def step(self, n: int = 1) -> None:
         lib().orc_step(self.h, int(n))

@@ -1,0 +1,82 @@
+"""Pins of the FP64 gradient oracle (no GPU).
+
+The PyTorch oracle recomputes the C oracle's discrete map with whole-lattice
+tensor operations; autograd then gives the exact gradient of a loss of the
+final ice fraction with respect to the per-node wettability cos(theta) and
+the wall temperatures, through the initialisation and every step.  Pinned
+by (1) agreement of its forward map with the C oracle to round-off and
+(2) FP64 central finite differences of the C oracle along random directions.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2510_18688_amd import workloads as W
+
+
+def small_freezing_case(nx=32, ny=24, hs=3.0, radius=8.0, Tw=-1.5):
+    """A drop on a thin diffuse slab over a cold wall: the cold front reaches
+    the drop within tens of steps, so the ice fraction depends on both
+    controls."""
+    case = W.slab_drop(nx, ny, radius, 75.0, Tw, h_s=hs)
+    rng = np.random.default_rng(1)
+    # per-column contact angles around 75 degrees
+    th = 75.0 + 10.0 * rng.uniform(-1, 1, nx)
+    case.cos_theta = np.broadcast_to(np.cos(np.radians(th))[None, :], (ny, nx)).copy()
+    case.wall_T = {W.BOTTOM: Tw + 0.2 * rng.uniform(-1, 1, nx)}
+    return case
+
+
+def test_torch_oracle_matches_c_oracle(oracle_mod):
+    from oracle import torch_oracle as TO
+    for case in (W.sessile_drop(nx=40, ny=30, radius=10.0),
+                 W.curved_substrate(n=64, R_s=14.0, R_0=10.0),
+                 W.porous_medium(nx=90, ny=60, seed=11, rmin=6.0, rmax=9.0, porosity=0.8),
+                 small_freezing_case()):
+        M, _, _, _ = TO.run(case, 40)
+        o = oracle_mod.Oracle(case)
+        o.step(40)
+        F = o.fields()
+        for k in ("phi", "T", "fs", "rhoH", "C", "chi", "rho"):
+            assert np.abs(M[k].detach().numpy() - F[k]).max() < 1e-12, (case.name, k)
+
+
+def loss_and_grads(case, steps, target):
+    from oracle import torch_oracle as TO
+    M, cth, wallT, _ = TO.run(case, steps, requires_grad=True)
+    J = 0.5 * ((M["fs"] - torch.from_numpy(target)) ** 2).sum()
+    J.backward()
+    return float(J.detach()), cth.grad.numpy().copy(), wallT.grad.numpy().copy()
+
+
+def oracle_loss(oracle_mod, case, steps, target):
+    o = oracle_mod.Oracle(case)
+    o.step(steps)
+    fs = o.fields()["fs"]
+    return 0.5 * float(((fs - target) ** 2).sum())
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_autograd_gradient_matches_central_differences(oracle_mod, seed):
+    case = small_freezing_case()
+    steps = 60
+    rng = np.random.default_rng(10 + seed)
+    target = 0.3 * rng.uniform(0, 1, (case.ny, case.nx))
+    J, g_cth, g_wall = loss_and_grads(case, steps, target)
+    assert np.abs(g_cth).max() > 0 and np.abs(g_wall[0, :case.nx]).max() > 0
+    # random direction over the per-column contact angles and the bottom-wall profile
+    d_th = rng.normal(size=case.nx)
+    d_tw = rng.normal(size=case.nx)
+    d_th /= np.linalg.norm(d_th)
+    d_tw /= np.linalg.norm(d_tw)
+    analytic = float((g_cth * d_th[None, :]).sum() + (g_wall[0, :case.nx] * d_tw).sum())
+    eps = 1e-6
+    vals = []
+    for sgn in (1, -1):
+        c = small_freezing_case()
+        c.cos_theta = c.cos_theta + sgn * eps * d_th[None, :]
+        c.wall_T = {W.BOTTOM: c.wall_T[W.BOTTOM] + sgn * eps * d_tw}
+        vals.append(oracle_loss(oracle_mod, c, steps, target))
+    fd = (vals[0] - vals[1]) / (2 * eps)
+    assert abs(fd - analytic) <= 1e-5 * abs(fd) + 1e-9, (fd, analytic)
