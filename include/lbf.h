@@ -220,6 +220,55 @@ int32_t lbf_batch_items(const lbf_batch* batch);
 
 void lbf_batch_destroy(lbf_batch* batch);
 
+/* ---- reverse-mode differentiation (adjoint with checkpoint recomputation) ----
+ * A tape records a forward run of nsteps steps of one simulation and then
+ * returns the exact gradient of a scalar J of the final state's phi, T and
+ * f_s (the caller supplies dJ/dphi, dJ/dT, dJ/df_s per node) with respect to
+ * the per-node cos(theta) of the wetting term (eq44) and the Dirichlet wall
+ * temperatures of the anti-bounce-back rule.  This is the discrete adjoint
+ * of the coupled step (an extension beyond the paper): each step is reversed
+ * exactly, in FP32, with FP64 gradient accumulation; at non-smooth points
+ * (clamps, the phase-change latch maximum, the enthalpy-map branches) it
+ * takes the one-sided derivative of the branch the forward evaluated, a
+ * clamp passing the derivative on its closed interval and a tie of the
+ * maximum splitting it evenly.  When the recorded run starts from
+ * lbf_init_fields (step 0), the dependence of the initial phase-field
+ * equilibrium on cos(theta) is included; otherwise the starting state is
+ * held fixed.  The wall temperatures and geometry must not change between
+ * the forward run and the backward sweep. */
+typedef struct lbf_tape lbf_tape;
+
+/* Device bytes a tape allocates: ceil(nsteps / segment) stored states of
+ * 34 planes, `segment` recomputed states and their moments, and the adjoint
+ * work planes.  segment <= 0 selects ceil(sqrt(nsteps)). */
+size_t lbf_tape_bytes(int32_t nx, int32_t ny, int32_t nsteps, int32_t segment);
+
+/* Create a tape for `sim` (which must outlive it) recording nsteps >= 0
+ * steps with a checkpoint every `segment` steps (<= 0: ceil(sqrt(nsteps))).
+ * The tape owns its device memory (hipMalloc; LBF_ENOMEM on failure). */
+int lbf_tape_create(lbf_sim* sim, int32_t nsteps, int32_t segment, lbf_tape** out);
+
+/* The checkpoint interval in use. */
+int lbf_tape_segment(const lbf_tape* tape);
+
+/* Advance the simulation by the tape's nsteps, storing its state every
+ * segment steps (asynchronous on the simulation's stream). */
+int lbf_tape_forward(lbf_tape* tape);
+
+/* Reverse sweep after lbf_tape_forward, with the simulation still at the
+ * final state (LBF_ESTATE otherwise).  seed_phi, seed_T, seed_fs: dJ/d field
+ * at every node of the final state (nx * ny floats each, host or device per
+ * seeds_on_device; NULL means zero).  Outputs (host or device per
+ * grads_on_device, FP64): grad_cos_theta[nx * ny] = dJ/dcos(theta) per node;
+ * grad_wall_T[2 nx + 2 ny] = dJ/dT_w per wall node, bottom (nx, by x), top
+ * (nx), left (ny, by y), right (ny); zero on adiabatic walls.  Each segment
+ * is recomputed once from its checkpoint.  Synchronises the stream. */
+int lbf_tape_backward(lbf_tape* tape, const float* seed_phi, const float* seed_T,
+                      const float* seed_fs, int32_t seeds_on_device, double* grad_cos_theta,
+                      double* grad_wall_T, int32_t grads_on_device);
+
+void lbf_tape_destroy(lbf_tape* tape);
+
 #ifdef __cplusplus
 }
 #endif

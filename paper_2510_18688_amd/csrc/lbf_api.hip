@@ -11,11 +11,12 @@
 
 #include "lbf.h"
 #include "lbf_device.hpp"
+#include "lbf_sim.hpp"
 #include "lbf_step.hpp"
 
 using namespace lbf;
 
-namespace {
+namespace lbfi {
 
 thread_local std::string g_err;
 
@@ -28,32 +29,6 @@ int fail(int code, const char* fmt, ...) {
   g_err = buf;
   return code;
 }
-
-#define HIP_TRY(expr)                                                                 \
-  do {                                                                                \
-    hipError_t e_ = (expr);                                                           \
-    if (e_ != hipSuccess)                                                             \
-      return fail(LBF_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_));           \
-  } while (0)
-
-constexpr size_t kAlign = 256;
-
-size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
-
-// Plane stride: nx * ny rounded up to 64 floats (256 bytes).
-long long plane_stride(int nx, int ny) { return (long long)round_up((size_t)nx * ny, 64); }
-
-// Kernels address each block of planes with 32-bit byte offsets: the 27
-// distribution planes must span less than 4 GiB.
-constexpr long long kMaxPlane = (0xFFFFFFFFLL / (4LL * 27)) / 64 * 64;
-
-// Worst-case number of per-block partial sums: 64-wide strips, 1 row each.
-size_t max_blocks(int nx, int ny) { return ((size_t)(nx + 63) / 64) * (size_t)ny; }
-
-struct Layout {
-  size_t dist[2], lag[2], stat, fields, wall, red[2], redfinal, total;
-  int wstride;
-};
 
 Layout make_layout(int nx, int ny) {
   Layout L{};
@@ -80,32 +55,11 @@ Layout make_layout(int nx, int ny) {
   return L;
 }
 
-}  // namespace
+}  // namespace lbfi
 
-struct lbf_sim {
-  lbf_params prm;
-  Geo G;
-  Phys ph;
-  Layout L;
-  hipStream_t stream;
-  char* ws;
-  bool owns_ws;
-  int cur;           // which distribution / lag buffer holds the current state
-  bool have_geo, have_init;
-  int tile_x, tile_y;
-  long long step;
-  bool have_budget;  // red[0] holds the budget of the last step
-  int budget_blocks;
-  bool timing;
-  double last_ms;
-  hipEvent_t ev0, ev1;
-  double* host_red;  // pinned host buffer for reductions
-};
+using namespace lbfi;
 
 namespace {
-
-float* fptr(lbf_sim* s, size_t off) { return reinterpret_cast<float*>(s->ws + off); }
-double* dptr(lbf_sim* s, size_t off) { return reinterpret_cast<double*>(s->ws + off); }
 
 BufArgs make_args(lbf_sim* s) {
   BufArgs B{};
@@ -313,6 +267,9 @@ int launch_wx(lbf_sim* s, int mode, bool red, BufArgs B) {
   else if (mode == MODE_STEP && red)
     hipLaunchKernelGGL((step_kernel<WX, MODE_STEP, true>), grid, block, 0, s->stream, s->G,
                        s->ph, B, s->tile_y, nbx, nt);
+  else if (mode == MODE_STEP_MOM)
+    hipLaunchKernelGGL((step_kernel<WX, MODE_STEP_MOM, false>), grid, block, 0, s->stream, s->G,
+                       s->ph, B, s->tile_y, nbx, nt);
   else if (mode == MODE_FIELDS && !red)
     hipLaunchKernelGGL((step_kernel<WX, MODE_FIELDS, false>), grid, block, 0, s->stream, s->G,
                        s->ph, B, s->tile_y, nbx, nt);
@@ -326,6 +283,12 @@ int launch_wx(lbf_sim* s, int mode, bool red, BufArgs B) {
 int launch_step(lbf_sim* s, int mode, bool red, double* red_buf) {
   BufArgs B = make_args(s);
   B.red = red_buf;
+  return launch_step_args(s, mode, red, B);
+}
+
+}  // namespace
+
+int lbfi::launch_step_args(lbf_sim* s, int mode, bool red, BufArgs B) {
   switch (s->tile_x) {
     case 64: return launch_wx<64>(s, mode, red, B);
     case 128: return launch_wx<128>(s, mode, red, B);
@@ -333,6 +296,8 @@ int launch_step(lbf_sim* s, int mode, bool red, double* red_buf) {
     default: return fail(LBF_EINVAL, "tile_x %d", s->tile_x);
   }
 }
+
+namespace {
 
 dim3 node_grid(const lbf_sim* s) { return dim3((s->G.nx + 255) / 256, s->G.ny, 1); }
 
@@ -471,6 +436,7 @@ int lbf_init_fields(lbf_sim* s, const float* phi, const float* T, int32_t on_dev
   s->step = 0;
   s->have_budget = false;
   s->have_init = true;
+  s->from_fields = true;
   return LBF_OK;
 }
 
@@ -497,6 +463,7 @@ int lbf_set_poststream_state(lbf_sim* s, const float* dist, const float* lag, in
   s->step = step;
   s->have_budget = false;
   s->have_init = true;
+  s->from_fields = false;
   return LBF_OK;
 }
 
@@ -646,6 +613,7 @@ int lbf_load_state(lbf_sim* s, const void* src, size_t bytes) {
   s->step = hdr[1];
   s->have_init = true;
   s->have_budget = false;
+  s->from_fields = false;
   return LBF_OK;
 }
 

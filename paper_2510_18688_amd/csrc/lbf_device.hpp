@@ -35,7 +35,9 @@ constexpr int NRED = 11;
 enum { LAG_FS = 0, LAG_Q = 1, LAG_JX = 2, LAG_JY = 3, LAG_P = 4, LAG_GHI = 5, LAG_HHI = 6 };
 // static planes: phi0, cos(theta), lap(phi0)
 enum { ST_PHI0 = 0, ST_CTH = 1, ST_LAP0 = 2 };
-enum { MODE_STEP = 0, MODE_FIELDS = 1 };
+// MODE_STEP_MOM: a step that also stores phi, f_s and rho of the state it
+// reads (planes 0-2 of the fields buffer), for the reverse sweep's stencils
+enum { MODE_STEP = 0, MODE_FIELDS = 1, MODE_STEP_MOM = 2 };
 
 // D2Q9 (Sec. 3.1): c_0 = 0, c_1..4 axis-aligned counter-clockwise from +x,
 // c_5..8 diagonal counter-clockwise from (1,1); weights 4/9, 1/9, 1/36.
@@ -275,6 +277,10 @@ __device__ __forceinline__ void pull_f(const Geo& G, const Bufs& B, int x, int y
 struct Mom {
   float C, chi, rhoH, T, fs, fstot, mdot, phi, rho, Ksol, Kliq, dphi, dH;
   float ref_g, sg, sh;   // references and stored sums (for exact global sums)
+  // intermediate values and branch decisions, read only by the reverse sweep
+  // (dead code in the forward kernels)
+  float Craw, Cpraw, Cp, chi1, fl, fl_m, span;
+  bool sol, liq;
 };
 
 // ref_g, ref_h: references of the rest populations; sg, sh: sums of the
@@ -283,12 +289,14 @@ __device__ __forceinline__ void moments(const Phys& ph, float ref_g, float sg, f
                                         float sh, float fs_prev, float Q_prev, float phi0,
                                         Mom& m) {
   const float phihat = ref_g + sg;
-  const float C = clampf(0.5f * (1.0f - phi0 + phihat), 0.0f, 1.0f);
+  const float Craw = 0.5f * (1.0f - phi0 + phihat);
+  const float C = clampf(Craw, 0.0f, 1.0f);
   // phase-change fraction: liquid weight above the floor, latched by the
   // previous ice fraction, at most the non-solid fraction
-  const float Cp = clampf((C - ph.pcm_floor) * ph.inv_pcm_span, 0.0f, 1.0f);
-  float chi = ph.latch ? fmaxf(Cp, fs_prev) : Cp;
-  chi = clampf(chi, 0.0f, 1.0f - phi0);
+  const float Cpraw = (C - ph.pcm_floor) * ph.inv_pcm_span;
+  const float Cp = clampf(Cpraw, 0.0f, 1.0f);
+  const float chi1 = ph.latch ? fmaxf(Cp, fs_prev) : Cp;
+  const float chi = clampf(chi1, 0.0f, 1.0f - phi0);
   // total enthalpy with the lagged source (Sec. 3.3)
   const float dH = sh + 0.5f * Q_prev;
   const float rhoH = ref_h + dH;
@@ -303,7 +311,8 @@ __device__ __forceinline__ void moments(const Phys& ph, float ref_g, float sg, f
   // three branches (solid below E_s, liquid above E_l, mushy between; an
   // empty mushy interval counts as liquid), evaluated without divergence
   const bool sol = rhoH < Es, liq = !sol && rhoH > El;
-  const float fl_m = (El > Es) ? (rhoH - Es) * rcp(El - Es) : 1.0f;
+  const float span = El - Es;
+  const float fl_m = (El > Es) ? (rhoH - Es) * rcp(span) : 1.0f;
   const float fl = sol ? 0.0f : (liq ? 1.0f : fl_m);
   const float T = sol ? rhoH * rcp(Ksol) : (liq ? ph.T_m + (rhoH - El) * rcp(Kliq) : ph.T_m);
   const float fs = chi * (1.0f - fl);
@@ -327,6 +336,15 @@ __device__ __forceinline__ void moments(const Phys& ph, float ref_g, float sg, f
   m.rho = zeta(fstot, C, ph.rho_s, ph.rho_l, ph.rho_g);
   m.Ksol = Ksol;
   m.Kliq = Kliq;
+  m.Craw = Craw;
+  m.Cpraw = Cpraw;
+  m.Cp = Cp;
+  m.chi1 = chi1;
+  m.fl = fl;
+  m.fl_m = fl_m;
+  m.span = span;
+  m.sol = sol;
+  m.liq = liq;
 }
 
 // Chemical potential, derivative of the free energy eq44.

@@ -203,7 +203,7 @@ __device__ __forceinline__ void step_strip(const Geo& G, const Phys& ph, const B
         a_liq += cm.chi - cm.fs;
       }
       Post o;
-      if (MODE == MODE_STEP) {
+      if (MODE != MODE_FIELDS) {
         collide_node<true>(ph, cm, S, phi0, fin.cth, fin.lap0, cQp, fin.jxp, fin.jyp, crh, fv, cg,
                            ch, o);
 #pragma unroll
@@ -219,6 +219,11 @@ __device__ __forceinline__ void step_strip(const Geo& G, const Phys& ph, const B
         stp(B.lout, LAG_P, P, k, o.p);
         stp(B.lout, LAG_GHI, P, k, o.ghi);
         stp(B.lout, LAG_HHI, P, k, o.hhi);
+        if (MODE == MODE_STEP_MOM) {
+          stp(B.fields, 0, P, k, cm.phi);
+          stp(B.fields, 1, P, k, cm.fs);
+          stp(B.fields, 2, P, k, cm.rho);
+        }
         if (RED) {
           a_sphi += (double)cm.phi * (double)cm.mdot;
           a_heat += o.heat_src;

@@ -27,7 +27,8 @@ EXPORTS = ["lbf_workspace_bytes", "lbf_create", "lbf_set_geometry", "lbf_set_wal
            "lbf_load_state", "lbf_set_timing", "lbf_last_step_kernel_ms", "lbf_last_error",
            "lbf_destroy", "lbf_batch_create", "lbf_batch_set_tile", "lbf_batch_step",
            "lbf_batch_set_timing", "lbf_batch_last_step_ms", "lbf_batch_items",
-           "lbf_batch_destroy"]
+           "lbf_batch_destroy", "lbf_tape_bytes", "lbf_tape_create", "lbf_tape_segment",
+           "lbf_tape_forward", "lbf_tape_backward", "lbf_tape_destroy"]
 
 ERRORS = {-1: "LBF_EINVAL", -2: "LBF_EHIP", -3: "LBF_ESTATE", -4: "LBF_EUNSTABLE",
           -5: "LBF_ENOMEM"}
@@ -97,6 +98,14 @@ def load(path: str = LIB_PATH):
     L.lbf_batch_items.restype = i32
     L.lbf_batch_items.argtypes = [vp]
     L.lbf_batch_destroy.argtypes = [vp]
+    L.lbf_tape_bytes.restype = C.c_size_t
+    L.lbf_tape_bytes.argtypes = [i32, i32, i32, i32]
+    L.lbf_tape_create.argtypes = [vp, i32, i32, C.POINTER(vp)]
+    L.lbf_tape_segment.restype = i32
+    L.lbf_tape_segment.argtypes = [vp]
+    L.lbf_tape_forward.argtypes = [vp]
+    L.lbf_tape_backward.argtypes = [vp, vp, vp, vp, i32, vp, vp, i32]
+    L.lbf_tape_destroy.argtypes = [vp]
     for name in EXPORTS:
         getattr(L, name)
     _lib = L
@@ -307,3 +316,133 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+class Tape:
+    """Reverse-mode differentiation of a run of `nsteps` steps of `sim` with a
+    checkpoint every `segment` steps (0: ceil(sqrt(nsteps)))."""
+
+    def __init__(self, sim: Sim, nsteps: int, segment: int = 0):
+        L = load()
+        self.sim = sim
+        self.nsteps = int(nsteps)
+        h = C.c_void_p()
+        check(L.lbf_tape_create(sim.h, self.nsteps, int(segment), C.byref(h)))
+        self.h = h
+
+    @property
+    def segment(self) -> int:
+        return int(_lib.lbf_tape_segment(self.h))
+
+    def forward(self) -> None:
+        check(_lib.lbf_tape_forward(self.h))
+
+    def backward(self, seed_phi=None, seed_T=None, seed_fs=None):
+        """Seeds dJ/dphi, dJ/dT, dJ/df_s of the final state ([ny, nx]; device
+        float32 tensors or host arrays, None = 0).  Returns the FP64 device
+        tensors dJ/dcos(theta) [ny, nx] and dJ/dT_w [2 nx + 2 ny] (bottom, top,
+        left, right)."""
+        import torch
+        seeds = [seed_phi, seed_T, seed_fs]
+        dev = [isinstance(a, torch.Tensor) for a in seeds if a is not None]
+        if dev and not (all(dev) or not any(dev)):
+            raise LbfError(-1, "seeds must all be device tensors or all host arrays")
+        on_dev = int(bool(dev) and dev[0])
+        ptrs, keep = [], []
+        for a in seeds:
+            if a is None:
+                ptrs.append(None)
+                continue
+            if on_dev:
+                if a.device.type != "cuda" or a.dtype != torch.float32 or not a.is_contiguous():
+                    raise LbfError(-1, "seed tensors must be contiguous float32 on the device")
+                if a.numel() != self.sim.nx * self.sim.ny:
+                    raise LbfError(-1, "a seed needs nx * ny values")
+                ptrs.append(C.c_void_p(a.data_ptr()))
+                keep.append(a)
+            else:
+                arr = _f32_host(a).reshape(-1)
+                if arr.size != self.sim.nx * self.sim.ny:
+                    raise LbfError(-1, "a seed needs nx * ny values")
+                ptrs.append(C.c_void_p(arr.ctypes.data))
+                keep.append(arr)
+        nx, ny = self.sim.nx, self.sim.ny
+        gc = torch.empty((ny, nx), dtype=torch.float64, device=self.sim.device)
+        gw = torch.empty(2 * nx + 2 * ny, dtype=torch.float64, device=self.sim.device)
+        check(_lib.lbf_tape_backward(self.h, ptrs[0], ptrs[1], ptrs[2], on_dev,
+                                     C.c_void_p(gc.data_ptr()), C.c_void_p(gw.data_ptr()), 1))
+        return gc, gw
+
+    def close(self) -> None:
+        if getattr(self, "h", None) is not None and self.h.value:
+            _lib.lbf_tape_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def wall_vector(case):
+    """The wall temperatures of a case as one vector [2 nx + 2 ny]: bottom,
+    top, left, right."""
+    return np.concatenate([np.broadcast_to(np.asarray(case.wall_profile(w), dtype=np.float64),
+                                           (case.nx if w < 2 else case.ny,))
+                           for w in range(4)])
+
+
+def _freeze_function():
+    import torch
+
+    class FreezeFields(torch.autograd.Function):
+        """(cos theta per node [ny, nx], wall temperatures [2 nx + 2 ny]) ->
+        (phi, T, f_s) [ny, nx] after `steps` coupled steps from the case's
+        initial fields.  The backward pass is the library's adjoint sweep."""
+
+        @staticmethod
+        def forward(ctx, cos_theta, wall_T, case, steps, segment, tile):
+            sim = Sim(case, tile=tile)
+            dev = sim.device
+            sim.set_geometry(torch.as_tensor(np.ascontiguousarray(case.phi0, dtype=np.float32),
+                                             device=dev),
+                             cos_theta.detach().to(device=dev, dtype=torch.float32).contiguous())
+            wt = wall_T.detach().to(device=dev, dtype=torch.float32).contiguous()
+            nx, ny = case.nx, case.ny
+            bounds = [0, nx, 2 * nx, 2 * nx + ny, 2 * nx + 2 * ny]
+            for w in range(4):
+                sim.set_wall_temperature(w, wt[bounds[w]:bounds[w + 1]].contiguous())
+            sim.init_fields(torch.as_tensor(np.ascontiguousarray(case.phi, dtype=np.float32),
+                                            device=dev),
+                            torch.as_tensor(np.ascontiguousarray(case.T, dtype=np.float32),
+                                            device=dev))
+            tape = Tape(sim, steps, segment)
+            tape.forward()
+            out = [sim.field(k, torch.empty((ny, nx), dtype=torch.float32, device=dev))
+                   for k in ("phi", "T", "fs")]
+            ctx.tape = tape
+            ctx.dtypes = (cos_theta.dtype, wall_T.dtype, cos_theta.device, wall_T.device)
+            return tuple(out)
+
+        @staticmethod
+        def backward(ctx, g_phi, g_T, g_fs):
+            def seed(g):
+                return None if g is None else g.detach().to(torch.float32).contiguous()
+            gc, gw = ctx.tape.backward(seed(g_phi), seed(g_T), seed(g_fs))
+            ctx.tape.close()
+            ct, wt, cd, wd = ctx.dtypes
+            return gc.to(device=cd, dtype=ct), gw.to(device=wd, dtype=wt), None, None, None, None
+
+    return FreezeFields
+
+
+_FREEZE = None
+
+
+def freeze_fields(cos_theta, wall_T, case, steps: int, segment: int = 0, tile=None):
+    """Differentiable run: see FreezeFields."""
+    global _FREEZE
+    if _FREEZE is None:
+        _FREEZE = _freeze_function()
+    return _FREEZE.apply(cos_theta, wall_T, case, int(steps), int(segment), tile)

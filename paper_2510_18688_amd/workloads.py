@@ -302,6 +302,20 @@ def adjoint_case(n: int = 256, steps: int = 2000):
     return case, 90.0 + 15.0 * s1, -1.0 + 0.25 * s2
 
 
+def small_freezing_case(nx: int = 32, ny: int = 24, h_s: float = 3.0, radius: float = 8.0,
+                        T_wall: float = -1.5, seed: int = 1) -> Case:
+    """A small drop on a thin diffuse slab over a cold wall: the cold front
+    reaches the drop within tens of steps, so the final ice fraction depends
+    on both the wettability and the wall temperature.  Contact angles
+    75 +- 10 degrees and wall temperatures T_wall +- 0.2, drawn per column."""
+    case = slab_drop(nx, ny, radius, 75.0, T_wall, h_s=h_s, name=f"small_freezing_{nx}x{ny}")
+    rng = np.random.default_rng(seed)
+    th = 75.0 + 10.0 * rng.uniform(-1, 1, nx)
+    case.cos_theta = np.broadcast_to(np.cos(np.radians(th))[None, :], (ny, nx)).copy()
+    case.wall_T = {BOTTOM: T_wall + 0.2 * rng.uniform(-1, 1, nx)}
+    return case
+
+
 WORKLOADS = {
     "sessile_flat_128x96": lambda: sessile_drop(),
     "curved_substrate_2048x2048": lambda: curved_substrate(),

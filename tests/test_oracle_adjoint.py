@@ -15,17 +15,8 @@ import torch
 from paper_2510_18688_amd import workloads as W
 
 
-def small_freezing_case(nx=32, ny=24, hs=3.0, radius=8.0, Tw=-1.5):
-    """A drop on a thin diffuse slab over a cold wall: the cold front reaches
-    the drop within tens of steps, so the ice fraction depends on both
-    controls."""
-    case = W.slab_drop(nx, ny, radius, 75.0, Tw, h_s=hs)
-    rng = np.random.default_rng(1)
-    # per-column contact angles around 75 degrees
-    th = 75.0 + 10.0 * rng.uniform(-1, 1, nx)
-    case.cos_theta = np.broadcast_to(np.cos(np.radians(th))[None, :], (ny, nx)).copy()
-    case.wall_T = {W.BOTTOM: Tw + 0.2 * rng.uniform(-1, 1, nx)}
-    return case
+def small_freezing_case():
+    return W.small_freezing_case()
 
 
 def test_torch_oracle_matches_c_oracle(oracle_mod):
