@@ -18,6 +18,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -27,6 +29,27 @@ sys.path.insert(0, ROOT)
 # lap phi0).
 BYTES_PER_LU = (27 + 7) * 2 * 4 + 3 * 4
 HBM_PEAK_GBS = 8000.0
+
+
+def hbm_traffic(kernel_ms):
+    """HBM traffic of the step kernel from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE per dispatch, scaled by the same
+    counters' reading of a plain 512 MiB copy), as GB/s at this run's kernel
+    time; None when the kernel sources changed since the counters were
+    taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "step_kernel_curved_substrate_2048x2048.hbm.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    h = hashlib.sha256()
+    for p in rec["sources"]:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    if h.hexdigest() != rec["sources_sha256"]:
+        return None
+    return rec
 
 
 def parse():
@@ -39,6 +62,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--batch-steps", type=int, default=320,
                     help="steps of the 64-lattice batched workload (0 skips it)")
+    ap.add_argument("--adjoint-steps", type=int, default=2000,
+                    help="steps of the 256 x 256 gradient workload (0 skips it)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run an elementwise copy of MIB MiB (read + write), the "
                          "reference kernel for scaling HBM byte counters")
@@ -103,6 +128,59 @@ def batched(lbf, W, torch, steps):
             "nonfinite": sum(r["nonfinite"] for r in red)}
 
 
+def adjoint(lbf, W, torch, steps):
+    """Gradient workload: a drop on a slab over a cold wall, 256 x 256.  The
+    forward time of `steps` plain steps against the reverse sweep (segment
+    recomputation included) of the same run, for J = 1/2 sum (f_l - f_l*)^2
+    with respect to cos(theta) per node and the wall temperatures."""
+    case, th_t, tw_t = W.adjoint_case(steps=steps)
+    from paper_2510_18688_amd import autotune
+    tile = autotune.lookup(case.nx, case.ny)
+    # the target: final liquid fraction under the target controls (any
+    # target gives the same work)
+    tcase, _, _ = W.adjoint_case(steps=steps)
+    tcase.cos_theta = np.broadcast_to(np.cos(np.radians(th_t))[None, :], (tcase.ny, tcase.nx)).copy()
+    tcase.wall_T = {W.BOTTOM: np.asarray(tw_t, dtype=np.float64)}
+    sim = lbf.Sim(tcase, tile=tile)
+    sim.step(steps)
+    fl_star = torch.as_tensor(sim.field("fl"), device="cuda")
+    sim.close()
+    # forward: plain steps from the initial state
+    sim = lbf.Sim(case, tile=tile)
+    sim.step(8)
+    sim.init_fields(case.phi, case.T)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    sim.init_fields(case.phi, case.T)
+    tape = lbf.Tape(sim, steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tape.forward()
+    torch.cuda.synchronize()
+    t_rec = time.perf_counter() - t0
+    fl = torch.as_tensor(sim.field("fl"), device="cuda")
+    J = 0.5 * float(((fl.double() - fl_star.double()) ** 2).sum())
+    seed_fs = (-(fl - fl_star)).contiguous()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gc, gw = tape.backward(seed_fs=seed_fs)
+    torch.cuda.synchronize()
+    t_bwd = time.perf_counter() - t0
+    seg = tape.segment
+    tape.close()
+    return {"workload": f"{case.name}: drop R 77 on slab h_s 10 over a cold wall, "
+                        "J = 1/2 sum (f_l - f_l*)^2",
+            "steps": steps, "segment": seg, "J": J,
+            "grad_norm_cos_theta": float(gc.norm()), "grad_norm_wall_T": float(gw.norm()),
+            "forward_ms": round(t_fwd * 1e3, 2), "tape_forward_ms": round(t_rec * 1e3, 2),
+            "backward_ms": round(t_bwd * 1e3, 2),
+            "adjoint_over_forward": round(t_bwd / t_fwd, 3),
+            "record_and_adjoint_over_forward": round((t_rec + t_bwd) / t_fwd, 3)}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -151,6 +229,10 @@ def main():
     nodes = case.nodes
     mlups = nodes * args.steps / wall / 1e6
     achieved = BYTES_PER_LU * nodes / (kms * 1e-3) / 1e9
+    counters = hbm_traffic(kms)
+    traffic = None
+    if counters is not None:
+        traffic = round(counters["hbm_bytes_per_launch"] / (kms * 1e-3) / 1e9, 1)
     out = {
         "metric": "MLUPS of coupled 3-field LB step, % of HBM peak; adjoint/forward time ratio",
         "value": round(mlups, 2),
@@ -169,13 +251,17 @@ def main():
         "pct_hbm": round(100.0 * mlups * 1e6 * BYTES_PER_LU / (HBM_PEAK_GBS * 1e9), 2),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None, "kernel": "step_kernel",
-                     "kernel_ms": round(kms, 5), "bytes_per_lu": BYTES_PER_LU},
+                     "traffic": traffic, "kernel": "step_kernel",
+                     "kernel_ms": round(kms, 5), "bytes_per_lu": BYTES_PER_LU,
+                     "traffic_bytes_per_launch": counters and counters["hbm_bytes_per_launch"],
+                     "traffic_over_algorithmic": counters and counters["traffic_over_algorithmic"]},
         "checks": {"nonfinite": red["nonfinite"], "umax": red["umax"]},
     }
+    del sim
     if args.batch_steps > 0:
-        del sim
         out["batched"] = batched(lbf, W, torch, args.batch_steps)
+    if args.adjoint_steps > 0:
+        out["adjoint"] = adjoint(lbf, W, torch, args.adjoint_steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(case, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -294,3 +294,30 @@ def run(case, steps: int, cth=None, wallT=None, requires_grad: bool = False
     for _ in range(steps):
         state = lat.step(state, cth, wallT)
     return lat.fields(state), cth, wallT, lat
+
+
+def run_checkpointed(case, steps: int, cth: torch.Tensor, wallT: torch.Tensor,
+                     segment: int = 50) -> Tuple[Dict[str, torch.Tensor], "TorchLattice"]:
+    """As run(), for long runs: the autograd graph is kept for one segment of
+    steps at a time (torch.utils.checkpoint recomputes each segment in the
+    backward pass), so memory grows with the number of segments, not steps.
+    cth and wallT are used as given (leaf tensors with requires_grad, or
+    expressions of them)."""
+    from torch.utils.checkpoint import checkpoint
+    lat = TorchLattice(case)
+    state = lat.init_state(cth)
+    flat = [state[0], state[1], state[2], *state[3]]
+
+    def seg_fn(n, c, w, *xs):
+        st = (xs[0], xs[1], xs[2], tuple(xs[3:8]))
+        for _ in range(n):
+            st = lat.step(st, c, w)
+        return (st[0], st[1], st[2], *st[3])
+
+    done = 0
+    while done < steps:
+        n = min(segment, steps - done)
+        flat = list(checkpoint(seg_fn, n, cth, wallT, *flat, use_reentrant=True))
+        done += n
+    state = (flat[0], flat[1], flat[2], tuple(flat[3:8]))
+    return lat.fields(state), lat
