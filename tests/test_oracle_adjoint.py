@@ -71,3 +71,47 @@ def test_autograd_gradient_matches_central_differences(oracle_mod, seed):
         vals.append(oracle_loss(oracle_mod, c, steps, target))
     fd = (vals[0] - vals[1]) / (2 * eps)
     assert abs(fd - analytic) <= 1e-5 * abs(fd) + 1e-9, (fd, analytic)
+
+
+def test_autograd_gradient_brute_force_every_parameter(oracle_mod):
+    """Every parameter of a 16 x 16, 50-step problem (cos theta at all 256
+    nodes and the 16 bottom-wall temperatures) by FP64 central differences
+    of the C oracle."""
+    from oracle import torch_oracle as TO
+    case = W.small_freezing_case(nx=16, ny=16, h_s=3.0, radius=5.0, T_wall=-2.0, seed=4)
+    steps = 50
+    rng = np.random.default_rng(20)
+    target = 0.3 * rng.uniform(0, 1, (case.ny, case.nx))
+    M, cth, wallT, _ = TO.run(case, steps, requires_grad=True)
+    J = 0.5 * ((M["fs"] - torch.from_numpy(target)) ** 2).sum()
+    J.backward()
+    ad = np.concatenate([cth.grad.numpy().ravel(), wallT.grad.numpy()[0, :case.nx]])
+    assert np.count_nonzero(ad) > 100
+    eps = 1e-6
+    fd = np.zeros_like(ad)
+    base_c, base_w = case.cos_theta.copy(), case.wall_T[W.BOTTOM].copy()
+    # 544 runs of a 256-node lattice: one thread each (no fork/join per row)
+    L = oracle_mod.lib()
+    threads0 = L.orc_max_threads()
+    L.orc_set_threads(1)
+    try:
+        _brute_force(oracle_mod, ad, fd, base_c, base_w, steps, target, eps)
+    finally:
+        L.orc_set_threads(threads0)
+    scale = float(np.abs(ad).max())
+    assert float(np.abs(fd - ad).max()) <= 1e-6 * scale, (float(np.abs(fd - ad).max()), scale)
+
+
+def _brute_force(oracle_mod, ad, fd, base_c, base_w, steps, target, eps):
+    for k in range(ad.size):
+        vals = []
+        for sgn in (1.0, -1.0):
+            c = W.small_freezing_case(nx=16, ny=16, h_s=3.0, radius=5.0, T_wall=-2.0, seed=4)
+            cc, ww = base_c.copy(), base_w.copy()
+            if k < cc.size:
+                cc.flat[k] += sgn * eps
+            else:
+                ww[k - cc.size] += sgn * eps
+            c.cos_theta, c.wall_T = cc, {W.BOTTOM: ww}
+            vals.append(oracle_loss(oracle_mod, c, steps, target))
+        fd[k] = (vals[0] - vals[1]) / (2 * eps)
