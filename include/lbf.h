@@ -188,7 +188,7 @@ void lbf_destroy(lbf_sim* sim);
 /* ---- batches: many lattices advanced by one persistent launch per step ----
  * A batch groups n initialised simulations that share one HIP stream (the
  * simulations stay owned by the caller and must outlive the batch).  Each
- * step is one launch of a fixed grid (two workgroups per compute unit) that
+ * step is one launch of a fixed grid (as many workgroups as fit on the device at once) that
  * walks the work list of every lattice's tiles; runs of 32 steps are
  * captured once in a HIP graph and replayed.  Every lattice is advanced
  * exactly as lbf_step would advance it (same arithmetic, bit-identical

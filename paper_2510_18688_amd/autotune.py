@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 DB = os.path.join(HERE, "tiles.json")
 
 CANDIDATES: Tuple[Tuple[int, int], ...] = tuple(
-    (tx, ty) for tx in (64, 128, 256) for ty in (8, 16, 32, 64, 128))
+    (tx, ty) for tx in (64, 128, 256) for ty in (1, 2, 4, 8, 16, 32, 64, 128))
 
 
 def _load() -> dict:
@@ -64,7 +64,7 @@ def tune(sim, steps: int = 20, candidates: Iterable[Sequence[int]] = CANDIDATES,
 
 
 BATCH_CANDIDATES: Tuple[Tuple[int, int], ...] = tuple(
-    (tx, ty) for tx in (64, 128, 256) for ty in (8, 16, 32, 64))
+    (tx, ty) for tx in (64, 128, 256) for ty in (2, 4, 8, 16, 32, 64))
 
 
 def lookup_batch(count: int, nodes: int) -> Optional[Tuple[int, int]]:

@@ -713,11 +713,27 @@ int batch_build(lbf_batch* b) {
   HIP_TRY(hipMemcpyAsync(b->d_items, items.data(), items.size() * sizeof(int2),
                          hipMemcpyHostToDevice, b->stream));
   b->nitems = (int)items.size();
-  int dev = 0, ncu = 0;
+  int dev = 0, ncu = 0, per_cu = 0;
   HIP_TRY(hipGetDevice(&dev));
   HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-  // two workgroups per CU, never many more than there are items
-  b->grid = std::max(8, std::min(2 * ncu, (b->nitems + 7) / 8 * 8));
+  // as many workgroups as fit on the device at once (register- and
+  // LDS-limited), never many more than there are items
+  switch (b->tile_x) {
+    case 64:
+      HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &per_cu, reinterpret_cast<const void*>(batch_step_kernel<64>), 64, 0));
+      break;
+    case 128:
+      HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &per_cu, reinterpret_cast<const void*>(batch_step_kernel<128>), 128, 0));
+      break;
+    default:
+      HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &per_cu, reinterpret_cast<const void*>(batch_step_kernel<256>), 256, 0));
+      break;
+  }
+  per_cu = std::max(per_cu, 1);
+  b->grid = std::max(8, std::min(per_cu * ncu, (b->nitems + 7) / 8 * 8));
   b->grid = (b->grid + 7) / 8 * 8;
   b->built = true;
   return batch_upload_desc(b);

@@ -16,6 +16,16 @@ namespace lbf {
 
 constexpr int CY_MAX = 256;
 
+// Rows of populations requested ahead of their use (1 or 2), and whether
+// the flow populations of the next row are requested before the collision
+// of the current one (1) or after it (0).
+#ifndef LBF_DEPTH
+#define LBF_DEPTH 1
+#endif
+#ifndef LBF_FLOW_AHEAD
+#define LBF_FLOW_AHEAD 1
+#endif
+
 template <int WX>
 struct StepShared {
   float v[4][4][WX + 2];        // [phi, fs, rho, p_prev][ring slot][column]
@@ -117,7 +127,9 @@ __device__ __forceinline__ void step_strip(const Geo& G, const Phys& ph, const B
   const int ys = dir > 0 ? y0 : y1 - 1;
   const int nrow = y1 - y0;
   NodeIn cin, ain;   // current row; row ahead (in flight)
+  NodeIn a2in;       // (LBF_DEPTH 2) two rows ahead, in flight
   FlowIn fin;        // flow data of the current row (in flight)
+  FlowIn fnx;        // (LBF_FLOW_AHEAD) flow data of the next row, in flight
   Mom cm;
   if (act) {
     NodeIn bin;
@@ -126,6 +138,7 @@ __device__ __forceinline__ void step_strip(const Geo& G, const Phys& ph, const B
     node_load(G, ph, B, x, map_axis(ys - dir, G.ny, G.py), bin);
     node_load(G, ph, B, x, ys, cin);
     node_load(G, ph, B, x, map_axis(ys + dir, G.ny, G.py), ain);
+    if (LBF_DEPTH > 1 && nrow >= 2) node_load(G, ph, B, x, map_axis(ys + 2 * dir, G.ny, G.py), a2in);
     flow_load(G, B, x, ys, fin);
     node_finish(ph, bin, m, st);
 #pragma unroll
@@ -167,7 +180,13 @@ __device__ __forceinline__ void step_strip(const Geo& G, const Phys& ph, const B
 #pragma unroll
       for (int f = 0; f < 4; ++f) sh.v[f][slot_n][l + 1] = st[f];
       next_c = ain;
-      if (more) node_load(G, ph, B, x, map_axis(ya + dir, G.ny, G.py), ain);
+      if (LBF_DEPTH > 1) {
+        if (it + 2 <= nrow) ain = a2in;
+        if (it + 3 <= nrow) node_load(G, ph, B, x, map_axis(ya + 2 * dir, G.ny, G.py), a2in);
+      } else if (more) {
+        node_load(G, ph, B, x, map_axis(ya + dir, G.ny, G.py), ain);
+      }
+      if (LBF_FLOW_AHEAD && more) flow_load(G, B, x, ya, fnx);
     }
     if (l == 0 || l == lastl) {
       const int r = ya - (y0 - 1);
@@ -252,7 +271,10 @@ __device__ __forceinline__ void step_strip(const Geo& G, const Phys& ph, const B
         if (!isfinite(cm.phi) || !isfinite(cm.T) || !isfinite(um) || !isfinite(o.p)) a_bad += 1;
       }
       // request the next row's flow data; rotate the row registers
-      if (more) flow_load(G, B, x, ya, fin);
+      if (more) {
+        if (LBF_FLOW_AHEAD) fin = fnx;
+        else flow_load(G, B, x, ya, fin);
+      }
       cin = next_c;
       cm = am;
     }

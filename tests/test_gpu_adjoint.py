@@ -181,3 +181,56 @@ def test_tape_call_order(lbf_mod):
         tape.backward(seed_fs=np.ones((case.ny, case.nx)))
     tape.close()
     sim.close()
+
+
+def test_gradient_workload_256_against_fp64_reference(lbf_mod):
+    """The 256 x 256, 2000-step gradient workload: per-column contact angle
+    (radians) and bottom-wall temperature, J = 1/2 sum (f_l - f_l*)^2 with the
+    oracle's f_l* of the target controls.  Compared with the stored FP64
+    reference (autograd gradient and central differences along 16 random
+    unit directions, written by tests/golden/make_c5_gradient.py)."""
+    import json
+    import os
+    import torch
+    from oracle import oracle as O
+    lbf = lbf_mod
+    ref = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "c5_gradient.json")))
+    steps = ref["steps"]
+    case, th_t, tw_t = W.adjoint_case(steps=steps)
+    n = case.nx
+    # target: the oracle's final liquid fraction under the target controls
+    O.build()
+    tc, _, _ = W.adjoint_case(steps=steps)
+    tc.cos_theta = np.broadcast_to(np.cos(np.radians(th_t))[None, :], (n, n)).copy()
+    tc.wall_T = {W.BOTTOM: np.asarray(tw_t, dtype=np.float64)}
+    o = O.Oracle(tc)
+    o.step(steps)
+    fl_star = torch.as_tensor(o.fields()["fl"], device="cuda")
+    theta = torch.full((n,), np.pi / 2, dtype=torch.float64, device="cuda", requires_grad=True)
+    tw = torch.full((n,), -1.0, dtype=torch.float64, device="cuda", requires_grad=True)
+    cth = torch.cos(theta)[None, :].expand(n, n).contiguous()
+    wall = torch.cat([tw, torch.zeros(n + 2 * n, dtype=torch.float64, device="cuda")])
+    phi, T, fs = lbf.freeze_fields(cth, wall, case, steps)
+    J = 0.5 * (((1.0 - fs.double()) - fl_star) ** 2).sum()
+    J.backward()
+    g = np.concatenate([theta.grad.cpu().numpy(), tw.grad.cpu().numpy()])
+    gr = np.asarray(ref["grad"])
+    assert abs(float(J) - ref["J0"]) <= 1e-3 * ref["J0"], (float(J), ref["J0"])
+    cos = float(g @ gr) / (np.linalg.norm(g) * np.linalg.norm(gr))
+    rel = float(np.linalg.norm(g - gr) / np.linalg.norm(gr))
+    rng = np.random.default_rng(ref["direction_seed"])
+    worst = 0.0
+    rows = []
+    for k in range(ref["directions"]):
+        d = rng.normal(size=2 * n)
+        d /= np.linalg.norm(d)
+        ours, orc = float(g @ d), float(gr @ d)
+        fds = [ref["fd"][key][k] for key in ref["fd"]]
+        rows.append((ours, orc, fds))
+        worst = max(worst, abs(ours - orc) / (1e-3 * abs(orc) + 1e-4 * np.linalg.norm(gr)))
+    print("gradient workload", dict(J=float(J), J_ref=ref["J0"], cosine=cos, rel_l2=rel,
+                                    dir_ratio=worst), flush=True)
+    for r in rows:
+        print("  direction", r, flush=True)
+    assert cos >= COSINE, cos
+    assert worst <= 1.0, worst
