@@ -115,3 +115,23 @@ def _brute_force(oracle_mod, ad, fd, base_c, base_w, steps, target, eps):
             c.cos_theta, c.wall_T = cc, {W.BOTTOM: ww}
             vals.append(oracle_loss(oracle_mod, c, steps, target))
         fd[k] = (vals[0] - vals[1]) / (2 * eps)
+
+
+def test_stored_gradient_reference_is_pinned_by_its_differences():
+    """tests/golden/c5_gradient.json (256 x 256, 2000 steps): the stored FP64
+    autograd gradient against the stored FP64 central differences of the C
+    oracle along the same 16 directions, at the smallest step."""
+    import json
+    import os
+    ref = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "c5_gradient.json")))
+    g = np.asarray(ref["grad"])
+    assert g.size == 512 and abs(ref["J_autograd"] - ref["J0"]) <= 1e-12 * ref["J0"]
+    rng = np.random.default_rng(ref["direction_seed"])
+    fd = ref["fd"]["1e-06"]
+    for k in range(ref["directions"]):
+        d = rng.normal(size=g.size)
+        d /= np.linalg.norm(d)
+        ad = float(g @ d)
+        assert abs(ad - fd[k]) <= 1e-5 * abs(ad) + 1e-7 * np.linalg.norm(g), (k, ad, fd[k])
+        # the larger steps converge towards it (first-order branch effects)
+        assert abs(ref["fd"]["0.0001"][k] - ad) >= abs(fd[k] - ad) or abs(fd[k] - ad) < 1e-7
