@@ -239,13 +239,16 @@ void lbf_batch_destroy(lbf_batch* batch);
 typedef struct lbf_tape lbf_tape;
 
 /* Device bytes a tape allocates: ceil(nsteps / segment) stored states of
- * 34 planes, `segment` recomputed states and their moments, and the adjoint
- * work planes.  segment <= 0 selects ceil(sqrt(nsteps)). */
+ * 34 planes, two buffers of `segment` recomputed states and their moments
+ * (one segment is recomputed on a second stream while the other is
+ * reversed), and the adjoint work planes.  segment <= 0 selects
+ * ceil(sqrt(nsteps)). */
 size_t lbf_tape_bytes(int32_t nx, int32_t ny, int32_t nsteps, int32_t segment);
 
 /* Create a tape for `sim` (which must outlive it) recording nsteps >= 0
  * steps with a checkpoint every `segment` steps (<= 0: ceil(sqrt(nsteps))).
- * The tape owns its device memory (hipMalloc; LBF_ENOMEM on failure). */
+ * The tape owns its device memory (hipMalloc; LBF_ENOMEM on failure) and a
+ * private non-blocking stream of default priority for the recomputation. */
 int lbf_tape_create(lbf_sim* sim, int32_t nsteps, int32_t segment, lbf_tape** out);
 
 /* The checkpoint interval in use. */

@@ -5,8 +5,11 @@
 // default).  The backward sweep walks the segments from last to first:
 // recompute the segment from its checkpoint with the step kernel (which also
 // stores phi, f_s and rho of every state for the reverse stencils), then
-// run the two adjoint kernels per step in reverse order.  Gradients are
-// accumulated in FP64 on the device.
+// run the two adjoint kernels per step in reverse order.  The recomputation
+// of segment k - 1 does not depend on the adjoint, so it runs on a second
+// stream into the other of two segment buffers while segment k is reversed;
+// events order each buffer's reuse.  Gradients are accumulated in FP64 on
+// the device.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -32,8 +35,8 @@ struct lbf_tape {
   char* mem;
   size_t bytes;
   float* ck;              // nck states
-  float* segs;            // seg states (recomputed segment)
-  float* mom;             // seg x 3 planes
+  float* segs[2];         // seg states each (recomputed segments, alternating)
+  float* mom[2];          // seg x 3 planes each
   float* adjD[2];         // NADJ_D planes per time-level parity
   float* adjL[2];         // NADJ_L planes
   float* st;              // NST planes
@@ -41,6 +44,8 @@ struct lbf_tape {
   float* seeds;           // 3 planes (staging of host seeds)
   double* gcth;           // nx * ny
   double* gwall;          // 4 * wstride
+  hipStream_t rstream;    // recomputation stream (default priority)
+  hipEvent_t ev_start, ev_rec[2], ev_used[2];
   bool recorded;          // forward run done, sim at its final state
   bool with_init;         // the run started from lbf_init_fields
   long long end_step;     // sim step count after the recorded run
@@ -48,7 +53,9 @@ struct lbf_tape {
 
 namespace {
 
-size_t tape_layout(int nx, int ny, int nsteps, int seg, size_t offs[12]) {
+constexpr int kTapeParts = 14;
+
+size_t tape_layout(int nx, int ny, int nsteps, int seg, size_t offs[kTapeParts]) {
   const size_t P = (size_t)plane_stride(nx, ny) * sizeof(float);
   const int nck = (nsteps + seg - 1) / seg;
   const size_t wstride = round_up((size_t)std::max(nx, ny), 64);
@@ -59,17 +66,19 @@ size_t tape_layout(int nx, int ny, int nsteps, int seg, size_t offs[12]) {
     off = round_up(off + b, kAlign);
   };
   take((size_t)std::max(nck, 1) * kStatePlanes * P);   // 0 checkpoints
-  take((size_t)seg * kStatePlanes * P);                // 1 segment states
-  take((size_t)seg * 3 * P);                           // 2 segment moments
-  take(NADJ_D * P);                                    // 3, 4
+  take((size_t)seg * kStatePlanes * P);                // 1, 2 segment states
+  take((size_t)seg * kStatePlanes * P);
+  take((size_t)seg * 3 * P);                           // 3, 4 segment moments
+  take((size_t)seg * 3 * P);
+  take(NADJ_D * P);                                    // 5, 6
   take(NADJ_D * P);
-  take(NADJ_L * P);                                    // 5, 6
+  take(NADJ_L * P);                                    // 7, 8
   take(NADJ_L * P);
-  take(NST * P);                                       // 7
-  take(NJAC * P);                                      // 8
-  take(3 * P);                                         // 9 seeds
-  take((size_t)nx * ny * sizeof(double));              // 10 gcth
-  take(4 * wstride * sizeof(double));                  // 11 gwall
+  take(NST * P);                                       // 9
+  take(NJAC * P);                                      // 10
+  take(3 * P);                                         // 11 seeds
+  take((size_t)nx * ny * sizeof(double));              // 12 gcth
+  take(4 * wstride * sizeof(double));                  // 13 gwall
   return off;
 }
 
@@ -77,8 +86,9 @@ int default_segment(int nsteps) {
   return std::max(1, (int)std::ceil(std::sqrt((double)std::max(nsteps, 1))));
 }
 
-float* state_ptr(lbf_tape* t, int slot_kind, int idx) {
-  float* base = slot_kind == 0 ? t->ck : t->segs;
+// state slot `idx` of the checkpoints (kind 0) or of segment buffer kind - 1
+float* state_ptr(lbf_tape* t, int kind, int idx) {
+  float* base = kind == 0 ? t->ck : t->segs[kind - 1];
   return base + (size_t)idx * kStatePlanes * t->P;
 }
 
@@ -110,14 +120,32 @@ int copy_state_out(lbf_tape* t, float* dst) {
 }
 
 // Step state `in` to `out` with the step kernel, storing phi, f_s, rho of
-// `in` in `mom`.
-int recompute_step(lbf_tape* t, const float* in, float* out, float* mom) {
+// `in` in `mom`, on stream `st`.
+int recompute_step(lbf_tape* t, const float* in, float* out, float* mom, hipStream_t st) {
   lbf_sim* s = t->sim;
   BufArgs B = state_args(t, in);
   B.dout = out;
   B.lout = out + NDIST * t->P;
   B.fields = mom;
-  return launch_step_args(s, MODE_STEP_MOM, false, B);
+  return launch_step_args(s, MODE_STEP_MOM, false, B, st);
+}
+
+// Recompute segment `sgi` (states c + 1 .. c + L - 1 and the moments of
+// c .. c + L - 1) into buffer sgi & 1 on the recomputation stream, after the
+// buffer's previous reader has finished.
+int recompute_segment(lbf_tape* t, int sgi, bool buffer_used) {
+  const int b = sgi & 1;
+  const int c = sgi * t->seg;
+  const int L = std::min(t->seg, t->nsteps - c);
+  if (buffer_used) HIP_TRY(hipStreamWaitEvent(t->rstream, t->ev_used[b], 0));
+  for (int j = 0; j < L; ++j) {
+    const float* in = j == 0 ? state_ptr(t, 0, sgi) : state_ptr(t, 1 + b, j - 1);
+    int rc = recompute_step(t, in, state_ptr(t, 1 + b, j), t->mom[b] + (size_t)j * 3 * t->P,
+                            t->rstream);
+    if (rc) return rc;
+  }
+  HIP_TRY(hipEventRecord(t->ev_rec[b], t->rstream));
+  return LBF_OK;
 }
 
 }  // namespace
@@ -127,7 +155,7 @@ extern "C" {
 size_t lbf_tape_bytes(int32_t nx, int32_t ny, int32_t nsteps, int32_t segment) {
   if (nx < 1 || ny < 1 || nsteps < 0) return 0;
   const int seg = segment > 0 ? segment : default_segment(nsteps);
-  size_t offs[12];
+  size_t offs[kTapeParts];
   return tape_layout(nx, ny, nsteps, seg, offs);
 }
 
@@ -143,7 +171,7 @@ int lbf_tape_create(lbf_sim* sim, int32_t nsteps, int32_t segment, lbf_tape** ou
   t->seg = segment > 0 ? std::min<int>(segment, std::max(nsteps, 1)) : default_segment(nsteps);
   t->nck = (nsteps + t->seg - 1) / t->seg;
   t->P = (size_t)sim->G.P;
-  size_t offs[12];
+  size_t offs[kTapeParts];
   t->bytes = tape_layout(sim->G.nx, sim->G.ny, nsteps, t->seg, offs);
   if (hipMalloc((void**)&t->mem, t->bytes) != hipSuccess) {
     const size_t b = t->bytes;
@@ -152,17 +180,26 @@ int lbf_tape_create(lbf_sim* sim, int32_t nsteps, int32_t segment, lbf_tape** ou
   }
   auto F = [&](int q) { return reinterpret_cast<float*>(t->mem + offs[q]); };
   t->ck = F(0);
-  t->segs = F(1);
-  t->mom = F(2);
-  t->adjD[0] = F(3);
-  t->adjD[1] = F(4);
-  t->adjL[0] = F(5);
-  t->adjL[1] = F(6);
-  t->st = F(7);
-  t->jac = F(8);
-  t->seeds = F(9);
-  t->gcth = reinterpret_cast<double*>(t->mem + offs[10]);
-  t->gwall = reinterpret_cast<double*>(t->mem + offs[11]);
+  t->segs[0] = F(1);
+  t->segs[1] = F(2);
+  t->mom[0] = F(3);
+  t->mom[1] = F(4);
+  t->adjD[0] = F(5);
+  t->adjD[1] = F(6);
+  t->adjL[0] = F(7);
+  t->adjL[1] = F(8);
+  t->st = F(9);
+  t->jac = F(10);
+  t->seeds = F(11);
+  t->gcth = reinterpret_cast<double*>(t->mem + offs[12]);
+  t->gwall = reinterpret_cast<double*>(t->mem + offs[13]);
+  bool ok = hipStreamCreateWithFlags(&t->rstream, hipStreamNonBlocking) == hipSuccess;
+  for (hipEvent_t* e : {&t->ev_start, &t->ev_rec[0], &t->ev_rec[1], &t->ev_used[0], &t->ev_used[1]})
+    ok = ok && hipEventCreateWithFlags(e, hipEventDisableTiming) == hipSuccess;
+  if (!ok) {
+    lbf_tape_destroy(t);
+    return fail(LBF_EHIP, "stream / event creation failed");
+  }
   *out = t;
   return LBF_OK;
 }
@@ -229,24 +266,31 @@ int lbf_tape_backward(lbf_tape* t, const float* seed_phi, const float* seed_T,
     hipLaunchKernelGGL(k_adj_seed, grid, block, 0, st, a);
     HIP_TRY(hipGetLastError());
   }
+  // both streams start after everything queued so far on the simulation's stream
+  HIP_TRY(hipEventRecord(t->ev_start, st));
+  HIP_TRY(hipStreamWaitEvent(t->rstream, t->ev_start, 0));
+  if (t->nck > 0) {
+    int rc = recompute_segment(t, t->nck - 1, false);
+    if (rc) return rc;
+  }
   for (int sgi = t->nck - 1; sgi >= 0; --sgi) {
+    const int b = sgi & 1;
     const int c = sgi * t->seg;
     const int L = std::min(t->seg, N - c);
-    // recompute the segment: state c + j lives in the checkpoint (j = 0) or
-    // segment slot j - 1; moments of state c + j in mom slot j
-    for (int j = 0; j < L; ++j) {
-      const float* in = j == 0 ? state_ptr(t, 0, sgi) : state_ptr(t, 1, j - 1);
-      int rc = recompute_step(t, in, state_ptr(t, 1, j), t->mom + (size_t)j * 3 * P);
+    // the next segment to reverse is recomputed while this one is reversed
+    if (sgi > 0) {
+      int rc = recompute_segment(t, sgi - 1, sgi + 1 < t->nck);
       if (rc) return rc;
     }
+    HIP_TRY(hipStreamWaitEvent(st, t->ev_rec[b], 0));
     for (int j = L - 1; j >= 0; --j) {
       const int nstep = c + j;
-      const float* stn = j == 0 ? state_ptr(t, 0, sgi) : state_ptr(t, 1, j - 1);
+      const float* stn = j == 0 ? state_ptr(t, 0, sgi) : state_ptr(t, 1 + b, j - 1);
       AdjStepArgs a{};
       a.G = s->G;
       a.ph = s->ph;
       a.F = state_args(t, stn);
-      a.mom = t->mom + (size_t)j * 3 * P;
+      a.mom = t->mom[b] + (size_t)j * 3 * P;
       a.lamD = t->adjD[(nstep + 1) & 1];
       a.lamL = t->adjL[(nstep + 1) & 1];
       a.outD = t->adjD[nstep & 1];
@@ -257,15 +301,16 @@ int lbf_tape_backward(lbf_tape* t, const float* seed_phi, const float* seed_T,
       a.gwall = t->gwall;
       hipLaunchKernelGGL(k_adj_collide, grid, block, 0, st, a);
       HIP_TRY(hipGetLastError());
-      AdjGatherArgs b{};
-      b.G = s->G;
-      b.st = t->st;
-      b.jac = t->jac;
-      b.outD = t->adjD[nstep & 1];
-      b.outL = t->adjL[nstep & 1];
-      hipLaunchKernelGGL(k_adj_gather, grid, block, 0, st, b);
+      AdjGatherArgs g{};
+      g.G = s->G;
+      g.st = t->st;
+      g.jac = t->jac;
+      g.outD = t->adjD[nstep & 1];
+      g.outL = t->adjL[nstep & 1];
+      hipLaunchKernelGGL(k_adj_gather, grid, block, 0, st, g);
       HIP_TRY(hipGetLastError());
     }
+    HIP_TRY(hipEventRecord(t->ev_used[b], st));
   }
   if (t->with_init) {
     AdjInitArgs a{};
@@ -296,6 +341,12 @@ void lbf_tape_destroy(lbf_tape* t) {
   if (!t) return;
   if (t->sim && t->sim->stream) (void)hipStreamSynchronize(t->sim->stream);
   else (void)hipDeviceSynchronize();
+  if (t->rstream) {
+    (void)hipStreamSynchronize(t->rstream);
+    (void)hipStreamDestroy(t->rstream);
+  }
+  for (hipEvent_t e : {t->ev_start, t->ev_rec[0], t->ev_rec[1], t->ev_used[0], t->ev_used[1]})
+    if (e) (void)hipEventDestroy(e);
   if (t->mem) (void)hipFree(t->mem);
   delete t;
 }

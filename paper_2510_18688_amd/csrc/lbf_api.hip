@@ -256,26 +256,26 @@ int grid_blocks(const lbf_sim* s, dim3& grid) {
 }
 
 template <int WX>
-int launch_wx(lbf_sim* s, int mode, bool red, BufArgs B) {
+int launch_wx(lbf_sim* s, int mode, bool red, BufArgs B, hipStream_t st) {
   dim3 g2;
   const int nt = grid_blocks(s, g2);
   const int nbx = (int)g2.x;
   const dim3 grid(nt), block(WX);
   if (mode == MODE_STEP && !red)
-    hipLaunchKernelGGL((step_kernel<WX, MODE_STEP, false>), grid, block, 0, s->stream, s->G,
-                       s->ph, B, s->tile_y, nbx, nt);
+    hipLaunchKernelGGL((step_kernel<WX, MODE_STEP, false>), grid, block, 0, st, s->G, s->ph, B,
+                       s->tile_y, nbx, nt);
   else if (mode == MODE_STEP && red)
-    hipLaunchKernelGGL((step_kernel<WX, MODE_STEP, true>), grid, block, 0, s->stream, s->G,
-                       s->ph, B, s->tile_y, nbx, nt);
+    hipLaunchKernelGGL((step_kernel<WX, MODE_STEP, true>), grid, block, 0, st, s->G, s->ph, B,
+                       s->tile_y, nbx, nt);
   else if (mode == MODE_STEP_MOM)
-    hipLaunchKernelGGL((step_kernel<WX, MODE_STEP_MOM, false>), grid, block, 0, s->stream, s->G,
-                       s->ph, B, s->tile_y, nbx, nt);
+    hipLaunchKernelGGL((step_kernel<WX, MODE_STEP_MOM, false>), grid, block, 0, st, s->G, s->ph,
+                       B, s->tile_y, nbx, nt);
   else if (mode == MODE_FIELDS && !red)
-    hipLaunchKernelGGL((step_kernel<WX, MODE_FIELDS, false>), grid, block, 0, s->stream, s->G,
-                       s->ph, B, s->tile_y, nbx, nt);
+    hipLaunchKernelGGL((step_kernel<WX, MODE_FIELDS, false>), grid, block, 0, st, s->G, s->ph, B,
+                       s->tile_y, nbx, nt);
   else
-    hipLaunchKernelGGL((step_kernel<WX, MODE_FIELDS, true>), grid, block, 0, s->stream, s->G,
-                       s->ph, B, s->tile_y, nbx, nt);
+    hipLaunchKernelGGL((step_kernel<WX, MODE_FIELDS, true>), grid, block, 0, st, s->G, s->ph, B,
+                       s->tile_y, nbx, nt);
   HIP_TRY(hipGetLastError());
   return LBF_OK;
 }
@@ -283,16 +283,16 @@ int launch_wx(lbf_sim* s, int mode, bool red, BufArgs B) {
 int launch_step(lbf_sim* s, int mode, bool red, double* red_buf) {
   BufArgs B = make_args(s);
   B.red = red_buf;
-  return launch_step_args(s, mode, red, B);
+  return launch_step_args(s, mode, red, B, s->stream);
 }
 
 }  // namespace
 
-int lbfi::launch_step_args(lbf_sim* s, int mode, bool red, BufArgs B) {
+int lbfi::launch_step_args(lbf_sim* s, int mode, bool red, BufArgs B, hipStream_t st) {
   switch (s->tile_x) {
-    case 64: return launch_wx<64>(s, mode, red, B);
-    case 128: return launch_wx<128>(s, mode, red, B);
-    case 256: return launch_wx<256>(s, mode, red, B);
+    case 64: return launch_wx<64>(s, mode, red, B, st);
+    case 128: return launch_wx<128>(s, mode, red, B, st);
+    case 256: return launch_wx<256>(s, mode, red, B, st);
     default: return fail(LBF_EINVAL, "tile_x %d", s->tile_x);
   }
 }

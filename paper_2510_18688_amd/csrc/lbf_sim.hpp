@@ -71,7 +71,7 @@ inline float* fptr(lbf_sim* s, size_t off) { return reinterpret_cast<float*>(s->
 inline double* dptr(lbf_sim* s, size_t off) { return reinterpret_cast<double*>(s->ws + off); }
 
 // Launch the step kernel (MODE_STEP, MODE_FIELDS or MODE_STEP_MOM) with the
-// simulation's tile shape on explicit buffers.
-int launch_step_args(lbf_sim* s, int mode, bool red, lbf::BufArgs B);
+// simulation's tile shape on explicit buffers, on stream `st`.
+int launch_step_args(lbf_sim* s, int mode, bool red, lbf::BufArgs B, hipStream_t st);
 
 }  // namespace lbfi
