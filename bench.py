@@ -226,6 +226,15 @@ def main():
     sim.set_timing(False)
     red = sim.reduce()
 
+    # observables: column and row profiles of the final state
+    from paper_2510_18688_amd import observe
+    sim.profiles()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(10):
+        prof = sim.profiles()
+    prof_ms = (time.perf_counter() - t0) / 10 * 1e3
+
     nodes = case.nodes
     mlups = nodes * args.steps / wall / 1e6
     achieved = BYTES_PER_LU * nodes / (kms * 1e-3) / 1e9
@@ -256,6 +265,9 @@ def main():
                      "traffic_bytes_per_launch": counters and counters["hbm_bytes_per_launch"],
                      "traffic_over_algorithmic": counters and counters["traffic_over_algorithmic"]},
         "checks": {"nonfinite": red["nonfinite"], "umax": red["umax"]},
+        "observables": {"profiles_ms": round(prof_ms, 3),
+                        "solid_fraction": observe.solid_fraction(prof),
+                        "drop_top_y": observe.drop_height(prof)},
     }
     del sim
     if args.batch_steps > 0:

@@ -165,6 +165,36 @@ int lbf_read_fields(lbf_sim* sim, float* dst, int32_t dst_on_device);
  * non-finite or max |u| exceeds 0.3. */
 int lbf_reduce(lbf_sim* sim, double* out);
 
+/* Column and row profiles of the current state, the reductions behind the
+ * freezing observables: front height and final solid height (Sec. 4.2,
+ * Table 1), drop height on a curved substrate (Sec. 4.4), radius and height
+ * of the three-phase contact line (Fig. 6), solid fraction against the
+ * Fourier number (Fig. 13).  FP64 sums of the FP32 fields in a fixed order
+ * (deterministic).  col[LBF_NCOL * nx] (profile-major, indexed by x):
+ *   LBF_COL_ICE      sum over y of the ice fraction f_s;
+ *   LBF_COL_PCM      sum over y of the phase-change fraction chi (liquid and
+ *                    ice of the phase-change material);
+ *   LBF_COL_PCM_TOP  highest y at which chi crosses 1/2 from above (linear
+ *                    interpolation between rows y and y + 1; ny - 1 when the
+ *                    top row is at or above 1/2; -1 when no node is);
+ *   LBF_COL_ICE_TOP  the same for f_s (the freezing front of the column).
+ * row[LBF_NROW * ny] (indexed by y):
+ *   LBF_ROW_ICE, LBF_ROW_PCM  sums over x of f_s and of chi;
+ *   LBF_ROW_PCM_LEFT / _RIGHT the outermost 1/2-crossings of chi in the row:
+ *                    the leftmost rise and the rightmost fall (linear
+ *                    interpolation; the edge node itself when it is at or
+ *                    above 1/2; -1 when no node is);
+ *   LBF_ROW_ICE_LEFT / _RIGHT the same for f_s.
+ * Rows and columns are ordered bottom to top and left to right whether or
+ * not the axis is periodic.  dst_on_device selects device or host outputs;
+ * synchronises the stream. */
+enum { LBF_COL_ICE = 0, LBF_COL_PCM = 1, LBF_COL_PCM_TOP = 2, LBF_COL_ICE_TOP = 3, LBF_NCOL = 4 };
+enum {
+  LBF_ROW_ICE = 0, LBF_ROW_PCM = 1, LBF_ROW_PCM_LEFT = 2, LBF_ROW_PCM_RIGHT = 3,
+  LBF_ROW_ICE_LEFT = 4, LBF_ROW_ICE_RIGHT = 5, LBF_NROW = 6
+};
+int lbf_profiles(lbf_sim* sim, double* col, double* row, int32_t dst_on_device);
+
 /* Launch shape of the step kernel: threads per block along x (64, 128, 256)
  * and rows per block along y (>= 1).  Defaults are chosen at creation. */
 int lbf_set_tile(lbf_sim* sim, int32_t tile_x, int32_t tile_y);

@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "liblbf.so")
-SOURCES = [os.path.join(CSRC, f) for f in ("lbf_api.hip", "lbf_adjoint.hip")]
+SOURCES = [os.path.join(CSRC, f) for f in ("lbf_api.hip", "lbf_adjoint.hip", "lbf_observe.hip")]
 HEADERS = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hpp", ".h"))] + [
     os.path.join(INCLUDE, "lbf.h")]
 

@@ -51,6 +51,11 @@ Layout make_layout(int nx, int ny) {
   L.red[0] = take(rb);
   L.red[1] = take(rb);
   L.redfinal = take(2 * NRED * sizeof(double));
+  // column-profile partials (4 per column and chunk of rows), then the
+  // column and row profiles
+  const size_t nchunk = ((size_t)ny + kProfileChunk - 1) / kProfileChunk;
+  L.prof = take((nchunk * nx * 4 + LBF_NCOL * (size_t)nx + LBF_NROW * (size_t)ny) *
+                sizeof(double));
   L.total = off;
   return L;
 }

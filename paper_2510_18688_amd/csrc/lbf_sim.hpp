@@ -35,8 +35,11 @@ constexpr long long kMaxPlane = (0xFFFFFFFFLL / (4LL * 27)) / 64 * 64;
 // Worst-case number of per-block partial sums: 64-wide strips, 1 row each.
 inline size_t max_blocks(int nx, int ny) { return ((size_t)(nx + 63) / 64) * (size_t)ny; }
 
+// Rows per chunk of the column-profile partial sums.
+constexpr int kProfileChunk = 64;
+
 struct Layout {
-  size_t dist[2], lag[2], stat, fields, wall, red[2], redfinal, total;
+  size_t dist[2], lag[2], stat, fields, wall, red[2], redfinal, prof, total;
   int wstride;
 };
 

@@ -28,7 +28,9 @@ EXPORTS = ["lbf_workspace_bytes", "lbf_create", "lbf_set_geometry", "lbf_set_wal
            "lbf_destroy", "lbf_batch_create", "lbf_batch_set_tile", "lbf_batch_step",
            "lbf_batch_set_timing", "lbf_batch_last_step_ms", "lbf_batch_items",
            "lbf_batch_destroy", "lbf_tape_bytes", "lbf_tape_create", "lbf_tape_segment",
-           "lbf_tape_forward", "lbf_tape_backward", "lbf_tape_destroy"]
+           "lbf_tape_forward", "lbf_tape_backward", "lbf_tape_destroy", "lbf_profiles"]
+COLS = ["ice", "pcm", "pcm_top", "ice_top"]
+ROWS = ["ice", "pcm", "pcm_left", "pcm_right", "ice_left", "ice_right"]
 
 ERRORS = {-1: "LBF_EINVAL", -2: "LBF_EHIP", -3: "LBF_ESTATE", -4: "LBF_EUNSTABLE",
           -5: "LBF_ENOMEM"}
@@ -106,6 +108,7 @@ def load(path: str = LIB_PATH):
     L.lbf_tape_forward.argtypes = [vp]
     L.lbf_tape_backward.argtypes = [vp, vp, vp, vp, i32, vp, vp, i32]
     L.lbf_tape_destroy.argtypes = [vp]
+    L.lbf_profiles.argtypes = [vp, vp, vp, i32]
     for name in EXPORTS:
         getattr(L, name)
     _lib = L
@@ -263,6 +266,16 @@ class Sim:
         if rc != 0 and (check_stable or rc != -4):
             check(rc)
         return dict(zip(REDS, list(out)))
+
+    def profiles(self) -> Dict[str, Dict[str, np.ndarray]]:
+        """Column and row profiles of the current state (FP64): {"col": {ice,
+        pcm, pcm_top, ice_top} each [nx], "row": {ice, pcm, pcm_left,
+        pcm_right, ice_left, ice_right} each [ny]}."""
+        col = np.empty(len(COLS) * self.nx)
+        row = np.empty(len(ROWS) * self.ny)
+        check(_lib.lbf_profiles(self.h, C.c_void_p(col.ctypes.data), C.c_void_p(row.ctypes.data), 0))
+        return {"col": {k: col[i * self.nx:(i + 1) * self.nx] for i, k in enumerate(COLS)},
+                "row": {k: row[i * self.ny:(i + 1) * self.ny] for i, k in enumerate(ROWS)}}
 
     def state_bytes(self) -> int:
         return int(_lib.lbf_state_bytes(self.h))
