@@ -1,0 +1,98 @@
+/*
+ * liblbf, three-dimensional lattice: the coupled freezing step of
+ * arXiv 2510.18688 on the D3Q19 lattice (Sec. 3.1 gives the nineteen
+ * velocities and weights; the flow, phase-field and enthalpy schemes of
+ * Sec. 3.1-3.3 are written for vectors of any dimension).
+ *
+ * Conventions as in lbf.h: a lattice has nx * ny * nz nodes; node (x, y, z)
+ * of a 3D field is element (z * ny + y) * nx + x.  Faces, in every per-face
+ * array: 0 x-low, 1 x-high, 2 y-low, 3 y-high, 4 z-low, 5 z-high; walls sit
+ * half-way outside the first and last node.  Float fields are IEEE binary32;
+ * every call returns LBF_OK or a negative LBF_* code with the message in
+ * lbf_last_error(); calls are ordered on the simulation's HIP stream.
+ *
+ * Differences from the two-dimensional entry points: a Dirichlet face takes
+ * one temperature (set in the parameters); a link that leaves through
+ * several walls takes the z face, else the y face, else the x face; the step
+ * budget entries of the reduction are not tracked.
+ */
+#ifndef LBF3_H
+#define LBF3_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include "lbf.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* read-out fields of lbf3_read_fields, field-major */
+enum {
+  LBF3_FIELD_PHI = 0, LBF3_FIELD_T, LBF3_FIELD_FL, LBF3_FIELD_FS, LBF3_FIELD_UX,
+  LBF3_FIELD_UY, LBF3_FIELD_UZ, LBF3_FIELD_P, LBF3_FIELD_RHOH, LBF3_FIELD_MU,
+  LBF3_FIELD_C, LBF3_FIELD_CHI, LBF3_FIELD_RHO, LBF3_FIELD_PHIHAT, LBF3_NFIELDS
+};
+
+typedef struct lbf3_params {
+  int32_t nx, ny, nz;          /* lattice size, each >= 1 */
+  int32_t periodic[3];         /* per axis: 1 periodic, 0 walls */
+  int32_t thermal_bc[6];       /* per face: LBF_ADIABATIC or LBF_DIRICHLET */
+  int32_t latch_fs, h_src_tau_a, substrate_fixed, reserved;
+  double rho_l, rho_g, rho_s;
+  double mu_l, mu_g, mu_s;
+  double lam_l, lam_g, lam_s;
+  double cp_l, cp_g, cp_s;
+  double latent, T_m;
+  double sigma, eps;
+  double mobility;
+  double cos_psi;
+  double rho_ref;
+  double T_substrate;
+  double pcm_floor;
+  double wall_T[6];            /* temperature of each Dirichlet face */
+} lbf3_params;
+
+typedef struct lbf3_sim lbf3_sim;
+
+/* Device bytes of one simulation's workspace, 0 for invalid sizes and for
+ * lattices above the addressing limit. */
+size_t lbf3_workspace_bytes(int32_t nx, int32_t ny, int32_t nz);
+
+/* Create on HIP stream `stream` (NULL: default stream); workspace as in
+ * lbf_create (caller-owned, 256-byte aligned, or NULL for a library
+ * allocation).  LBF_EINVAL for the parameter sets lbf_create rejects and
+ * for lattices above the 56.5 M-node addressing limit. */
+int lbf3_create(const lbf3_params* params, void* stream, void* workspace,
+                size_t workspace_bytes, lbf3_sim** out);
+
+/* phi0 and cos(theta), nx * ny * nz floats each; lap(phi0) is computed. */
+int lbf3_set_geometry(lbf3_sim* sim, const float* phi0, const float* cos_theta,
+                      int32_t on_device);
+
+/* Initial state from phi and T (u = 0, p = 0, equilibria, PCM liquid). */
+int lbf3_init_fields(lbf3_sim* sim, const float* phi, const float* T, int32_t on_device);
+
+/* Advance nsteps steps (two kernels per step: moments, then the step). */
+int lbf3_step(lbf3_sim* sim, int32_t nsteps);
+
+/* Every read-out field (LBF3_NFIELDS * nx * ny * nz floats, field-major). */
+int lbf3_read_fields(lbf3_sim* sim, float* dst, int32_t dst_on_device);
+
+/* FP64 sums in lbf.h's LBF_RED_* order: sum g, sum h, sum f_s, sum of the
+ * liquid PCM, max |u|, non-finite count; entries 6-9 (step budget) are 0;
+ * step count.  Returns LBF_EUNSTABLE (after filling out) like lbf_reduce. */
+int lbf3_reduce(lbf3_sim* sim, double* out);
+
+/* HIP-event timing of the step kernels: average milliseconds per step of
+ * the last lbf3_step call (0 if timing is off). */
+int lbf3_set_timing(lbf3_sim* sim, int32_t on);
+double lbf3_last_step_ms(const lbf3_sim* sim);
+
+void lbf3_destroy(lbf3_sim* sim);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

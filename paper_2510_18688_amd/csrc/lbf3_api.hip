@@ -1,0 +1,565 @@
+// C ABI of the three-dimensional (D3Q19) coupled step (contracts in
+// include/lbf3.h).  Two kernels per step, one node per lane: the moments pass
+// pulls g and h and stores phi, f_s and rho for the stencils; the step pass
+// pulls f, g and h, accumulates the 3D stencils from those planes, collides
+// and stores the next state.  Workgroups are dealt to the XCDs in contiguous
+// bands of nodes so that the y and z neighbours a band reads stay in one L2.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "lbf3.h"
+#include "lbf3_device.hpp"
+#include "lbf_sim.hpp"
+#include "lbf_step.hpp"
+
+using namespace lbf3;
+using lbfi::fail;
+
+namespace {
+
+constexpr size_t kAlign3 = 256;
+size_t up3(size_t v, size_t a) { return (v + a - 1) / a * a; }
+// 19 planes per buffer resource with 32-bit byte offsets
+constexpr long long kMaxNodes3 = (0xFFFFFFFFLL / (4LL * NQ)) / 64 * 64;
+constexpr int kRed3 = 6;   // sum g, sum h, sum f_s, liquid PCM, max |u|, non-finite
+
+struct Layout3 {
+  size_t dist[2], lag[2], stat, mom, fields, red, redfinal, total;
+  size_t P;
+  int nblocks;
+};
+
+Layout3 make_layout3(int nx, int ny, int nz) {
+  Layout3 L{};
+  const size_t n = (size_t)nx * ny * nz;
+  L.P = up3(n, 64);
+  const size_t pb = L.P * sizeof(float);
+  L.nblocks = (int)((n + 255) / 256);
+  size_t off = 0;
+  auto take = [&](size_t b) {
+    size_t o = off;
+    off = up3(off + b, kAlign3);
+    return o;
+  };
+  L.dist[0] = take(NDIST * pb);
+  L.dist[1] = take(NDIST * pb);
+  L.lag[0] = take(NLAG * pb);
+  L.lag[1] = take(NLAG * pb);
+  L.stat = take(NSTAT * pb);
+  L.mom = take(3 * pb);
+  L.fields = take(NFIELD * pb);
+  L.red = take((size_t)L.nblocks * kRed3 * sizeof(double));
+  L.redfinal = take(kRed3 * sizeof(double));
+  L.total = off;
+  return L;
+}
+
+__device__ __forceinline__ void coords(const Geo3& G, int k, int& x, int& y, int& z) {
+  x = k % G.n[0];
+  const int r = k / G.n[0];
+  y = r % G.n[1];
+  z = r / G.n[1];
+}
+
+__device__ __forceinline__ int node_of_block(int nblocks) {
+  return lbf::xcd_tile(blockIdx.x, nblocks) * 256 + threadIdx.x;
+}
+
+__global__ __launch_bounds__(256) void k3_lap_static(Geo3 G, float* stat, int N) {
+  const int k = blockIdx.x * 256 + threadIdx.x;
+  if (k >= N) return;
+  int x, y, z;
+  coords(G, k, x, y, z);
+  const float* phi0 = stat + ST_PHI0 * (size_t)G.P;
+  const float c = phi0[k];
+  float lap = 0.0f;
+#pragma unroll
+  for (int i = 1; i < NQ; ++i) {
+    const int xx = nb3(x + cx(i), G.n[0], G.per[0]), yy = nb3(y + cy(i), G.n[1], G.per[1]);
+    const int zz = nb3(z + cz(i), G.n[2], G.per[2]);
+    lap += wgt(i) * (phi0[((size_t)zz * G.n[1] + yy) * G.n[0] + xx] - c);
+  }
+  stat[ST_LAP0 * (size_t)G.P + k] = 6.0f * lap;
+}
+
+// Equilibria of the initial state in post-stream form (tmp: 57 planes);
+// `in` holds phi (plane 0) and T (plane 1).
+__global__ __launch_bounds__(256) void k3_init_eq(Geo3 G, Phys ph, const float* stat,
+                                                  const float* in, float* tmp, int N) {
+  const int k = blockIdx.x * 256 + threadIdx.x;
+  if (k >= N) return;
+  int x, y, z;
+  coords(G, k, x, y, z);
+  const size_t P = G.P;
+  const float pc = in[k];
+  float lap = 0.0f;
+#pragma unroll
+  for (int i = 1; i < NQ; ++i) {
+    const int xx = nb3(x + cx(i), G.n[0], G.per[0]), yy = nb3(y + cy(i), G.n[1], G.per[1]);
+    const int zz = nb3(z + cz(i), G.n[2], G.per[2]);
+    lap += wgt(i) * (in[((size_t)zz * G.n[1] + yy) * G.n[0] + xx] - pc);
+  }
+  lap *= 6.0f;
+  const float phi0 = stat[ST_PHI0 * P + k];
+  const float mu = lbf::chem_pot(ph, pc, lap, phi0, stat[ST_CTH * P + k], stat[ST_LAP0 * P + k],
+                                 0.0f, 0.0f);
+  const float C = lbf::clampf(0.5f * (1.0f - phi0 + pc), 0.0f, 1.0f);
+  const float Cp = lbf::clampf((C - ph.pcm_floor) * ph.inv_pcm_span, 0.0f, 1.0f);
+  const float chi = lbf::clampf(Cp, 0.0f, 1.0f - phi0);
+  const float Kliq = lbf::zeta(phi0, C, ph.rho_s, ph.rho_l, ph.rho_g) *
+                     lbf::zeta(phi0, C, ph.cp_s, ph.cp_l, ph.cp_g);
+  const float Tk = in[P + k];
+  const float rhoH = Kliq * (Tk - ph.T_m) + Kliq * ph.T_m + chi * ph.rho_l * ph.latent;
+  const float ET = ph.Eref * Tk;
+#pragma unroll
+  for (int i = 0; i < NQ; ++i) {
+    tmp[i * P + k] = 0.0f;
+    tmp[(NQ + i) * P + k] = (i == 0 ? pc : 0.0f) + (wgt(i) - (i == 0 ? 1.0f : 0.0f)) * mu;
+    tmp[(2 * NQ + i) * P + k] = (i == 0) ? rhoH - ET + wgt(0) * ET : wgt(i) * ET;
+  }
+}
+
+// Inverse of the pull: post-collision populations whose pull gives `tmp`;
+// the rest populations become the high parts of their float-float storage.
+__global__ __launch_bounds__(256) void k3_unstream(Geo3 G, Phys ph, const float* tmp, float* dst,
+                                                   float* lag, int N) {
+  const int k = blockIdx.x * 256 + threadIdx.x;
+  if (k >= N) return;
+  int x, y, z;
+  coords(G, k, x, y, z);
+  const size_t P = G.P;
+  dst[k] = tmp[k];
+  lag[LAG_GHI * P + k] = tmp[NQ * P + k];
+  lag[LAG_HHI * P + k] = tmp[2 * NQ * P + k];
+  dst[NQ * P + k] = 0.0f;
+  dst[2 * NQ * P + k] = 0.0f;
+  for (int j = 1; j < NQ; ++j) {
+    // destination of population j leaving the node; the face of its wall
+    const int v[3] = {x + cx(j), y + cy(j), z + cz(j)};
+    int d[3];
+    int face = -1;
+    for (int a = 2; a >= 0; --a) {
+      d[a] = v[a];
+      if (v[a] < 0 || v[a] >= G.n[a]) {
+        if (G.per[a]) d[a] = v[a] < 0 ? v[a] + G.n[a] : v[a] - G.n[a];
+        else if (face < 0) face = 2 * a + (v[a] < 0 ? 0 : 1);
+      }
+    }
+    if (face < 0) {
+      const size_t dk = ((size_t)d[2] * G.n[1] + d[1]) * G.n[0] + d[0];
+      for (int b = 0; b < 3; ++b) dst[(b * NQ + j) * P + k] = tmp[(b * NQ + j) * P + dk];
+    } else {
+      const int i = opp(j);   // the population the node pulls back
+      dst[j * P + k] = tmp[i * P + k];
+      dst[(NQ + j) * P + k] = tmp[(NQ + i) * P + k];
+      const float hb = tmp[(2 * NQ + i) * P + k];
+      dst[(2 * NQ + j) * P + k] =
+          ((G.tmask >> face) & 1) ? 2.0f * wgt(i) * ph.Eref * G.Tw[face] - hb : hb;
+    }
+  }
+}
+
+// Moments pass: phi, f_s, rho of the state read, for the stencils.
+__global__ __launch_bounds__(256) void k3_moments(Geo3 G, Phys ph, BufArgs3 A, int N, int nblocks) {
+  const int k = node_of_block(nblocks);
+  if (k >= N) return;
+  int x, y, z;
+  coords(G, k, x, y, z);
+  const Bufs3 B = make_bufs3(A, G.P);
+  Pull19 n;
+  pull19(G, x, y, z, n);
+  float gv[NQ], hv[NQ];
+  pull_gh3(G, ph, B, n, gv, hv);
+  Mom m;
+  node_moments3(G, ph, B, (uint32_t)k, gv, hv, lbf::ldp(B.stat, ST_PHI0, G.P, k), m);
+  lbf::stp(B.mom, 0, G.P, k, m.phi);
+  lbf::stp(B.mom, 1, G.P, k, m.fs);
+  lbf::stp(B.mom, 2, G.P, k, m.rho);
+}
+
+// Step pass (READOUT = false) or read-out of the fields with FP64 block sums
+// (READOUT = true).
+template <bool READOUT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) void k3_step(
+    Geo3 G, Phys ph, BufArgs3 A, float* fields, double* red, int N, int nblocks) {
+  const int k = node_of_block(nblocks);
+  const bool act = k < N;
+  double v[kRed3] = {0, 0, 0, 0, 0, 0};
+  if (act) {
+    int x, y, z;
+    coords(G, k, x, y, z);
+    const Bufs3 B = make_bufs3(A, G.P);
+    const size_t P = G.P;
+    Pull19 n;
+    pull19(G, x, y, z, n);
+    float gv[NQ], hv[NQ], fv[NQ];
+    pull_gh3(G, ph, B, n, gv, hv);
+    const float phi0 = lbf::ldp(B.stat, ST_PHI0, G.P, k);
+    Mom m;
+    node_moments3(G, ph, B, (uint32_t)k, gv, hv, phi0, m);
+    Stencil3 S;
+    stencils3(G, B, x, y, z, m.phi, m.fs, S);
+    pull_f3(G, B, n, fv);
+    const float jprev[3] = {lbf::ldp(B.lin, LAG_JX, G.P, k), lbf::ldp(B.lin, LAG_JY, G.P, k),
+                            lbf::ldp(B.lin, LAG_JZ, G.P, k)};
+    const float ref_h = lbf::ldp(B.lin, LAG_HHI, G.P, k);
+    Post3 o;
+    collide3(ph, m, S, phi0, lbf::ldp(B.stat, ST_CTH, G.P, k), lbf::ldp(B.stat, ST_LAP0, G.P, k),
+             jprev, ref_h, fv, gv, hv, o);
+    if (!READOUT) {
+#pragma unroll
+      for (int i = 0; i < NQ; ++i) {
+        lbf::stp(B.fout, i, G.P, k, fv[i]);
+        lbf::stp(B.gout, i, G.P, k, gv[i]);
+        lbf::stp(B.hout, i, G.P, k, hv[i]);
+      }
+      lbf::stp(B.lout, LAG_FS, G.P, k, m.fs);
+      lbf::stp(B.lout, LAG_Q, G.P, k, o.Q);
+      lbf::stp(B.lout, LAG_JX, G.P, k, o.j[0]);
+      lbf::stp(B.lout, LAG_JY, G.P, k, o.j[1]);
+      lbf::stp(B.lout, LAG_JZ, G.P, k, o.j[2]);
+      lbf::stp(B.lout, LAG_P, G.P, k, o.p);
+      lbf::stp(B.lout, LAG_GHI, G.P, k, o.ghi);
+      lbf::stp(B.lout, LAG_HHI, G.P, k, o.hhi);
+    } else {
+      const float mu = lbf::chem_pot(ph, m.phi, S.lphi, phi0, lbf::ldp(B.stat, ST_CTH, G.P, k),
+                                     lbf::ldp(B.stat, ST_LAP0, G.P, k), m.fs, S.lfs);
+      const float out[NFIELD] = {m.phi, m.T, 1.0f - m.fs, m.fs, o.u[0], o.u[1], o.u[2], o.p,
+                                 m.rhoH, mu, m.C, m.chi, m.rho, m.ref_g + m.sg};
+#pragma unroll
+      for (int f = 0; f < NFIELD; ++f) fields[f * P + k] = out[f];
+      const float um = sqrtf(o.u[0] * o.u[0] + o.u[1] * o.u[1] + o.u[2] * o.u[2]);
+      v[0] = (double)m.ref_g + (double)m.sg;
+      v[1] = (double)ref_h + (double)m.sh;
+      v[2] = m.fs;
+      v[3] = m.chi - m.fs;
+      v[4] = um;
+      v[5] = (!isfinite(m.phi) || !isfinite(m.T) || !isfinite(um) || !isfinite(o.p)) ? 1.0 : 0.0;
+    }
+  }
+  if (READOUT) {
+    __shared__ double s[4][kRed3];
+#pragma unroll
+    for (int j = 0; j < kRed3; ++j)
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        const double t = __shfl_down(v[j], off, 64);
+        v[j] = (j == 4) ? fmax(v[j], t) : v[j] + t;
+      }
+    const int l = threadIdx.x;
+    if ((l & 63) == 0)
+      for (int j = 0; j < kRed3; ++j) s[l >> 6][j] = v[j];
+    __syncthreads();
+    if (l < kRed3) {
+      double t = s[0][l];
+      for (int w = 1; w < 4; ++w) t = (l == 4) ? fmax(t, s[w][l]) : t + s[w][l];
+      red[(size_t)lbf::xcd_tile(blockIdx.x, nblocks) * kRed3 + l] = t;
+    }
+  }
+}
+
+__global__ void k3_reduce_final(const double* part, int nblocks, double* out) {
+  __shared__ double s[256];
+  for (int j = 0; j < kRed3; ++j) {
+    double v = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += blockDim.x) {
+      const double t = part[(size_t)b * kRed3 + j];
+      v = (j == 4) ? fmax(v, t) : v + t;
+    }
+    s[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w)
+        s[threadIdx.x] = (j == 4) ? fmax(s[threadIdx.x], s[threadIdx.x + w])
+                                  : s[threadIdx.x] + s[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) out[j] = s[0];
+    __syncthreads();
+  }
+}
+
+int validate3(const lbf3_params* p) {
+  if (!p) return fail(LBF_EINVAL, "params is NULL");
+  if (p->nx < 1 || p->ny < 1 || p->nz < 1)
+    return fail(LBF_EINVAL, "lattice size %d x %d x %d", p->nx, p->ny, p->nz);
+  if ((long long)p->nx * p->ny * p->nz > kMaxNodes3)
+    return fail(LBF_EINVAL, "lattice of %lld nodes exceeds the %lld-node limit",
+                (long long)p->nx * p->ny * p->nz, kMaxNodes3);
+  const double pos[] = {p->rho_l, p->rho_g, p->rho_s, p->mu_l, p->mu_g, p->mu_s, p->lam_l,
+                        p->lam_g, p->lam_s, p->cp_l, p->cp_g, p->cp_s, p->eps, p->mobility,
+                        p->rho_ref};
+  for (double v : pos)
+    if (!(v > 0.0) || !std::isfinite(v))
+      return fail(LBF_EINVAL, "densities, viscosities, conductivities, heat capacities, eps, "
+                              "mobility and rho_ref must be positive and finite");
+  if (!(p->pcm_floor >= 0.0 && p->pcm_floor < 1.0))
+    return fail(LBF_EINVAL, "pcm_floor must be in [0, 1) (got %g)", p->pcm_floor);
+  if (!(p->latent >= 0.0) || !(p->sigma >= 0.0))
+    return fail(LBF_EINVAL, "latent heat and surface tension must be non-negative");
+  for (int f = 0; f < 6; ++f)
+    if (p->thermal_bc[f] != LBF_ADIABATIC && p->thermal_bc[f] != LBF_DIRICHLET)
+      return fail(LBF_EINVAL, "thermal_bc[%d] = %d", f, p->thermal_bc[f]);
+  const double cpref = 2.0 * p->cp_s * p->cp_l / (p->cp_s + p->cp_l);
+  const double kmin = std::min({p->rho_l, p->rho_g, p->rho_s}) *
+                      std::min({p->cp_l, p->cp_g, p->cp_s});
+  if (p->rho_ref * cpref > kmin * (1.0 + 1e-12))
+    return fail(LBF_EINVAL, "rho_ref * C_p,ref = %g exceeds the smallest nodal heat capacity %g: "
+                            "the enthalpy scheme would be unstable", p->rho_ref * cpref, kmin);
+  return LBF_OK;
+}
+
+void fill_phys3(const lbf3_params* p, Phys& ph) {
+  ph.rho_l = (float)p->rho_l; ph.rho_g = (float)p->rho_g; ph.rho_s = (float)p->rho_s;
+  ph.mu_l = (float)p->mu_l; ph.mu_g = (float)p->mu_g; ph.mu_s = (float)p->mu_s;
+  ph.lam_l = (float)p->lam_l; ph.lam_g = (float)p->lam_g; ph.lam_s = (float)p->lam_s;
+  ph.cp_l = (float)p->cp_l; ph.cp_g = (float)p->cp_g; ph.cp_s = (float)p->cp_s;
+  ph.latent = (float)p->latent;
+  ph.T_m = (float)p->T_m;
+  ph.cos_psi = (float)p->cos_psi;
+  ph.T_sub = (float)p->T_substrate;
+  ph.a3 = (float)(3.0 * p->sigma / p->eps);
+  ph.kap = (float)(3.0 * p->eps * p->sigma / 8.0);
+  ph.tau_g = (float)(3.0 * p->mobility + 0.5);
+  ph.inv_tau_g = (float)(1.0 / (3.0 * p->mobility + 0.5));
+  ph.pg = (float)(1.0 - 0.5 / (3.0 * p->mobility + 0.5));
+  const double Eref = p->rho_ref * 2.0 * p->cp_s * p->cp_l / (p->cp_s + p->cp_l);
+  ph.Eref = (float)Eref;
+  ph.three_over_Eref = (float)(3.0 / Eref);
+  ph.mdot_coef = (float)(1.0 - p->rho_s / p->rho_l);
+  ph.pcm_floor = (float)p->pcm_floor;
+  ph.inv_pcm_span = (float)(1.0 / (1.0 - p->pcm_floor));
+  ph.latch = p->latch_fs ? 1 : 0;
+  ph.src_tau_a = p->h_src_tau_a ? 1 : 0;
+  ph.subfix = p->substrate_fixed ? 1 : 0;
+}
+
+}  // namespace
+
+struct lbf3_sim {
+  lbf3_params prm;
+  Geo3 G;
+  Phys ph;
+  Layout3 L;
+  hipStream_t stream;
+  char* ws;
+  bool owns_ws, have_geo, have_init, timing;
+  int cur;
+  long long step;
+  double last_ms;
+  hipEvent_t ev0, ev1;
+  double* host_red;
+};
+
+namespace {
+
+float* fp3(lbf3_sim* s, size_t off) { return reinterpret_cast<float*>(s->ws + off); }
+
+int N3(const lbf3_sim* s) { return s->G.n[0] * s->G.n[1] * s->G.n[2]; }
+
+BufArgs3 args3(lbf3_sim* s, int c) {
+  BufArgs3 A{};
+  A.din = fp3(s, s->L.dist[c]);
+  A.dout = fp3(s, s->L.dist[1 - c]);
+  A.lin = fp3(s, s->L.lag[c]);
+  A.lout = fp3(s, s->L.lag[1 - c]);
+  A.stat = fp3(s, s->L.stat);
+  A.mom = fp3(s, s->L.mom);
+  return A;
+}
+
+int copy3(lbf3_sim* s, void* dst, const void* src, size_t bytes, int on_device) {
+  if (hipMemcpyAsync(dst, src, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                     s->stream) != hipSuccess)
+    return fail(LBF_EHIP, "hipMemcpyAsync failed");
+  if (!on_device && hipStreamSynchronize(s->stream) != hipSuccess)
+    return fail(LBF_EHIP, "hipStreamSynchronize failed");
+  return LBF_OK;
+}
+
+int launch_pair(lbf3_sim* s, bool readout) {
+  const int N = N3(s), nb = s->L.nblocks;
+  BufArgs3 A = args3(s, s->cur);
+  hipLaunchKernelGGL(k3_moments, dim3(nb), dim3(256), 0, s->stream, s->G, s->ph, A, N, nb);
+  HIP_TRY(hipGetLastError());
+  if (readout)
+    hipLaunchKernelGGL((k3_step<true>), dim3(nb), dim3(256), 0, s->stream, s->G, s->ph, A,
+                       fp3(s, s->L.fields), reinterpret_cast<double*>(s->ws + s->L.red), N, nb);
+  else
+    hipLaunchKernelGGL((k3_step<false>), dim3(nb), dim3(256), 0, s->stream, s->G, s->ph, A,
+                       (float*)nullptr, (double*)nullptr, N, nb);
+  HIP_TRY(hipGetLastError());
+  return LBF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t lbf3_workspace_bytes(int32_t nx, int32_t ny, int32_t nz) {
+  if (nx < 1 || ny < 1 || nz < 1) return 0;
+  if ((long long)nx * ny * nz > kMaxNodes3) return 0;
+  return make_layout3(nx, ny, nz).total;
+}
+
+int lbf3_create(const lbf3_params* params, void* stream, void* workspace, size_t workspace_bytes,
+                lbf3_sim** out) {
+  if (!out) return fail(LBF_EINVAL, "out is NULL");
+  *out = nullptr;
+  int rc = validate3(params);
+  if (rc) return rc;
+  lbf3_sim* s = new lbf3_sim();
+  s->prm = *params;
+  s->G.n[0] = params->nx; s->G.n[1] = params->ny; s->G.n[2] = params->nz;
+  s->G.tmask = 0;
+  for (int a = 0; a < 3; ++a) s->G.per[a] = params->periodic[a] ? 1 : 0;
+  for (int f = 0; f < 6; ++f) {
+    if (params->thermal_bc[f] == LBF_DIRICHLET) s->G.tmask |= 1 << f;
+    s->G.Tw[f] = (float)params->wall_T[f];
+  }
+  fill_phys3(params, s->ph);
+  s->L = make_layout3(params->nx, params->ny, params->nz);
+  s->G.P = (int)s->L.P;
+  s->stream = (hipStream_t)stream;
+  if (workspace) {
+    if (workspace_bytes < s->L.total || (uintptr_t)workspace % kAlign3) {
+      delete s;
+      return fail(LBF_ENOMEM, "workspace too small or not 256-byte aligned");
+    }
+    s->ws = (char*)workspace;
+  } else {
+    if (hipMalloc((void**)&s->ws, s->L.total) != hipSuccess) {
+      delete s;
+      return fail(LBF_ENOMEM, "hipMalloc failed");
+    }
+    s->owns_ws = true;
+  }
+  if (hipHostMalloc((void**)&s->host_red, kRed3 * sizeof(double), hipHostMallocDefault) !=
+          hipSuccess ||
+      hipEventCreate(&s->ev0) != hipSuccess || hipEventCreate(&s->ev1) != hipSuccess) {
+    lbf3_destroy(s);
+    return fail(LBF_EHIP, "host buffer / event creation failed");
+  }
+  *out = s;
+  return LBF_OK;
+}
+
+void lbf3_destroy(lbf3_sim* s) {
+  if (!s) return;
+  if (s->stream) (void)hipStreamSynchronize(s->stream);
+  else (void)hipDeviceSynchronize();
+  if (s->owns_ws && s->ws) (void)hipFree(s->ws);
+  if (s->host_red) (void)hipHostFree(s->host_red);
+  if (s->ev0) (void)hipEventDestroy(s->ev0);
+  if (s->ev1) (void)hipEventDestroy(s->ev1);
+  delete s;
+}
+
+int lbf3_set_geometry(lbf3_sim* s, const float* phi0, const float* cth, int32_t on_device) {
+  if (!s || !phi0 || !cth) return fail(LBF_EINVAL, "NULL argument");
+  const size_t n = (size_t)N3(s);
+  float* stat = fp3(s, s->L.stat);
+  int rc = copy3(s, stat + ST_PHI0 * s->L.P, phi0, n * sizeof(float), on_device);
+  if (rc) return rc;
+  rc = copy3(s, stat + ST_CTH * s->L.P, cth, n * sizeof(float), on_device);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k3_lap_static, dim3(s->L.nblocks), dim3(256), 0, s->stream, s->G, stat,
+                     N3(s));
+  HIP_TRY(hipGetLastError());
+  s->have_geo = true;
+  s->have_init = false;
+  return LBF_OK;
+}
+
+int lbf3_init_fields(lbf3_sim* s, const float* phi, const float* T, int32_t on_device) {
+  if (!s || !phi || !T) return fail(LBF_EINVAL, "NULL argument");
+  if (!s->have_geo) return fail(LBF_ESTATE, "lbf3_set_geometry must precede lbf3_init_fields");
+  const size_t n = (size_t)N3(s);
+  float* stage = fp3(s, s->L.fields);
+  int rc = copy3(s, stage, phi, n * sizeof(float), on_device);
+  if (rc) return rc;
+  rc = copy3(s, stage + s->L.P, T, n * sizeof(float), on_device);
+  if (rc) return rc;
+  s->cur = 0;
+  float* tmp = fp3(s, s->L.dist[1]);
+  hipLaunchKernelGGL(k3_init_eq, dim3(s->L.nblocks), dim3(256), 0, s->stream, s->G, s->ph,
+                     (const float*)fp3(s, s->L.stat), (const float*)stage, tmp, N3(s));
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemsetAsync(fp3(s, s->L.lag[0]), 0, NLAG * s->L.P * sizeof(float), s->stream));
+  hipLaunchKernelGGL(k3_unstream, dim3(s->L.nblocks), dim3(256), 0, s->stream, s->G, s->ph,
+                     (const float*)tmp, fp3(s, s->L.dist[0]), fp3(s, s->L.lag[0]), N3(s));
+  HIP_TRY(hipGetLastError());
+  s->step = 0;
+  s->have_init = true;
+  return LBF_OK;
+}
+
+int lbf3_step(lbf3_sim* s, int32_t nsteps) {
+  if (!s) return fail(LBF_EINVAL, "sim is NULL");
+  if (nsteps < 0) return fail(LBF_EINVAL, "nsteps %d", nsteps);
+  if (!s->have_init) return fail(LBF_ESTATE, "lbf3_init_fields must precede lbf3_step");
+  if (nsteps == 0) return LBF_OK;
+  if (s->timing) HIP_TRY(hipEventRecord(s->ev0, s->stream));
+  for (int it = 0; it < nsteps; ++it) {
+    int rc = launch_pair(s, false);
+    if (rc) return rc;
+    s->cur = 1 - s->cur;
+    s->step++;
+  }
+  if (s->timing) {
+    HIP_TRY(hipEventRecord(s->ev1, s->stream));
+    HIP_TRY(hipEventSynchronize(s->ev1));
+    float ms = 0.0f;
+    HIP_TRY(hipEventElapsedTime(&ms, s->ev0, s->ev1));
+    s->last_ms = ms / nsteps;
+  }
+  return LBF_OK;
+}
+
+int lbf3_read_fields(lbf3_sim* s, float* dst, int32_t dst_on_device) {
+  if (!s || !dst) return fail(LBF_EINVAL, "NULL argument");
+  if (!s->have_init) return fail(LBF_ESTATE, "not initialised");
+  int rc = launch_pair(s, true);
+  if (rc) return rc;
+  const size_t n = (size_t)N3(s);
+  for (int f = 0; f < NFIELD; ++f)
+    HIP_TRY(hipMemcpyAsync(dst + f * n, fp3(s, s->L.fields) + f * s->L.P, n * sizeof(float),
+                           dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                           s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  return LBF_OK;
+}
+
+int lbf3_reduce(lbf3_sim* s, double* out) {
+  if (!s || !out) return fail(LBF_EINVAL, "NULL argument");
+  if (!s->have_init) return fail(LBF_ESTATE, "not initialised");
+  int rc = launch_pair(s, true);
+  if (rc) return rc;
+  double* fin = reinterpret_cast<double*>(s->ws + s->L.redfinal);
+  hipLaunchKernelGGL(k3_reduce_final, dim3(1), dim3(256), 0, s->stream,
+                     (const double*)(s->ws + s->L.red), s->L.nblocks, fin);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(s->host_red, fin, kRed3 * sizeof(double), hipMemcpyDeviceToHost,
+                         s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  for (int j = 0; j < LBF_NRED; ++j) out[j] = 0.0;
+  for (int j = 0; j < kRed3; ++j) out[j] = s->host_red[j];
+  out[LBF_RED_STEP] = (double)s->step;
+  if (out[LBF_RED_NONFINITE] > 0 || !(out[LBF_RED_UMAX] <= 0.3))
+    return fail(LBF_EUNSTABLE, "unstable: %g non-finite nodes, max |u| = %g",
+                out[LBF_RED_NONFINITE], out[LBF_RED_UMAX]);
+  return LBF_OK;
+}
+
+int lbf3_set_timing(lbf3_sim* s, int32_t on) {
+  if (!s) return fail(LBF_EINVAL, "sim is NULL");
+  s->timing = on != 0;
+  return LBF_OK;
+}
+
+double lbf3_last_step_ms(const lbf3_sim* s) { return s ? s->last_ms : 0.0; }
+
+}  // extern "C"

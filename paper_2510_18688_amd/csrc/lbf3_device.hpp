@@ -1,0 +1,342 @@
+// Device-side building blocks of the three-dimensional (D3Q19) coupled step.
+//
+// Layout in HBM (structure of arrays, FP32, plane stride P floats, node
+// (x, y, z) at element (z ny + y) nx + x):
+//   distributions 57 planes: f_0..f_18, g_0..g_18, h_0..h_18, post-collision,
+//                 stored at the node that wrote them (pull scheme); the rest
+//                 populations g_0, h_0 hold the low parts of float-float
+//                 values whose high parts are lagged planes;
+//   lagged        8 planes: f_s, Q = rho C_p T mdot, (phi u)_x, _y, _z, p of
+//                 the previous step, high parts of g_0 and h_0;
+//   static        3 planes: phi0, cos(theta), lap(phi0).
+// The node-local moments, the chemical potential and the mixing rule are the
+// dimension-free functions of the two-dimensional step (lbf_device.hpp).
+#pragma once
+#include "lbf_device.hpp"
+
+namespace lbf3 {
+
+using lbf::Mom;
+using lbf::Phys;
+using lbf::Rsrc;
+
+constexpr int NQ = 19;
+constexpr int NDIST = 3 * NQ;
+constexpr int NLAG = 8;
+constexpr int NSTAT = 3;
+constexpr int NFIELD = 14;
+enum { LAG_FS = 0, LAG_Q, LAG_JX, LAG_JY, LAG_JZ, LAG_P, LAG_GHI, LAG_HHI };
+enum { ST_PHI0 = 0, ST_CTH = 1, ST_LAP0 = 2 };
+
+// D3Q19 (Sec. 3.1): rest, six axis directions, twelve face diagonals, in the
+// printed order; weights 1/3, 1/18, 1/36.
+__host__ __device__ constexpr int cx(int i) {
+  return (i == 1 || i == 7 || i == 9 || i == 11 || i == 13) ? 1
+         : (i == 2 || i == 8 || i == 10 || i == 12 || i == 14) ? -1 : 0;
+}
+__host__ __device__ constexpr int cy(int i) {
+  return (i == 3 || i == 7 || i == 10 || i == 15 || i == 17) ? 1
+         : (i == 4 || i == 8 || i == 9 || i == 16 || i == 18) ? -1 : 0;
+}
+__host__ __device__ constexpr int cz(int i) {
+  return (i == 5 || i == 11 || i == 14 || i == 15 || i == 18) ? 1
+         : (i == 6 || i == 12 || i == 13 || i == 16 || i == 17) ? -1 : 0;
+}
+__host__ __device__ constexpr int opp(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
+__host__ __device__ constexpr float wgt(int i) {
+  return i == 0 ? 1.0f / 3.0f : (i <= 6 ? 1.0f / 18.0f : 1.0f / 36.0f);
+}
+
+struct Geo3 {
+  int n[3];          // nx, ny, nz
+  int per[3];        // periodic flags
+  int tmask;         // bit f: face f is Dirichlet (0 x-low .. 5 z-high)
+  int P;             // plane stride (floats)
+  float Tw[6];       // face temperatures
+};
+
+struct Bufs3 {
+  Rsrc fin, gin, hin, fout, gout, hout, lin, lout, stat, mom;
+};
+
+struct BufArgs3 {
+  const float* din;
+  float* dout;
+  const float* lin;
+  float* lout;
+  const float* stat;
+  float* mom;        // 3 planes: phi, f_s, rho of the state read (moments pass)
+};
+
+__device__ __forceinline__ Bufs3 make_bufs3(const BufArgs3& a, int P) {
+  const uint32_t pb = (uint32_t)P * 4u;
+  Bufs3 B;
+  B.fin = lbf::make_rsrc(a.din, NQ * pb);
+  B.gin = lbf::make_rsrc(a.din + NQ * (size_t)P, NQ * pb);
+  B.hin = lbf::make_rsrc(a.din + 2 * NQ * (size_t)P, NQ * pb);
+  B.fout = lbf::make_rsrc(a.dout, a.dout ? NQ * pb : 0u);
+  B.gout = lbf::make_rsrc(a.dout ? a.dout + NQ * (size_t)P : nullptr, a.dout ? NQ * pb : 0u);
+  B.hout = lbf::make_rsrc(a.dout ? a.dout + 2 * NQ * (size_t)P : nullptr, a.dout ? NQ * pb : 0u);
+  B.lin = lbf::make_rsrc(a.lin, NLAG * pb);
+  B.lout = lbf::make_rsrc(a.lout, a.lout ? NLAG * pb : 0u);
+  B.stat = lbf::make_rsrc(a.stat, NSTAT * pb);
+  B.mom = lbf::make_rsrc(a.mom, 3 * pb);
+  return B;
+}
+
+// Pull sources of one node: byte offset of x - c_i (the node itself across a
+// wall), the wall masks and the face of each wall link.  A link leaving
+// through several walls takes the z face, else the y face, else the x face.
+struct Pull19 {
+  uint32_t off[NQ];
+  uint32_t k4;
+  uint32_t wmask;
+  uint8_t face[NQ];
+};
+
+__device__ __forceinline__ int src_axis(int v, int c, int n, int periodic, bool& out) {
+  int s = v - c;
+  out = false;
+  if (s < 0) {
+    if (periodic) return s + n;
+    out = true;
+    return v;
+  }
+  if (s >= n) {
+    if (periodic) return s - n;
+    out = true;
+    return v;
+  }
+  return s;
+}
+
+__device__ __forceinline__ void pull19(const Geo3& G, int x, int y, int z, Pull19& p) {
+  const uint32_t k = ((uint32_t)z * G.n[1] + y) * G.n[0] + x;
+  p.k4 = k * 4u;
+  p.wmask = 0u;
+#pragma unroll
+  for (int i = 0; i < NQ; ++i) {
+    bool ox, oy, oz;
+    const int sx = src_axis(x, cx(i), G.n[0], G.per[0], ox);
+    const int sy = src_axis(y, cy(i), G.n[1], G.per[1], oy);
+    const int sz = src_axis(z, cz(i), G.n[2], G.per[2], oz);
+    const bool w = ox || oy || oz;
+    p.off[i] = w ? p.k4 : (((uint32_t)sz * G.n[1] + sy) * G.n[0] + sx) * 4u;
+    p.wmask |= (uint32_t)w << i;
+    // the face whose rule applies: z first, then y, then x; low when c > 0
+    p.face[i] = oz ? (cz(i) > 0 ? 4 : 5) : (oy ? (cy(i) > 0 ? 2 : 3) : (cx(i) > 0 ? 0 : 1));
+  }
+}
+
+// Pulled g and h of a node (bounce-back; anti-bounce-back for h on
+// Dirichlet faces).
+__device__ __forceinline__ void pull_gh3(const Geo3& G, const Phys& ph, const Bufs3& B,
+                                         const Pull19& n, float* gv, float* hv) {
+#pragma unroll
+  for (int i = 0; i < NQ; ++i) {
+    gv[i] = lbf::ldo(B.gin, n.off[i], i, G.P);
+    hv[i] = lbf::ldo(B.hin, n.off[i], i, G.P);
+  }
+  if (n.wmask) {
+#pragma unroll
+    for (int i = 1; i < NQ; ++i) {
+      if ((n.wmask >> i) & 1u) {
+        const int j = opp(i);
+        gv[i] = lbf::ldo(B.gin, n.k4, j, G.P);
+        const float hb = lbf::ldo(B.hin, n.k4, j, G.P);
+        const int f = n.face[i];
+        hv[i] = ((G.tmask >> f) & 1) ? -hb + 2.0f * wgt(i) * ph.Eref * G.Tw[f] : hb;
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ void pull_f3(const Geo3& G, const Bufs3& B, const Pull19& n,
+                                        float* fv) {
+#pragma unroll
+  for (int i = 0; i < NQ; ++i) fv[i] = lbf::ldo(B.fin, n.off[i], i, G.P);
+  if (n.wmask) {
+#pragma unroll
+    for (int i = 1; i < NQ; ++i)
+      if ((n.wmask >> i) & 1u) fv[i] = lbf::ldo(B.fin, n.k4, opp(i), G.P);
+  }
+}
+
+// Node moments from the pulled g, h and the lagged fields.
+__device__ __forceinline__ void node_moments3(const Geo3& G, const Phys& ph, const Bufs3& B,
+                                              uint32_t k, const float* gv, const float* hv,
+                                              float phi0, Mom& m) {
+  float sg = gv[0], sh = hv[0];
+#pragma unroll
+  for (int i = 1; i < NQ; ++i) {
+    sg += gv[i];
+    sh += hv[i];
+  }
+  const float ghi = lbf::ldp(B.lin, LAG_GHI, G.P, (int)k);
+  const float hhi = lbf::ldp(B.lin, LAG_HHI, G.P, (int)k);
+  const float fsp = lbf::ldp(B.lin, LAG_FS, G.P, (int)k);
+  const float Qp = lbf::ldp(B.lin, LAG_Q, G.P, (int)k);
+  lbf::moments(ph, ghi, sg, hhi, sh, fsp, Qp, phi0, m);
+}
+
+// Neighbour index for the stencils: wrap, or the mirror ghost at a wall.
+__device__ __forceinline__ int nb3(int v, int n, int periodic) {
+  if (v < 0) return periodic ? v + n : 0;
+  if (v >= n) return periodic ? v - n : n - 1;
+  return v;
+}
+
+// Stencil sums of one node: gradients of phi, rho, p_prev; Laplacians of phi
+// and f_s (isotropic D3Q19 stencils: factor 3 for the gradient, 6 for the
+// Laplacian).
+struct Stencil3 {
+  float gph[3], gr[3], gp[3], lphi, lfs;
+};
+
+__device__ __forceinline__ void stencils3(const Geo3& G, const Bufs3& B, int x, int y, int z,
+                                          float phic, float fsc, Stencil3& S) {
+  float gph[3] = {0, 0, 0}, gr[3] = {0, 0, 0}, gp[3] = {0, 0, 0}, lphi = 0, lfs = 0;
+#pragma unroll
+  for (int i = 1; i < NQ; ++i) {
+    const int xx = nb3(x + cx(i), G.n[0], G.per[0]);
+    const int yy = nb3(y + cy(i), G.n[1], G.per[1]);
+    const int zz = nb3(z + cz(i), G.n[2], G.per[2]);
+    const uint32_t o = (((uint32_t)zz * G.n[1] + yy) * G.n[0] + xx) * 4u;
+    const float vphi = lbf::ldo(B.mom, o, 0, G.P);
+    const float vfs = lbf::ldo(B.mom, o, 1, G.P);
+    const float vrho = lbf::ldo(B.mom, o, 2, G.P);
+    const float vp = lbf::ldo(B.lin, o, LAG_P, G.P);
+    const float w = wgt(i);
+    const float c[3] = {(float)cx(i), (float)cy(i), (float)cz(i)};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      gph[a] += w * c[a] * vphi;
+      gr[a] += w * c[a] * vrho;
+      gp[a] += w * c[a] * vp;
+    }
+    lphi += w * (vphi - phic);
+    lfs += w * (vfs - fsc);
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    S.gph[a] = 3.0f * gph[a];
+    S.gr[a] = 3.0f * gr[a];
+    S.gp[a] = 3.0f * gp[a];
+  }
+  S.lphi = 6.0f * lphi;
+  S.lfs = 6.0f * lfs;
+}
+
+struct Post3 {
+  float u[3], p, Q, j[3], ghi, hhi;
+};
+
+// Collision of the three populations at one node (Sec. 3.1-3.3 in three
+// dimensions), in place on fv, gv, hv (gv[0], hv[0] as deviations from the
+// node's references); the rest populations are renormalised to float-float.
+__device__ __forceinline__ void collide3(const Phys& ph, const Mom& m, const Stencil3& S,
+                                         float phi0, float cth, float lap_phi0,
+                                         const float* jprev, float ref_h, float* fv, float* gv,
+                                         float* hv, Post3& o) {
+  const float phi = m.phi, rho = m.rho, C = m.C, fstot = m.fstot, mdot = m.mdot, T = m.T;
+  const float mu_v = lbf::zeta(fstot, C, ph.mu_s, ph.mu_l, ph.mu_g);
+  const float lam = lbf::zeta(fstot, C, ph.lam_s, ph.lam_l, ph.lam_g);
+  const float cp = lbf::zeta(fstot, C, ph.cp_s, ph.cp_l, ph.cp_g);
+  const float inv_rho = lbf::rcp(rho);
+  const float tau_f = 3.0f * mu_v * inv_rho + 0.5f;
+  const float inv_tau_a = lbf::rcp(lam * ph.three_over_Eref + 0.5f);
+  const float inv_tau_s = 2.0f - inv_tau_a;
+  const float mu = lbf::chem_pot(ph, phi, S.lphi, phi0, cth, lap_phi0, m.fs, S.lfs);
+  float F[3], mm[3] = {0, 0, 0}, snz = 0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) F[a] = mu * S.gph[a];
+#pragma unroll
+  for (int i = 0; i < NQ; ++i) {
+    mm[0] += cx(i) * fv[i];
+    mm[1] += cy(i) * fv[i];
+    mm[2] += cz(i) * fv[i];
+    if (i) snz += fv[i];
+  }
+  float u[3], fd[3], Ft[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const float us = (mm[a] + 0.5f * F[a]) * inv_rho;
+    fd[a] = -fstot * us;
+    u[a] = us + 0.5f * fd[a];
+    Ft[a] = F[a] - S.gp[a] + (1.0f / 3.0f) * S.gr[a];
+  }
+  const float Sm = rho * mdot + u[0] * S.gr[0] + u[1] * S.gr[1] + u[2] * S.gr[2];
+  const float uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+  const float uFt = u[0] * Ft[0] + u[1] * Ft[1] + u[2] * Ft[2];
+  const float w0 = wgt(0);
+  const float F0 = w0 * (Sm - 3.0f * uFt);
+  const float p = (1.0f / 3.0f) / (1.0f - w0) *
+                  (snz + 0.5f * Sm + (tau_f - 0.5f) * F0 - 1.5f * w0 * rho * uu);
+  const float j[3] = {phi * u[0], phi * u[1], phi * u[2]};
+  const float rhocp = rho * cp;
+  const float Q = rhocp * T * mdot;
+  // flow (Sec. 3.1)
+  const float ift = lbf::rcp(tau_f);
+  const float pf = 1.0f - 0.5f * ift;
+  const float rf[3] = {rho * fd[0] + F[0], rho * fd[1] + F[1], rho * fd[2] + F[2]};
+#pragma unroll
+  for (int i = 0; i < NQ; ++i) {
+    const float cu = cx(i) * u[0] + cy(i) * u[1] + cz(i) * u[2];
+    const float cF = cx(i) * rf[0] + cy(i) * rf[1] + cz(i) * rf[2];
+    const float cFt = cx(i) * Ft[0] + cy(i) * Ft[1] + cz(i) * Ft[2];
+    const float feq = 3.0f * p * (wgt(i) - (i == 0 ? 1.0f : 0.0f)) +
+                      rho * wgt(i) * (3.0f * cu + 4.5f * cu * cu - 1.5f * uu);
+    const float Fi = wgt(i) * (Sm + 3.0f * cF + 9.0f * cu * cFt - 3.0f * uFt);
+    fv[i] = fv[i] - (fv[i] - feq) * ift + pf * Fi;
+  }
+  // phase field (Sec. 3.2)
+  const float dj[3] = {j[0] - jprev[0], j[1] - jprev[1], j[2] - jprev[2]};
+  const float pm = phi * mdot;
+#pragma unroll
+  for (int i = 0; i < NQ; ++i) {
+    const float cj = cx(i) * j[0] + cy(i) * j[1] + cz(i) * j[2];
+    const float geq = (i == 0 ? m.dphi : 0.0f) + (wgt(i) - (i == 0 ? 1.0f : 0.0f)) * mu +
+                      3.0f * wgt(i) * cj;
+    const float Gi = wgt(i) * (3.0f * (cx(i) * dj[0] + cy(i) * dj[1] + cz(i) * dj[2]) + pm);
+    gv[i] = gv[i] - (gv[i] - geq) * ph.inv_tau_g + ph.pg * Gi;
+  }
+  lbf::two_sum(m.ref_g, gv[0], o.ghi, gv[0]);
+  // enthalpy, TRT (Sec. 3.3, eq22)
+  const float ET = ph.Eref * T, cT = rhocp * T;
+  float heq[NQ];
+#pragma unroll
+  for (int i = 0; i < NQ; ++i) {
+    const float cu = cx(i) * u[0] + cy(i) * u[1] + cz(i) * u[2];
+    heq[i] = (i == 0) ? m.dH - (1.0f - w0) * ET - 1.5f * w0 * cT * uu
+                      : wgt(i) * (ET + cT * (3.0f * cu + 4.5f * cu * cu - 1.5f * uu));
+  }
+  const float ps = ph.src_tau_a ? (1.0f - 0.5f * inv_tau_a) : (1.0f - 0.5f * inv_tau_s);
+  float hn[NQ];
+#pragma unroll
+  for (int i = 0; i < NQ; ++i) {
+    const int jj = opp(i);
+    const float ha = 0.5f * (hv[i] - hv[jj]), hs = 0.5f * (hv[i] + hv[jj]);
+    const float ea = 0.5f * (heq[i] - heq[jj]), es = 0.5f * (heq[i] + heq[jj]);
+    hn[i] = hv[i] - (ha - ea) * inv_tau_a - (hs - es) * inv_tau_s + ps * wgt(i) * Q;
+  }
+  if (ph.subfix && phi0 >= 0.5f) {
+    const float Tw = ph.T_sub;
+    const float rH = lbf::enthalpy_at(ph, Tw, m.Ksol, m.Kliq, m.chi);
+    const float EW = ph.Eref * Tw;
+#pragma unroll
+    for (int i = 0; i < NQ; ++i)
+      hn[i] = (i == 0) ? (rH - ref_h) - (1.0f - wgt(0)) * EW : wgt(i) * EW;
+  }
+#pragma unroll
+  for (int i = 1; i < NQ; ++i) hv[i] = hn[i];
+  lbf::two_sum(ref_h, hn[0], o.hhi, hv[0]);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    o.u[a] = u[a];
+    o.j[a] = j[a];
+  }
+  o.p = p;
+  o.Q = Q;
+}
+
+}  // namespace lbf3

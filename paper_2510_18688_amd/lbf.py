@@ -28,7 +28,10 @@ EXPORTS = ["lbf_workspace_bytes", "lbf_create", "lbf_set_geometry", "lbf_set_wal
            "lbf_destroy", "lbf_batch_create", "lbf_batch_set_tile", "lbf_batch_step",
            "lbf_batch_set_timing", "lbf_batch_last_step_ms", "lbf_batch_items",
            "lbf_batch_destroy", "lbf_tape_bytes", "lbf_tape_create", "lbf_tape_segment",
-           "lbf_tape_forward", "lbf_tape_backward", "lbf_tape_destroy", "lbf_profiles"]
+           "lbf_tape_forward", "lbf_tape_backward", "lbf_tape_destroy", "lbf_profiles",
+           "lbf3_workspace_bytes", "lbf3_create", "lbf3_set_geometry", "lbf3_init_fields",
+           "lbf3_step", "lbf3_read_fields", "lbf3_reduce", "lbf3_set_timing",
+           "lbf3_last_step_ms", "lbf3_destroy"]
 COLS = ["ice", "pcm", "pcm_top", "ice_top"]
 ROWS = ["ice", "pcm", "pcm_left", "pcm_right", "ice_left", "ice_right"]
 
@@ -459,3 +462,116 @@ def freeze_fields(cos_theta, wall_T, case, steps: int, segment: int = 0, tile=No
     if _FREEZE is None:
         _FREEZE = _freeze_function()
     return _FREEZE.apply(cos_theta, wall_T, case, int(steps), int(segment), tile)
+
+
+# ---------------------------------------------------------------- 3D (D3Q19)
+FIELDS3 = ["phi", "T", "fl", "fs", "ux", "uy", "uz", "p", "rhoH", "mu", "C", "chi", "rho",
+           "phihat"]
+
+
+class Params3(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+                ("periodic", C.c_int32 * 3), ("thermal_bc", C.c_int32 * 6),
+                ("latch_fs", C.c_int32), ("h_src_tau_a", C.c_int32),
+                ("substrate_fixed", C.c_int32), ("reserved", C.c_int32)] + [
+        (k, C.c_double) for k in (
+            "rho_l", "rho_g", "rho_s", "mu_l", "mu_g", "mu_s", "lam_l", "lam_g", "lam_s",
+            "cp_l", "cp_g", "cp_s", "latent", "T_m", "sigma", "eps", "mobility", "cos_psi",
+            "rho_ref", "T_substrate", "pcm_floor")] + [("wall_T", C.c_double * 6)]
+
+
+def _declare3(L):
+    if getattr(L, "_lbf3_declared", False):
+        return
+    vp, i32 = C.c_void_p, C.c_int32
+    L.lbf3_workspace_bytes.restype = C.c_size_t
+    L.lbf3_workspace_bytes.argtypes = [i32, i32, i32]
+    L.lbf3_create.argtypes = [C.POINTER(Params3), vp, vp, C.c_size_t, C.POINTER(vp)]
+    L.lbf3_set_geometry.argtypes = [vp, vp, vp, i32]
+    L.lbf3_init_fields.argtypes = [vp, vp, vp, i32]
+    L.lbf3_step.argtypes = [vp, i32]
+    L.lbf3_read_fields.argtypes = [vp, vp, i32]
+    L.lbf3_reduce.argtypes = [vp, C.POINTER(C.c_double)]
+    L.lbf3_set_timing.argtypes = [vp, i32]
+    L.lbf3_last_step_ms.restype = C.c_double
+    L.lbf3_last_step_ms.argtypes = [vp]
+    L.lbf3_destroy.argtypes = [vp]
+    L._lbf3_declared = True
+
+
+def make_params3(case) -> Params3:
+    p = Params3()
+    p.nx, p.ny, p.nz = case.nx, case.ny, case.nz
+    for a in range(3):
+        p.periodic[a] = int(bool(case.periodic[a]))
+    for f in range(6):
+        p.thermal_bc[f] = int(case.thermal_bc[f])
+        p.wall_T[f] = float(case.wall_T[f])
+    m = case.mat
+    p.latch_fs, p.h_src_tau_a = int(m.latch_fs), int(m.h_src_tau_a)
+    p.substrate_fixed = int(case.substrate_fixed)
+    for k in ("rho_l", "rho_g", "rho_s", "mu_l", "mu_g", "mu_s", "lam_l", "lam_g", "lam_s",
+              "cp_l", "cp_g", "cp_s", "latent", "T_m", "sigma", "eps", "mobility", "cos_psi",
+              "rho_ref", "pcm_floor"):
+        setattr(p, k, float(getattr(m, k)))
+    p.T_substrate = float(case.T_substrate)
+    return p
+
+
+class Sim3:
+    """One D3Q19 lattice on the current HIP device (workspace: a torch tensor)."""
+
+    def __init__(self, case, device: str = "cuda", stream=None):
+        torch = _torch()
+        L = load()
+        _declare3(L)
+        self.case = case
+        self.shape = (case.nz, case.ny, case.nx)
+        self.params = make_params3(case)
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        nbytes = L.lbf3_workspace_bytes(case.nx, case.ny, case.nz)
+        if nbytes == 0:
+            raise LbfError(-1, "bad lattice size")
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        h = C.c_void_p()
+        check(L.lbf3_create(C.byref(self.params), C.c_void_p(self.stream.cuda_stream),
+                            C.c_void_p(self.workspace.data_ptr()), nbytes, C.byref(h)))
+        self.h = h
+        a, b = _f32_host(case.phi0), _f32_host(case.cos_theta)
+        check(L.lbf3_set_geometry(self.h, C.c_void_p(a.ctypes.data), C.c_void_p(b.ctypes.data), 0))
+        a, b = _f32_host(case.phi), _f32_host(case.T)
+        check(L.lbf3_init_fields(self.h, C.c_void_p(a.ctypes.data), C.c_void_p(b.ctypes.data), 0))
+
+    def step(self, n: int = 1) -> None:
+        check(_lib.lbf3_step(self.h, int(n)))
+
+    def set_timing(self, on: bool) -> None:
+        check(_lib.lbf3_set_timing(self.h, int(bool(on))))
+
+    def last_step_ms(self) -> float:
+        return float(_lib.lbf3_last_step_ms(self.h))
+
+    def fields(self) -> Dict[str, np.ndarray]:
+        n = int(np.prod(self.shape))
+        out = np.empty(len(FIELDS3) * n, dtype=np.float32)
+        check(_lib.lbf3_read_fields(self.h, C.c_void_p(out.ctypes.data), 0))
+        return {k: out[i * n:(i + 1) * n].reshape(self.shape) for i, k in enumerate(FIELDS3)}
+
+    def reduce(self, check_stable: bool = True) -> Dict[str, float]:
+        out = (C.c_double * len(REDS))()
+        rc = _lib.lbf3_reduce(self.h, out)
+        if rc != 0 and (check_stable or rc != -4):
+            check(rc)
+        return dict(zip(REDS, list(out)))
+
+    def close(self) -> None:
+        if getattr(self, "h", None) is not None and self.h.value:
+            _lib.lbf3_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,7 +1,7 @@
 """Host-side checks of the C ABI (no GPU): the library loads, exports every
-entry point that include/lbf.h declares, its parameter struct matches the
-binding's, and parameter validation rejects bad sets before touching a
-device."""
+entry point that include/lbf.h and include/lbf3.h declare, both parameter
+structs match the binding's, and parameter validation rejects bad sets
+before touching a device."""
 
 import ctypes as C
 import os
@@ -14,7 +14,7 @@ import pytest
 from paper_2510_18688_amd import lbf, workloads as W
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "lbf.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("lbf.h", "lbf3.h")]
 
 
 @pytest.fixture(scope="module")
@@ -26,14 +26,16 @@ def L():
 
 
 def declared_functions():
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(lbf_[a-z_0-9]+)\s*\(", text)))
+    names = set()
+    for h in HEADERS:
+        text = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names |= set(re.findall(r"\b(lbf3?_[a-z_0-9]+)\s*\(", text))
+    return sorted(names)
 
 
 def test_exports_every_declared_symbol(L):
     names = declared_functions()
-    assert len(names) >= 15
+    assert len(names) >= 25 and "lbf3_step" in names
     for n in names:
         assert hasattr(L, n), n
     assert set(lbf.EXPORTS) <= set(names)
@@ -53,6 +55,20 @@ def test_params_layout_matches_header(tmp_path):
     assert int(out[1]) == P.rho_l.offset
     assert int(out[2]) == P.T_substrate.offset
     assert int(out[3]) == P.thermal_bc.offset
+
+
+def test_params3_layout_matches_header(tmp_path):
+    src = tmp_path / "sz3.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "lbf3.h"\n'
+                   'int main(void){printf("%zu %zu %zu %zu\\n", sizeof(lbf3_params),'
+                   ' offsetof(lbf3_params, rho_l), offsetof(lbf3_params, pcm_floor),'
+                   ' offsetof(lbf3_params, wall_T));return 0;}\n')
+    exe = tmp_path / "sz3"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()
+    P = lbf.Params3
+    assert [int(v) for v in out] == [C.sizeof(P), P.rho_l.offset, P.pcm_floor.offset,
+                                     P.wall_T.offset]
 
 
 def test_workspace_bytes(L):
@@ -96,6 +112,39 @@ def test_null_arguments(L):
     assert L.lbf_batch_step(None, 1) == -1
     assert L.lbf_batch_set_tile(None, 64, 8) == -1
     L.lbf_batch_destroy(None)
+    lbf._declare3(L)
+    assert L.lbf3_step(None, 1) == -1
+    assert L.lbf3_reduce(None, None) == -1
+    assert L.lbf3_read_fields(None, None, 0) == -1
+    assert L.lbf3_set_geometry(None, None, None, 0) == -1
+    assert L.lbf3_create(None, None, None, 0, C.byref(out)) == -1
+    L.lbf3_destroy(None)
+
+
+def test_workspace3_bytes_and_limits(L):
+    lbf._declare3(L)
+    assert L.lbf3_workspace_bytes(0, 4, 4) == 0
+    assert L.lbf3_workspace_bytes(4, 4, -1) == 0
+    a, b = L.lbf3_workspace_bytes(16, 16, 16), L.lbf3_workspace_bytes(32, 32, 32)
+    assert 0 < a < b
+    assert L.lbf3_workspace_bytes(1024, 1024, 1024) == 0      # above the addressing limit
+
+
+@pytest.mark.parametrize("mutate, needle", [
+    (lambda c: setattr(c, "nz", 0), "lattice size"),
+    (lambda c: setattr(c.mat, "pcm_floor", 1.0), "pcm_floor"),
+    (lambda c: setattr(c, "thermal_bc", [0, 0, 0, 0, 3, 0]), "thermal_bc[4]"),
+    (lambda c: setattr(c.mat, "latent", -1.0), "non-negative"),
+])
+def test_invalid_params3_rejected_on_host(L, mutate, needle):
+    from paper_2510_18688_amd import workloads3 as W3
+    lbf._declare3(L)
+    case = W3.sessile_drop3(nx=12, ny=10, nz=12, radius=4.0, h_s=3.0)
+    mutate(case)
+    p = lbf.make_params3(case)
+    h = C.c_void_p()
+    rc = L.lbf3_create(C.byref(p), None, None, 0, C.byref(h))
+    assert rc == -1 and needle in L.lbf_last_error().decode()
 
 
 def test_binding_refuses_without_device(monkeypatch):
