@@ -29,16 +29,23 @@ sys.path.insert(0, ROOT)
 # lap phi0).
 BYTES_PER_LU = (27 + 7) * 2 * 4 + 3 * 4
 HBM_PEAK_GBS = 8000.0
+# D3Q19, two kernels per step.  Moments pass: g and h pulled (38 planes), the
+# high parts of g_0, h_0, f_s and Q of the previous step, phi0 read; phi,
+# f_s, rho written.  Step pass: 57 distributions, 8 lagged, 3 static and the
+# 3 moment planes read; 57 distributions and 8 lagged planes written.  The
+# state itself (one pass, no moment planes) is 532 bytes per update.
+BYTES3_MOMENTS = (38 + 4 + 1) * 4 + 3 * 4
+BYTES3_STEP = (57 + 8 + 3 + 3) * 4 + (57 + 8) * 4
+BYTES3_STATE = (57 + 8) * 2 * 4 + 3 * 4
 
 
-def hbm_traffic(kernel_ms):
-    """HBM traffic of the step kernel from the committed rocprofv3 counter
-    summary (FETCH_SIZE and WRITE_SIZE per dispatch, scaled by the same
-    counters' reading of a plain 512 MiB copy), as GB/s at this run's kernel
-    time; None when the kernel sources changed since the counters were
-    taken."""
+def hbm_traffic(kernel_ms, name="step_kernel_curved_substrate_2048x2048"):
+    """HBM traffic of a kernel from a committed rocprofv3 counter summary
+    (FETCH_SIZE and WRITE_SIZE per dispatch, scaled by the same counters'
+    reading of a plain 512 MiB copy); None when the kernel sources changed
+    since the counters were taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "step_kernel_curved_substrate_2048x2048.hbm.json")
+    path = os.path.join(ROOT, "profiles", name + ".hbm.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -64,6 +71,8 @@ def parse():
                     help="steps of the 64-lattice batched workload (0 skips it)")
     ap.add_argument("--adjoint-steps", type=int, default=2000,
                     help="steps of the 256 x 256 gradient workload (0 skips it)")
+    ap.add_argument("--d3q19-steps", type=int, default=200,
+                    help="steps of the D3Q19 workloads (0 skips them)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run an elementwise copy of MIB MiB (read + write), the "
                          "reference kernel for scaling HBM byte counters")
@@ -181,6 +190,50 @@ def adjoint(lbf, W, torch, steps):
             "record_and_adjoint_over_forward": round((t_rec + t_bwd) / t_fwd, 3)}
 
 
+def d3q19(lbf, torch, steps):
+    """The three-dimensional coupled step: freezing in a rough fracture
+    (256 x 128 x 30, three trapped bubbles, cold inlet face) and a drop in a
+    periodic 256^3 box."""
+    from paper_2510_18688_amd import workloads3 as W3
+    out = {}
+    for label, case in (("fracture_256x128x30", W3.fracture()),
+                        ("sphere_drop_256x256x256", W3.sphere_drop(256, 64.0))):
+        sim = lbf.Sim3(case)
+        sim.step(max(steps // 10, 5))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(steps)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        sim.set_timing(True)
+        sim.step(steps)
+        ms = sim.last_step_ms()
+        sim.set_timing(False)
+        red = sim.reduce()
+        sim.close()
+        del sim
+        torch.cuda.empty_cache()
+        n = case.nodes
+        gbs = (BYTES3_MOMENTS + BYTES3_STEP) * n / (ms * 1e-3) / 1e9
+        out[label] = {
+            "nodes": n, "steps": steps,
+            "mlups": round(n * steps / wall / 1e6, 1),
+            "ms_per_step": round(wall / steps * 1e3, 5),
+            "kernel_ms_per_step": round(ms, 5),
+            "bytes_per_lu": BYTES3_MOMENTS + BYTES3_STEP,
+            "achieved_gbs": round(gbs, 1),
+            "frac": round(gbs / HBM_PEAK_GBS, 4),
+            "state_bytes_frac": round(BYTES3_STATE * n / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "nonfinite": red["nonfinite"], "umax": red["umax"],
+        }
+        rec = hbm_traffic(ms, "d3q19_kernels_" + label) if n == 16777216 else None
+        if rec is not None:
+            per_lu = sum((k["hbm_bytes_per_launch"] / n) for k in rec["kernels"].values())
+            out[label]["traffic_bytes_per_lu"] = round(per_lu, 1)
+            out[label]["traffic_gbs"] = round(per_lu * n / (ms * 1e-3) / 1e9, 1)
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -274,6 +327,8 @@ def main():
         out["batched"] = batched(lbf, W, torch, args.batch_steps)
     if args.adjoint_steps > 0:
         out["adjoint"] = adjoint(lbf, W, torch, args.adjoint_steps)
+    if args.d3q19_steps > 0:
+        out["d3q19"] = d3q19(lbf, torch, args.d3q19_steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(case, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -128,27 +128,40 @@ __device__ __forceinline__ void pull19(const Geo3& G, int x, int y, int z, Pull1
   }
 }
 
-// Pulled g and h of a node (bounce-back; anti-bounce-back for h on
-// Dirichlet faces).
-__device__ __forceinline__ void pull_gh3(const Geo3& G, const Phys& ph, const Bufs3& B,
-                                         const Pull19& n, float* gv, float* hv) {
+// Pulled g of a node (bounce-back at every wall).
+__device__ __forceinline__ void pull_g3(const Geo3& G, const Bufs3& B, const Pull19& n,
+                                        float* gv) {
 #pragma unroll
-  for (int i = 0; i < NQ; ++i) {
-    gv[i] = lbf::ldo(B.gin, n.off[i], i, G.P);
-    hv[i] = lbf::ldo(B.hin, n.off[i], i, G.P);
+  for (int i = 0; i < NQ; ++i) gv[i] = lbf::ldo(B.gin, n.off[i], i, G.P);
+  if (n.wmask) {
+#pragma unroll
+    for (int i = 1; i < NQ; ++i)
+      if ((n.wmask >> i) & 1u) gv[i] = lbf::ldo(B.gin, n.k4, opp(i), G.P);
   }
+}
+
+// Pulled h of a node (bounce-back; anti-bounce-back with the face
+// temperature on Dirichlet faces).
+__device__ __forceinline__ void pull_h3(const Geo3& G, const Phys& ph, const Bufs3& B,
+                                        const Pull19& n, float* hv) {
+#pragma unroll
+  for (int i = 0; i < NQ; ++i) hv[i] = lbf::ldo(B.hin, n.off[i], i, G.P);
   if (n.wmask) {
 #pragma unroll
     for (int i = 1; i < NQ; ++i) {
       if ((n.wmask >> i) & 1u) {
-        const int j = opp(i);
-        gv[i] = lbf::ldo(B.gin, n.k4, j, G.P);
-        const float hb = lbf::ldo(B.hin, n.k4, j, G.P);
+        const float hb = lbf::ldo(B.hin, n.k4, opp(i), G.P);
         const int f = n.face[i];
         hv[i] = ((G.tmask >> f) & 1) ? -hb + 2.0f * wgt(i) * ph.Eref * G.Tw[f] : hb;
       }
     }
   }
+}
+
+__device__ __forceinline__ void pull_gh3(const Geo3& G, const Phys& ph, const Bufs3& B,
+                                         const Pull19& n, float* gv, float* hv) {
+  pull_g3(G, B, n, gv);
+  pull_h3(G, ph, B, n, hv);
 }
 
 __device__ __forceinline__ void pull_f3(const Geo3& G, const Bufs3& B, const Pull19& n,
@@ -231,25 +244,31 @@ struct Post3 {
   float u[3], p, Q, j[3], ghi, hhi;
 };
 
-// Collision of the three populations at one node (Sec. 3.1-3.3 in three
-// dimensions), in place on fv, gv, hv (gv[0], hv[0] as deviations from the
-// node's references); the rest populations are renormalised to float-float.
-__device__ __forceinline__ void collide3(const Phys& ph, const Mom& m, const Stencil3& S,
-                                         float phi0, float cth, float lap_phi0,
-                                         const float* jprev, float ref_h, float* fv, float* gv,
-                                         float* hv, Post3& o) {
+// Node quantities of one collision that do not depend on the population
+// index: velocity, pressure, forces and relaxation rates.
+struct Coll3 {
+  float u[3], rf[3], Ft[3], j[3], dj[3];
+  float Sm, uu, uFt, p, rho, ift, pf, mu, pm, Q, ET, cT, inv_tau_a, inv_tau_s, ps;
+};
+
+// Velocity and pressure from the pulled f (Sec. 3.1: the forced velocity
+// with the solid drag, the pressure from the non-rest populations), the
+// chemical potential, and the rates of the three collisions.
+__device__ __forceinline__ void collide3_prepare(const Phys& ph, const Mom& m, const Stencil3& S,
+                                                 float phi0, float cth, float lap_phi0,
+                                                 const float* jprev, const float* fv, Coll3& c) {
   const float phi = m.phi, rho = m.rho, C = m.C, fstot = m.fstot, mdot = m.mdot, T = m.T;
   const float mu_v = lbf::zeta(fstot, C, ph.mu_s, ph.mu_l, ph.mu_g);
   const float lam = lbf::zeta(fstot, C, ph.lam_s, ph.lam_l, ph.lam_g);
   const float cp = lbf::zeta(fstot, C, ph.cp_s, ph.cp_l, ph.cp_g);
   const float inv_rho = lbf::rcp(rho);
   const float tau_f = 3.0f * mu_v * inv_rho + 0.5f;
-  const float inv_tau_a = lbf::rcp(lam * ph.three_over_Eref + 0.5f);
-  const float inv_tau_s = 2.0f - inv_tau_a;
-  const float mu = lbf::chem_pot(ph, phi, S.lphi, phi0, cth, lap_phi0, m.fs, S.lfs);
+  c.inv_tau_a = lbf::rcp(lam * ph.three_over_Eref + 0.5f);
+  c.inv_tau_s = 2.0f - c.inv_tau_a;
+  c.mu = lbf::chem_pot(ph, phi, S.lphi, phi0, cth, lap_phi0, m.fs, S.lfs);
   float F[3], mm[3] = {0, 0, 0}, snz = 0;
 #pragma unroll
-  for (int a = 0; a < 3; ++a) F[a] = mu * S.gph[a];
+  for (int a = 0; a < 3; ++a) F[a] = c.mu * S.gph[a];
 #pragma unroll
   for (int i = 0; i < NQ; ++i) {
     mm[0] += cx(i) * fv[i];
@@ -257,67 +276,87 @@ __device__ __forceinline__ void collide3(const Phys& ph, const Mom& m, const Ste
     mm[2] += cz(i) * fv[i];
     if (i) snz += fv[i];
   }
-  float u[3], fd[3], Ft[3];
+  float fd[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     const float us = (mm[a] + 0.5f * F[a]) * inv_rho;
     fd[a] = -fstot * us;
-    u[a] = us + 0.5f * fd[a];
-    Ft[a] = F[a] - S.gp[a] + (1.0f / 3.0f) * S.gr[a];
+    c.u[a] = us + 0.5f * fd[a];
+    c.Ft[a] = F[a] - S.gp[a] + (1.0f / 3.0f) * S.gr[a];
+    c.rf[a] = rho * fd[a] + F[a];
   }
-  const float Sm = rho * mdot + u[0] * S.gr[0] + u[1] * S.gr[1] + u[2] * S.gr[2];
-  const float uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-  const float uFt = u[0] * Ft[0] + u[1] * Ft[1] + u[2] * Ft[2];
+  c.Sm = rho * mdot + c.u[0] * S.gr[0] + c.u[1] * S.gr[1] + c.u[2] * S.gr[2];
+  c.uu = c.u[0] * c.u[0] + c.u[1] * c.u[1] + c.u[2] * c.u[2];
+  c.uFt = c.u[0] * c.Ft[0] + c.u[1] * c.Ft[1] + c.u[2] * c.Ft[2];
   const float w0 = wgt(0);
-  const float F0 = w0 * (Sm - 3.0f * uFt);
-  const float p = (1.0f / 3.0f) / (1.0f - w0) *
-                  (snz + 0.5f * Sm + (tau_f - 0.5f) * F0 - 1.5f * w0 * rho * uu);
-  const float j[3] = {phi * u[0], phi * u[1], phi * u[2]};
-  const float rhocp = rho * cp;
-  const float Q = rhocp * T * mdot;
-  // flow (Sec. 3.1)
-  const float ift = lbf::rcp(tau_f);
-  const float pf = 1.0f - 0.5f * ift;
-  const float rf[3] = {rho * fd[0] + F[0], rho * fd[1] + F[1], rho * fd[2] + F[2]};
+  const float F0 = w0 * (c.Sm - 3.0f * c.uFt);
+  c.p = (1.0f / 3.0f) / (1.0f - w0) *
+        (snz + 0.5f * c.Sm + (tau_f - 0.5f) * F0 - 1.5f * w0 * rho * c.uu);
+  c.rho = rho;
+  c.ift = lbf::rcp(tau_f);
+  c.pf = 1.0f - 0.5f * c.ift;
 #pragma unroll
-  for (int i = 0; i < NQ; ++i) {
-    const float cu = cx(i) * u[0] + cy(i) * u[1] + cz(i) * u[2];
-    const float cF = cx(i) * rf[0] + cy(i) * rf[1] + cz(i) * rf[2];
-    const float cFt = cx(i) * Ft[0] + cy(i) * Ft[1] + cz(i) * Ft[2];
-    const float feq = 3.0f * p * (wgt(i) - (i == 0 ? 1.0f : 0.0f)) +
-                      rho * wgt(i) * (3.0f * cu + 4.5f * cu * cu - 1.5f * uu);
-    const float Fi = wgt(i) * (Sm + 3.0f * cF + 9.0f * cu * cFt - 3.0f * uFt);
-    fv[i] = fv[i] - (fv[i] - feq) * ift + pf * Fi;
+  for (int a = 0; a < 3; ++a) {
+    c.j[a] = phi * c.u[a];
+    c.dj[a] = c.j[a] - jprev[a];
   }
-  // phase field (Sec. 3.2)
-  const float dj[3] = {j[0] - jprev[0], j[1] - jprev[1], j[2] - jprev[2]};
-  const float pm = phi * mdot;
+  c.pm = phi * mdot;
+  const float rhocp = rho * cp;
+  c.Q = rhocp * T * mdot;
+  c.ET = ph.Eref * T;
+  c.cT = rhocp * T;
+  c.ps = ph.src_tau_a ? (1.0f - 0.5f * c.inv_tau_a) : (1.0f - 0.5f * c.inv_tau_s);
+}
+
+// Flow collision (Sec. 3.1), in place.
+__device__ __forceinline__ void collide3_f(const Coll3& c, float* fv) {
 #pragma unroll
   for (int i = 0; i < NQ; ++i) {
-    const float cj = cx(i) * j[0] + cy(i) * j[1] + cz(i) * j[2];
-    const float geq = (i == 0 ? m.dphi : 0.0f) + (wgt(i) - (i == 0 ? 1.0f : 0.0f)) * mu +
+    const float cu = cx(i) * c.u[0] + cy(i) * c.u[1] + cz(i) * c.u[2];
+    const float cF = cx(i) * c.rf[0] + cy(i) * c.rf[1] + cz(i) * c.rf[2];
+    const float cFt = cx(i) * c.Ft[0] + cy(i) * c.Ft[1] + cz(i) * c.Ft[2];
+    const float feq = 3.0f * c.p * (wgt(i) - (i == 0 ? 1.0f : 0.0f)) +
+                      c.rho * wgt(i) * (3.0f * cu + 4.5f * cu * cu - 1.5f * c.uu);
+    const float Fi = wgt(i) * (c.Sm + 3.0f * cF + 9.0f * cu * cFt - 3.0f * c.uFt);
+    fv[i] = fv[i] - (fv[i] - feq) * c.ift + c.pf * Fi;
+  }
+}
+
+// Phase-field collision (Sec. 3.2), in place; g_0 leaves as float-float
+// (ghi, gv[0]).
+__device__ __forceinline__ void collide3_g(const Phys& ph, const Mom& m, const Coll3& c,
+                                           float* gv, float& ghi) {
+#pragma unroll
+  for (int i = 0; i < NQ; ++i) {
+    const float cj = cx(i) * c.j[0] + cy(i) * c.j[1] + cz(i) * c.j[2];
+    const float geq = (i == 0 ? m.dphi : 0.0f) + (wgt(i) - (i == 0 ? 1.0f : 0.0f)) * c.mu +
                       3.0f * wgt(i) * cj;
-    const float Gi = wgt(i) * (3.0f * (cx(i) * dj[0] + cy(i) * dj[1] + cz(i) * dj[2]) + pm);
+    const float Gi =
+        wgt(i) * (3.0f * (cx(i) * c.dj[0] + cy(i) * c.dj[1] + cz(i) * c.dj[2]) + c.pm);
     gv[i] = gv[i] - (gv[i] - geq) * ph.inv_tau_g + ph.pg * Gi;
   }
-  lbf::two_sum(m.ref_g, gv[0], o.ghi, gv[0]);
-  // enthalpy, TRT (Sec. 3.3, eq22)
-  const float ET = ph.Eref * T, cT = rhocp * T;
+  lbf::two_sum(m.ref_g, gv[0], ghi, gv[0]);
+}
+
+// Enthalpy collision, TRT (Sec. 3.3, eq22), in place, or the held
+// substrate's equilibrium at T_substrate; h_0 leaves as float-float.
+__device__ __forceinline__ void collide3_h(const Phys& ph, const Mom& m, const Coll3& c,
+                                           float phi0, float ref_h, float* hv, float& hhi) {
+  const float w0 = wgt(0);
   float heq[NQ];
 #pragma unroll
   for (int i = 0; i < NQ; ++i) {
-    const float cu = cx(i) * u[0] + cy(i) * u[1] + cz(i) * u[2];
-    heq[i] = (i == 0) ? m.dH - (1.0f - w0) * ET - 1.5f * w0 * cT * uu
-                      : wgt(i) * (ET + cT * (3.0f * cu + 4.5f * cu * cu - 1.5f * uu));
+    const float cu = cx(i) * c.u[0] + cy(i) * c.u[1] + cz(i) * c.u[2];
+    heq[i] = (i == 0) ? m.dH - (1.0f - w0) * c.ET - 1.5f * w0 * c.cT * c.uu
+                      : wgt(i) * (c.ET + c.cT * (3.0f * cu + 4.5f * cu * cu - 1.5f * c.uu));
   }
-  const float ps = ph.src_tau_a ? (1.0f - 0.5f * inv_tau_a) : (1.0f - 0.5f * inv_tau_s);
   float hn[NQ];
 #pragma unroll
   for (int i = 0; i < NQ; ++i) {
     const int jj = opp(i);
     const float ha = 0.5f * (hv[i] - hv[jj]), hs = 0.5f * (hv[i] + hv[jj]);
     const float ea = 0.5f * (heq[i] - heq[jj]), es = 0.5f * (heq[i] + heq[jj]);
-    hn[i] = hv[i] - (ha - ea) * inv_tau_a - (hs - es) * inv_tau_s + ps * wgt(i) * Q;
+    hn[i] = hv[i] - (ha - ea) * c.inv_tau_a - (hs - es) * c.inv_tau_s + c.ps * wgt(i) * c.Q;
   }
   if (ph.subfix && phi0 >= 0.5f) {
     const float Tw = ph.T_sub;
@@ -329,14 +368,27 @@ __device__ __forceinline__ void collide3(const Phys& ph, const Mom& m, const Ste
   }
 #pragma unroll
   for (int i = 1; i < NQ; ++i) hv[i] = hn[i];
-  lbf::two_sum(ref_h, hn[0], o.hhi, hv[0]);
+  lbf::two_sum(ref_h, hn[0], hhi, hv[0]);
+}
+
+// The whole collision of one node, in place on fv, gv, hv (gv[0], hv[0] as
+// deviations from the node's references).
+__device__ __forceinline__ void collide3(const Phys& ph, const Mom& m, const Stencil3& S,
+                                         float phi0, float cth, float lap_phi0,
+                                         const float* jprev, float ref_h, float* fv, float* gv,
+                                         float* hv, Post3& o) {
+  Coll3 c;
+  collide3_prepare(ph, m, S, phi0, cth, lap_phi0, jprev, fv, c);
+  collide3_f(c, fv);
+  collide3_g(ph, m, c, gv, o.ghi);
+  collide3_h(ph, m, c, phi0, ref_h, hv, o.hhi);
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    o.u[a] = u[a];
-    o.j[a] = j[a];
+    o.u[a] = c.u[a];
+    o.j[a] = c.j[a];
   }
-  o.p = p;
-  o.Q = Q;
+  o.p = c.p;
+  o.Q = c.Q;
 }
 
 }  // namespace lbf3
