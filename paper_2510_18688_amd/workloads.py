@@ -62,6 +62,12 @@ class Material:
     pcm_floor: float = 0.01
     latch_fs: int = 1
     h_src_tau_a: int = 0
+    # flow collision: 0 BGK (Sec. 3.1), 1 MRT with the bulk rate s_b (density,
+    # energy and energy-square moments) and the energy-flux rate s_q; 0 stands
+    # for the BGK rate 1/tau_f
+    mrt: int = 0
+    s_b: float = 0.0
+    s_q: float = 0.0
 
     def as_dict(self) -> Dict[str, float]:
         return dataclasses.asdict(self)
@@ -321,3 +327,74 @@ WORKLOADS = {
     "curved_substrate_2048x2048": lambda: curved_substrate(),
     "porous_4096x2048": lambda: porous_medium(),
 }
+
+
+def sandpack_image(shape, porosity: float = 0.3585, seed: int = 12, r_median: float = 8.0,
+                   sigma_log: float = 0.45, r_min: float = 2.5, periodic=(False, False, False),
+                   max_grains: int = 2_000_000) -> np.ndarray:
+    """Binary image of a poorly sorted, unconsolidated grain pack (1 = solid):
+    overlapping disks (2D shape (ny, nx)) or spheres (3D shape (nz, ny, nx))
+    with log-normal radii (median r_median, log standard deviation
+    sigma_log, floored at r_min), centres uniform in the box, added until the
+    pore fraction falls to `porosity`.  Grains wrap across periodic axes."""
+    rng = np.random.default_rng(seed)
+    shape = tuple(int(v) for v in shape)
+    dim = len(shape)
+    img = np.zeros(shape, dtype=np.uint8)
+    total = img.size
+    solid = 0
+    target = (1.0 - porosity) * total
+    axes_n = shape[::-1]            # (nx, ny[, nz])
+    for _ in range(max_grains):
+        if solid >= target:
+            break
+        r = max(r_min, r_median * math.exp(sigma_log * rng.standard_normal()))
+        ctr = [rng.uniform(0.0, n) for n in axes_n]
+        idx, off = [], []
+        for a in range(dim):
+            lo, hi = int(math.floor(ctr[a] - r)), int(math.ceil(ctr[a] + r)) + 1
+            i = np.arange(lo, hi)
+            if periodic[a]:
+                sel = np.ones(i.size, dtype=bool)
+                ii = np.mod(i, axes_n[a])
+            else:
+                sel = (i >= 0) & (i < axes_n[a])
+                ii = i[sel]
+            idx.append(ii)
+            off.append((i[sel] + 0.5 - ctr[a]) ** 2)
+        d2 = off[0][None, :] + off[1][:, None] if dim == 2 else (
+            off[0][None, None, :] + off[1][None, :, None] + off[2][:, None, None])
+        inside = d2 <= r * r
+        sub = img[np.ix_(*idx[::-1])]
+        new = int(np.count_nonzero(inside & (sub == 0)))
+        if new:
+            sub = sub | inside.astype(np.uint8)
+            img[np.ix_(*idx[::-1])] = sub
+            solid += new
+    return img
+
+
+def unsaturated_medium(phi0: np.ndarray, S_w: float = 0.32, theta_deg: float = 60.0,
+                       T0: float = 0.5, steps: int = 0, mat: Optional[Material] = None,
+                       name: str = "unsaturated") -> Case:
+    """The unsaturated porous set-up of Sec. 4.6 on a 2D solid indicator phi0
+    (ny, nx): the pores hold phi = (1 - phi0) phi_i with phi_i = 2 S_w - 1
+    (a uniform mixture whose liquid share of the pore volume is S_w), at a
+    uniform T0 above melting; walls on all sides, the x walls Dirichlet at
+    T0 for the phase-separation stage (`wall_T_freezing` gives the cold and
+    warm x walls of the freezing stage), the y walls adiabatic."""
+    mat = mat or Material()
+    ny, nx = phi0.shape
+    phi_i = 2.0 * S_w - 1.0
+    phi = (1.0 - phi0) * phi_i
+    cth = np.full((ny, nx), math.cos(math.radians(theta_deg)))
+    return Case(f"{name}_{nx}x{ny}_Sw{S_w:g}_th{theta_deg:g}", nx, ny, False, False,
+                [ADIABATIC, ADIABATIC, DIRICHLET, DIRICHLET],
+                {LEFT: np.full(ny, T0), RIGHT: np.full(ny, T0)},
+                np.asarray(phi0, dtype=np.float64), cth, phi, np.full((ny, nx), T0), mat,
+                steps=steps)
+
+
+def wall_T_freezing(case: Case, T_cold: float = -1.0, T_hot: float = 0.5) -> Dict[int, np.ndarray]:
+    """Wall temperatures of the freezing stage of `unsaturated_medium`."""
+    return {LEFT: np.full(case.ny, T_cold), RIGHT: np.full(case.ny, T_hot)}
