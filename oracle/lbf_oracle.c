@@ -52,6 +52,10 @@ typedef struct {
   double cp_l, cp_g, cp_s;
   double latent, T_m, sigma, eps, mobility, cos_psi, rho_ref, T_substrate;
   double pcm_floor;           /* R45 */
+  int32_t mrt;                /* 1: MRT flow collision (R53) */
+  int32_t pad2_;
+  double s_b, s_q;            /* MRT rates: density, e and epsilon moments; energy flux
+                                 (0: the BGK rate 1/tau_f) */
 } orc_params;
 
 enum { WB = 0, WT = 1, WL = 2, WR = 3 };
@@ -73,6 +77,7 @@ typedef struct {
   double budget[4];             /* sum phi*mdot, heat source, wall flux, reset */
   long step;
   int store_f32;                /* conditioning probe: round the state to binary32 each step */
+  double mrtM[81], mrtMinv[81]; /* MRT basis and its inverse (R53) */
 } orc_sim;
 
 /* --------------------------------------------------------- small helpers */
@@ -160,6 +165,96 @@ void orc_forcing(double S, double Fx, double Fy, double rfx, double rfy,
 
 /* Phase-field equilibrium (Sec. 3.2), eta = 1 (R11):
  * g_0^eq = phi + (w_0 - 1) mu,  g_i^eq = w_i mu + w_i c_i.(phi u)/c_s^2. */
+/* ------------------------------------------------------------ MRT (R53) */
+/* Orthogonal moment basis of the D2Q9 lattice (Lallemand and Luo): density,
+ * energy e, energy square epsilon, momentum j_x, energy flux q_x, j_y, q_y,
+ * and the stresses p_xx, p_xy, as polynomials of the velocities. */
+void orc_mrt_matrix(double* M /* 81, row-major: moment k, velocity i */) {
+  for (int i = 0; i < 9; ++i) {
+    double cx = CX[i], cy = CY[i], c2 = cx * cx + cy * cy;
+    M[0 * 9 + i] = 1.0;
+    M[1 * 9 + i] = -4.0 + 3.0 * c2;
+    M[2 * 9 + i] = 4.0 - 10.5 * c2 + 4.5 * c2 * c2;
+    M[3 * 9 + i] = cx;
+    M[4 * 9 + i] = (-5.0 + 3.0 * c2) * cx;
+    M[5 * 9 + i] = cy;
+    M[6 * 9 + i] = (-5.0 + 3.0 * c2) * cy;
+    M[7 * 9 + i] = cx * cx - cy * cy;
+    M[8 * 9 + i] = cx * cy;
+  }
+}
+
+/* Inverse of a 9 x 9 matrix by Gauss-Jordan elimination with partial
+ * pivoting. */
+void orc_invert9(const double* A, double* Ainv) {
+  double a[9][18];
+  for (int r = 0; r < 9; ++r)
+    for (int c = 0; c < 18; ++c) a[r][c] = c < 9 ? A[r * 9 + c] : (c - 9 == r ? 1.0 : 0.0);
+  for (int col = 0; col < 9; ++col) {
+    int piv = col;
+    for (int r = col + 1; r < 9; ++r)
+      if (fabs(a[r][col]) > fabs(a[piv][col])) piv = r;
+    if (piv != col)
+      for (int c = 0; c < 18; ++c) {
+        double t = a[col][c];
+        a[col][c] = a[piv][c];
+        a[piv][c] = t;
+      }
+    double d = a[col][col];
+    for (int c = 0; c < 18; ++c) a[col][c] /= d;
+    for (int r = 0; r < 9; ++r) {
+      if (r == col) continue;
+      double f = a[r][col];
+      for (int c = 0; c < 18; ++c) a[r][c] -= f * a[col][c];
+    }
+  }
+  for (int r = 0; r < 9; ++r)
+    for (int c = 0; c < 9; ++c) Ainv[r * 9 + c] = a[r][c + 9];
+}
+
+/* Relaxation rates of the nine moments: momentum and stresses at 1/tau_f
+ * (the viscosity); density, e and epsilon at one bulk rate s_b (the three
+ * moments the rest population projects on, so its non-equilibrium part keeps
+ * the BGK form with tau_f -> 1/s_b); the energy fluxes at s_q. */
+static void mrt_rates(const orc_params* p, double tau_f, double* sr) {
+  double sv = 1.0 / tau_f;
+  double sb = p->s_b > 0 ? p->s_b : sv, sq = p->s_q > 0 ? p->s_q : sv;
+  double r[9] = {sb, sb, sb, sv, sq, sv, sq, sv, sv};
+  memcpy(sr, r, sizeof r);
+}
+
+/* Rest-population non-equilibrium implied by the forcing, f_0^neq =
+ * [M^-1 (S^-1 - 1/2) M F]_0: (tau_f - 1/2) F_0 for BGK. */
+static double mrt_f0neq(const double* M, const double* Minv, const double* sr, const double* Fi) {
+  double v = 0.0;
+  for (int k = 0; k < 9; ++k) {
+    double Fm = 0.0;
+    for (int i = 0; i < 9; ++i) Fm += M[k * 9 + i] * Fi[i];
+    v += Minv[0 * 9 + k] * (1.0 / sr[k] - 0.5) * Fm;
+  }
+  return v;
+}
+
+/* Post-collision f = M^-1 [m - S (m - m^eq) + (I - S/2) M F]. */
+static void mrt_collide(const double* M, const double* Minv, const double* sr, const double* f,
+                        const double* feq, const double* Fi, double* out) {
+  double ms[9];
+  for (int k = 0; k < 9; ++k) {
+    double m = 0, me = 0, Fm = 0;
+    for (int i = 0; i < 9; ++i) {
+      m += M[k * 9 + i] * f[i];
+      me += M[k * 9 + i] * feq[i];
+      Fm += M[k * 9 + i] * Fi[i];
+    }
+    ms[k] = m - sr[k] * (m - me) + (1.0 - 0.5 * sr[k]) * Fm;
+  }
+  for (int i = 0; i < 9; ++i) {
+    double v = 0;
+    for (int k = 0; k < 9; ++k) v += Minv[i * 9 + k] * ms[k];
+    out[i] = v;
+  }
+}
+
 void orc_geq(double phi, double mu, double phiux, double phiuy, double* out) {
   for (int i = 0; i < 9; ++i) {
     double cj = CX[i] * phiux + CY[i] * phiuy;
@@ -251,6 +346,8 @@ orc_sim* orc_create(const orc_params* p) {
   for (size_t k = 0; k < sizeof one / sizeof one[0]; ++k) *one[k] = alloc0(n);
   s->wallT[WB] = alloc0(p->nx); s->wallT[WT] = alloc0(p->nx);
   s->wallT[WL] = alloc0(p->ny); s->wallT[WR] = alloc0(p->ny);
+  orc_mrt_matrix(s->mrtM);
+  orc_invert9(s->mrtM, s->mrtMinv);
   return s;
 }
 
@@ -390,16 +487,29 @@ static void pass2(orc_sim* s, int collide) {
       double uu = ux * ux + uy * uy;
       double F0 = W[0] * (S - (ux * Ftx + uy * Fty) / CS2);
       double s0 = W[0] * (-uu / (2 * CS2));
-      double pr = CS2 / (1.0 - W[0]) * (sum_nz + 0.5 * S + (tau_f - 0.5) * F0 + rho * s0);
+      double Fi[9], sr[9];
+      orc_forcing(S, Fx, Fy, rho * fdx, rho * fdy, Ftx, Fty, ux, uy, Fi);
+      /* the rest population's non-equilibrium part: (tau_f - 1/2) F_0, or
+       * its moment-space form under MRT (R53) */
+      double f0neq = (tau_f - 0.5) * F0;
+      if (p->mrt) {
+        mrt_rates(p, tau_f, sr);
+        f0neq = mrt_f0neq(s->mrtM, s->mrtMinv, sr, Fi);
+      }
+      double pr = CS2 / (1.0 - W[0]) * (sum_nz + 0.5 * S + f0neq + rho * s0);
       s->ux[k] = ux; s->uy[k] = uy; s->pr[k] = pr; s->mu[k] = mu;
       if (!collide) continue;
-      /* flow collision (Sec. 3.1) */
-      double feq[9], Fi[9];
+      /* flow collision (Sec. 3.1; MRT: R53) */
+      double feq[9], fin[9];
       orc_feq(pr, rho, ux, uy, feq);
-      orc_forcing(S, Fx, Fy, rho * fdx, rho * fdy, Ftx, Fty, ux, uy, Fi);
-      for (int i = 0; i < 9; ++i) {
-        double fi = s->f[i * n + k];
-        s->fc[i * n + k] = fi - (fi - feq[i]) / tau_f + (1.0 - 0.5 / tau_f) * Fi[i];
+      for (int i = 0; i < 9; ++i) fin[i] = s->f[i * n + k];
+      if (p->mrt) {
+        double fo[9];
+        mrt_collide(s->mrtM, s->mrtMinv, sr, fin, feq, Fi, fo);
+        for (int i = 0; i < 9; ++i) s->fc[i * n + k] = fo[i];
+      } else {
+        for (int i = 0; i < 9; ++i)
+          s->fc[i * n + k] = fin[i] - (fin[i] - feq[i]) / tau_f + (1.0 - 0.5 / tau_f) * Fi[i];
       }
       /* phase-field collision (Sec. 3.2): G_i = w_i c.d_t(phi u)/c_s^2 +
        * w_i phi div u, with a backward difference in time (R13) */

@@ -32,7 +32,8 @@ class OrcParams(C.Structure):
         (k, C.c_double) for k in (
             "rho_l", "rho_g", "rho_s", "mu_l", "mu_g", "mu_s", "lam_l", "lam_g", "lam_s",
             "cp_l", "cp_g", "cp_s", "latent", "T_m", "sigma", "eps", "mobility",
-            "cos_psi", "rho_ref", "T_substrate", "pcm_floor")]
+            "cos_psi", "rho_ref", "T_substrate", "pcm_floor")] + [
+        ("mrt", C.c_int32), ("pad2_", C.c_int32), ("s_b", C.c_double), ("s_q", C.c_double)]
 
 
 def build(force: bool = False) -> str:
@@ -67,6 +68,8 @@ def lib():
         L.orc_get_state.argtypes = [C.c_void_p, dp, dp, dp, dp]
         L.orc_set_state.argtypes = [C.c_void_p, dp, dp, dp, dp]
         L.orc_feq.argtypes = [C.c_double] * 4 + [dp]
+        L.orc_mrt_matrix.argtypes = [dp]
+        L.orc_invert9.argtypes = [dp, dp]
         L.orc_geq.argtypes = [C.c_double] * 4 + [dp]
         L.orc_heq.argtypes = [C.c_double] * 6 + [dp]
         L.orc_forcing.argtypes = [C.c_double] * 9 + [dp]
@@ -104,6 +107,8 @@ def make_params(case) -> OrcParams:
               "mobility", "cos_psi", "rho_ref", "pcm_floor"):
         setattr(p, k, float(getattr(m, k)))
     p.T_substrate = float(case.T_substrate)
+    p.mrt = int(getattr(m, "mrt", 0))
+    p.s_b, p.s_q = float(getattr(m, "s_b", 0.0)), float(getattr(m, "s_q", 0.0))
     return p
 
 
