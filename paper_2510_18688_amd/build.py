@@ -14,9 +14,11 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "liblbf.so")
-SOURCES = [os.path.join(CSRC, f) for f in ("lbf_api.hip", "lbf_adjoint.hip", "lbf_observe.hip", "lbf3_api.hip")]
+SOURCES = [os.path.join(CSRC, f) for f in ("lbf_api.hip", "lbf_adjoint.hip", "lbf_observe.hip", "lbf3_api.hip",
+                                                    "lbf_pre.hip")]
 HEADERS = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hpp", ".h"))] + [
-    os.path.join(INCLUDE, "lbf.h"), os.path.join(INCLUDE, "lbf3.h")]
+    os.path.join(INCLUDE, "lbf.h"), os.path.join(INCLUDE, "lbf3.h"),
+    os.path.join(INCLUDE, "lbf_pre.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("LBF_OFFLOAD_ARCH", "gfx950")
