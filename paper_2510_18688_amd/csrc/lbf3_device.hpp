@@ -85,14 +85,24 @@ __device__ __forceinline__ Bufs3 make_bufs3(const BufArgs3& a, int P) {
 }
 
 // Pull sources of one node: byte offset of x - c_i (the node itself across a
-// wall), the wall masks and the face of each wall link.  A link leaving
-// through several walls takes the z face, else the y face, else the x face.
+// wall), the wall mask, and the node's coordinates (a wall link's face is
+// recomputed from them: a link leaving through several walls takes the z
+// face, else the y face, else the x face).
 struct Pull19 {
   uint32_t off[NQ];
   uint32_t k4;
   uint32_t wmask;
-  uint8_t face[NQ];
+  int x, y, z;
 };
+
+// Face of the wall that link i of node (x, y, z) crosses (low face when
+// c > 0: the source x - c lies below the lattice).
+__device__ __forceinline__ int wall_face(const Geo3& G, int x, int y, int z, int i) {
+  const int sz = z - cz(i), sy = y - cy(i);
+  if (!G.per[2] && (sz < 0 || sz >= G.n[2])) return cz(i) > 0 ? 4 : 5;
+  if (!G.per[1] && (sy < 0 || sy >= G.n[1])) return cy(i) > 0 ? 2 : 3;
+  return cx(i) > 0 ? 0 : 1;
+}
 
 __device__ __forceinline__ int src_axis(int v, int c, int n, int periodic, bool& out) {
   int s = v - c;
@@ -123,9 +133,10 @@ __device__ __forceinline__ void pull19(const Geo3& G, int x, int y, int z, Pull1
     const bool w = ox || oy || oz;
     p.off[i] = w ? p.k4 : (((uint32_t)sz * G.n[1] + sy) * G.n[0] + sx) * 4u;
     p.wmask |= (uint32_t)w << i;
-    // the face whose rule applies: z first, then y, then x; low when c > 0
-    p.face[i] = oz ? (cz(i) > 0 ? 4 : 5) : (oy ? (cy(i) > 0 ? 2 : 3) : (cx(i) > 0 ? 0 : 1));
   }
+  p.x = x;
+  p.y = y;
+  p.z = z;
 }
 
 // Pulled g of a node (bounce-back at every wall).
@@ -151,7 +162,7 @@ __device__ __forceinline__ void pull_h3(const Geo3& G, const Phys& ph, const Buf
     for (int i = 1; i < NQ; ++i) {
       if ((n.wmask >> i) & 1u) {
         const float hb = lbf::ldo(B.hin, n.k4, opp(i), G.P);
-        const int f = n.face[i];
+        const int f = wall_face(G, n.x, n.y, n.z, i);
         hv[i] = ((G.tmask >> f) & 1) ? -hb + 2.0f * wgt(i) * ph.Eref * G.Tw[f] : hb;
       }
     }

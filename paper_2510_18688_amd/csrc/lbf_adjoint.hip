@@ -163,6 +163,7 @@ int lbf_tape_create(lbf_sim* sim, int32_t nsteps, int32_t segment, lbf_tape** ou
   if (!out) return fail(LBF_EINVAL, "out is NULL");
   *out = nullptr;
   if (!sim) return fail(LBF_EINVAL, "sim is NULL");
+  if (sim->prm.mrt) return fail(LBF_EINVAL, "the adjoint supports the BGK flow collision only");
   if (nsteps < 0) return fail(LBF_EINVAL, "nsteps %d", nsteps);
   if (segment < 0) return fail(LBF_EINVAL, "segment %d", segment);
   lbf_tape* t = new lbf_tape();

@@ -54,6 +54,14 @@ __host__ __device__ constexpr float wgt(int i) {
   return i == 0 ? 4.0f / 9.0f : (i <= 4 ? 1.0f / 9.0f : 1.0f / 36.0f);
 }
 
+// Values at the D2Q9 velocities of the moment polynomials that an MRT
+// collision relaxes away from the viscous rate: energy -4 + 3c^2, energy
+// square 4 - 21/2 c^2 + 9/2 c^4, energy fluxes (-5 + 3c^2) c_x, (-5 + 3c^2) c_y.
+__host__ __device__ constexpr float mrt_e(int i) { return i == 0 ? -4.0f : (i <= 4 ? -1.0f : 2.0f); }
+__host__ __device__ constexpr float mrt_eps(int i) { return i == 0 ? 4.0f : (i <= 4 ? -2.0f : 1.0f); }
+__host__ __device__ constexpr float mrt_qx(int i) { return i <= 4 ? -2.0f * cx(i) : (float)cx(i); }
+__host__ __device__ constexpr float mrt_qy(int i) { return i <= 4 ? -2.0f * cy(i) : (float)cy(i); }
+
 // Lattice geometry and boundary types.
 struct Geo {
   int nx, ny;
@@ -78,6 +86,8 @@ struct Phys {
   float pcm_floor;   // liquid weight below which a node holds no phase-change material
   float inv_pcm_span; // 1 / (1 - pcm_floor)
   int latch, src_tau_a, subfix;
+  int mrt;           // 1: MRT flow collision
+  float s_b, s_q;    // MRT bulk and energy-flux rates (0: 1/tau_f)
 };
 
 // Buffers of one lattice.  Device arrays are addressed through buffer
@@ -433,8 +443,13 @@ __device__ __forceinline__ void collide_node(const Phys& ph, const Mom& m, const
   const float uu = ux * ux + uy * uy;
   const float uFt = ux * Ftx + uy * Fty;
   const float F0 = wgt(0) * (Sm - 3.0f * uFt);
+  // the rest population's non-equilibrium part (tau - 1/2) F_0: tau = tau_f,
+  // or 1/s_b under MRT (the density, e and epsilon moments it projects on
+  // relax at s_b)
+  const bool mrt_b = ph.mrt && ph.s_b > 0.0f;
+  const float tau_0 = mrt_b ? rcp(ph.s_b) : tau_f;
   const float p = (1.0f / 3.0f) / (1.0f - wgt(0)) *
-                  (sum_nz + 0.5f * Sm + (tau_f - 0.5f) * F0 - 1.5f * wgt(0) * rho * uu);
+                  (sum_nz + 0.5f * Sm + (tau_0 - 0.5f) * F0 - 1.5f * wgt(0) * rho * uu);
   o.ux = ux; o.uy = uy; o.p = p; o.mu = mu;
   const float jx = phi * ux, jy = phi * uy;
   o.jx = jx; o.jy = jy;
@@ -449,15 +464,45 @@ __device__ __forceinline__ void collide_node(const Phys& ph, const Mom& m, const
   const float inv_tau_f = rcp(tau_f);
   const float pf = 1.0f - 0.5f * inv_tau_f;
   const float rfx = rho * fdx + Fx, rfy = rho * fdy + Fy;
+  if (!ph.mrt) {
 #pragma unroll
-  for (int i = 0; i < 9; ++i) {
-    const float cu = cx(i) * ux + cy(i) * uy;
-    const float cF = cx(i) * rfx + cy(i) * rfy;
-    const float cFt = cx(i) * Ftx + cy(i) * Fty;
-    const float feq = 3.0f * p * (wgt(i) - (i == 0 ? 1.0f : 0.0f)) +
-                      rho * wgt(i) * (3.0f * cu + 4.5f * cu * cu - 1.5f * uu);
-    const float Fi = wgt(i) * (Sm + 3.0f * cF + 9.0f * cu * cFt - 3.0f * uFt);
-    fv[i] = fv[i] - (fv[i] - feq) * inv_tau_f + pf * Fi;
+    for (int i = 0; i < 9; ++i) {
+      const float cu = cx(i) * ux + cy(i) * uy;
+      const float cF = cx(i) * rfx + cy(i) * rfy;
+      const float cFt = cx(i) * Ftx + cy(i) * Fty;
+      const float feq = 3.0f * p * (wgt(i) - (i == 0 ? 1.0f : 0.0f)) +
+                        rho * wgt(i) * (3.0f * cu + 4.5f * cu * cu - 1.5f * uu);
+      const float Fi = wgt(i) * (Sm + 3.0f * cF + 9.0f * cu * cFt - 3.0f * uFt);
+      fv[i] = fv[i] - (fv[i] - feq) * inv_tau_f + pf * Fi;
+    }
+  } else {
+    // MRT in the orthogonal basis (density, e, epsilon, j, q, p_xx, p_xy):
+    // the BGK update plus, for the moments relaxing at s_b (density, e,
+    // epsilon) and s_q (q_x, q_y), -(s_k - 1/tau_f) r_k / |r_k|^2 d_k with
+    // d_k = sum_i r_k(c_i) (f_i - f_i^eq + F_i / 2)
+    float d[5] = {0, 0, 0, 0, 0};
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      const float cu = cx(i) * ux + cy(i) * uy;
+      const float cF = cx(i) * rfx + cy(i) * rfy;
+      const float cFt = cx(i) * Ftx + cy(i) * Fty;
+      const float feq = 3.0f * p * (wgt(i) - (i == 0 ? 1.0f : 0.0f)) +
+                        rho * wgt(i) * (3.0f * cu + 4.5f * cu * cu - 1.5f * uu);
+      const float Fi = wgt(i) * (Sm + 3.0f * cF + 9.0f * cu * cFt - 3.0f * uFt);
+      const float neq = fv[i] - feq + 0.5f * Fi;
+      fv[i] = fv[i] - inv_tau_f * neq + Fi;
+      d[0] += neq;
+      d[1] += mrt_e(i) * neq;
+      d[2] += mrt_eps(i) * neq;
+      d[3] += mrt_qx(i) * neq;
+      d[4] += mrt_qy(i) * neq;
+    }
+    const float db = (mrt_b ? ph.s_b : inv_tau_f) - inv_tau_f;
+    const float dq = (ph.s_q > 0.0f ? ph.s_q : inv_tau_f) - inv_tau_f;
+#pragma unroll
+    for (int i = 0; i < 9; ++i)
+      fv[i] -= db * ((1.0f / 9.0f) * d[0] + (1.0f / 36.0f) * (mrt_e(i) * d[1] + mrt_eps(i) * d[2])) +
+               dq * (1.0f / 12.0f) * (mrt_qx(i) * d[3] + mrt_qy(i) * d[4]);
   }
   // phase field (Sec. 3.2)
   const float inv_tau_g = ph.inv_tau_g;

@@ -1,6 +1,6 @@
 """Host-side checks of the C ABI (no GPU): the library loads, exports every
-entry point that include/lbf.h and include/lbf3.h declare, both parameter
-structs match the binding's, and parameter validation rejects bad sets
+entry point that include/lbf.h, include/lbf3.h and include/lbf_pre.h
+declare, the parameter structs match the binding's, and parameter validation rejects bad sets
 before touching a device."""
 
 import ctypes as C
@@ -14,7 +14,7 @@ import pytest
 from paper_2510_18688_amd import lbf, workloads as W
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADERS = [os.path.join(ROOT, "include", h) for h in ("lbf.h", "lbf3.h")]
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("lbf.h", "lbf3.h", "lbf_pre.h")]
 
 
 @pytest.fixture(scope="module")
@@ -35,18 +35,20 @@ def declared_functions():
 
 def test_exports_every_declared_symbol(L):
     names = declared_functions()
-    assert len(names) >= 25 and "lbf3_step" in names
+    assert len(names) >= 27 and "lbf3_step" in names and "lbf_ch_smooth" in names
     for n in names:
         assert hasattr(L, n), n
-    assert set(lbf.EXPORTS) <= set(names)
+    from paper_2510_18688_amd import porous
+    assert set(lbf.EXPORTS) | set(porous.EXPORTS) == set(names)
 
 
 def test_params_layout_matches_header(tmp_path):
     src = tmp_path / "sz.c"
     src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "lbf.h"\n'
-                   'int main(void){printf("%zu %zu %zu %zu\\n", sizeof(lbf_params),'
+                   'int main(void){printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(lbf_params),'
                    ' offsetof(lbf_params, rho_l), offsetof(lbf_params, T_substrate),'
-                   ' offsetof(lbf_params, thermal_bc));return 0;}\n')
+                   ' offsetof(lbf_params, thermal_bc), offsetof(lbf_params, mrt),'
+                   ' offsetof(lbf_params, s_q));return 0;}\n')
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()
@@ -55,6 +57,7 @@ def test_params_layout_matches_header(tmp_path):
     assert int(out[1]) == P.rho_l.offset
     assert int(out[2]) == P.T_substrate.offset
     assert int(out[3]) == P.thermal_bc.offset
+    assert int(out[4]) == P.mrt.offset and int(out[5]) == P.s_q.offset
 
 
 def test_params3_layout_matches_header(tmp_path):
@@ -94,6 +97,9 @@ def _create_rc(L, case):
     (lambda c: setattr(c.mat, "eps", -4.0), "positive"),
     (lambda c: setattr(c.mat, "pcm_floor", 1.0), "pcm_floor"),
     (lambda c: setattr(c, "thermal_bc", [2, 0, 0, 0]), "thermal_bc"),
+    (lambda c: (setattr(c.mat, "mrt", 1), setattr(c.mat, "s_b", 2.0)), "MRT rates"),
+    (lambda c: (setattr(c.mat, "mrt", 1), setattr(c.mat, "s_q", -0.1)), "MRT rates"),
+    (lambda c: setattr(c.mat, "mrt", 2), "mrt = 2"),
 ])
 def test_invalid_params_rejected_on_host(L, mutate, needle):
     case = W.sessile_drop(nx=16, ny=8)
@@ -153,3 +159,38 @@ def test_binding_refuses_without_device(monkeypatch):
         pytest.skip("a device is present")
     with pytest.raises(RuntimeError, match="HIP device"):
         lbf.Sim(W.sessile_drop(nx=16, ny=8))
+
+
+def test_ch_params_layout_matches_header(tmp_path):
+    from paper_2510_18688_amd import porous
+    src = tmp_path / "szch.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "lbf_pre.h"\n'
+                   'int main(void){printf("%zu %zu %zu\\n", sizeof(lbf_ch_params),'
+                   ' offsetof(lbf_ch_params, A), offsetof(lbf_ch_params, dt));return 0;}\n')
+    exe = tmp_path / "szch"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()
+    P = porous.ChParams
+    assert [int(v) for v in out] == [C.sizeof(P), P.A.offset, P.dt.offset]
+
+
+@pytest.mark.parametrize("change, needle", [
+    (dict(nx=0), "image size"),
+    (dict(dt=0.05), "stability bound"),
+    (dict(kappa=-1.0), "A, kappa, mobility"),
+    (dict(dt=float("nan")), "A, kappa, mobility"),
+])
+def test_ch_invalid_params_rejected_on_host(L, change, needle):
+    from paper_2510_18688_amd import porous
+    porous._declare(L)
+    p = porous.ch_params((8, 8), (False, False))
+    for k, v in change.items():
+        setattr(p, k, v)
+    buf = (C.c_uint8 * 64)()
+    out = (C.c_float * 64)()
+    rc = L.lbf_ch_smooth(C.byref(p), buf, 0, out, 0, 1, None, None, 0)
+    assert rc == -1 and needle in L.lbf_last_error().decode()
+    assert L.lbf_ch_smooth(C.byref(p), None, 0, out, 0, 1, None, None, 0) == -1
+    assert L.lbf_ch_workspace_bytes(0, 1, 1) == 0
+    assert L.lbf_ch_workspace_bytes(65536, 65536, 1) == 0
+    assert L.lbf_ch_workspace_bytes(10, 10, 1) == 2 * 512

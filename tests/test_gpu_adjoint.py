@@ -213,7 +213,8 @@ def test_gradient_workload_256_against_fp64_reference(lbf_mod):
     J.backward()
     g = np.concatenate([theta.grad.cpu().numpy(), tw.grad.cpu().numpy()])
     gr = np.asarray(ref["grad"])
-    assert abs(float(J) - ref["J0"]) <= 1e-3 * ref["J0"], (float(J), ref["J0"])
+    Jv = float(J.detach())
+    assert abs(Jv - ref["J0"]) <= 1e-3 * ref["J0"], (Jv, ref["J0"])
     cos = float(g @ gr) / (np.linalg.norm(g) * np.linalg.norm(gr))
     rel = float(np.linalg.norm(g - gr) / np.linalg.norm(gr))
     rng = np.random.default_rng(ref["direction_seed"])

@@ -111,3 +111,4 @@ def test_degenerate_lattices(lbf_mod, O3, shape):
     sim.step(3)
     orc.step(3)
     compare(sim.fields(), orc.fields(), 2e-5, case.name, ["phi", "T", "fs", "rhoH", "C", "chi"])
+
