@@ -37,6 +37,9 @@ HBM_PEAK_GBS = 8000.0
 BYTES3_MOMENTS = (38 + 4 + 1) * 4 + 3 * 4
 BYTES3_STEP = (57 + 8 + 3 + 3) * 4 + (57 + 8) * 4
 BYTES3_STATE = (57 + 8) * 2 * 4 + 3 * 4
+# Cahn-Hilliard smoothing, per node and Euler step (one fused pass): c read
+# once and the new c written once.
+BYTES_CH = 4 + 4
 
 
 def hbm_traffic(kernel_ms, name="step_kernel_curved_substrate_2048x2048"):
@@ -73,6 +76,10 @@ def parse():
                     help="steps of the 256 x 256 gradient workload (0 skips it)")
     ap.add_argument("--d3q19-steps", type=int, default=200,
                     help="steps of the D3Q19 workloads (0 skips them)")
+    ap.add_argument("--mrt-steps", type=int, default=1000,
+                    help="steps of the headline workload with the MRT flow collision (0 skips)")
+    ap.add_argument("--ch-iterations", type=int, default=500,
+                    help="Euler steps of the Cahn-Hilliard smoothing workloads (0 skips them)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run an elementwise copy of MIB MiB (read + write), the "
                          "reference kernel for scaling HBM byte counters")
@@ -234,6 +241,64 @@ def d3q19(lbf, torch, steps):
     return out
 
 
+def mrt(lbf, W, torch, steps, tile):
+    """The headline workload with the MRT flow collision (bulk rate 1.5,
+    energy-flux rate 1.2): the same state and bytes per update as BGK."""
+    case = W.curved_substrate()
+    case.mat.mrt, case.mat.s_b, case.mat.s_q = 1, 1.5, 1.2
+    sim = lbf.Sim(case, tile=tile)
+    sim.step(50)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    sim.set_timing(True)
+    sim.step(steps)
+    kms = sim.last_step_kernel_ms()
+    red = sim.reduce()
+    sim.close()
+    gbs = BYTES_PER_LU * case.nodes / (kms * 1e-3) / 1e9
+    return {"workload": case.name + " with MRT (s_b 1.5, s_q 1.2)", "steps": steps,
+            "mlups": round(case.nodes * steps / wall / 1e6, 1),
+            "kernel_ms": round(kms, 5), "achieved_gbs": round(gbs, 1),
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "nonfinite": red["nonfinite"]}
+
+
+def ch_smoothing(torch, iterations):
+    """Porous pre-processing: Cahn-Hilliard smoothing of a synthetic sandpack
+    image (porosity 0.3585, log-normal grains), 2D 4096 x 2048 with walls and
+    3D 256^3 with walls normal to x; image and result resident on the
+    device."""
+    from paper_2510_18688_amd import lbf, porous, workloads as W
+    L = lbf.load()
+    porous._declare(L)
+    out = {}
+    for label, shape, per in (("sandpack_4096x2048", (2048, 4096), (False, False)),
+                              ("sandpack_256x256x256", (256, 256, 256), (False, True, True))):
+        img = torch.as_tensor(W.sandpack_image(shape, seed=12, periodic=per), device="cuda")
+        p = porous.ch_params(shape, per)
+        ws = torch.empty(L.lbf_ch_workspace_bytes(p.nx, p.ny, p.nz), dtype=torch.uint8,
+                         device="cuda")
+        porous.ch_smooth(img, per, 10, workspace=ws)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        phi0 = porous.ch_smooth(img, per, iterations, workspace=ws)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        n = img.numel()
+        gbs = BYTES_CH * n * iterations / wall / 1e9
+        out[label] = {"nodes": n, "iterations": iterations, "ms": round(wall * 1e3, 3),
+                      "us_per_iteration": round(wall / iterations * 1e6, 2),
+                      "mlups": round(n * iterations / wall / 1e6, 1),
+                      "bytes_per_lu": BYTES_CH, "achieved_gbs": round(gbs, 1),
+                      "frac": round(gbs / HBM_PEAK_GBS, 4),
+                      "solid_fraction": round(float(phi0.double().mean()), 5)}
+        del img, ws, phi0
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -327,8 +392,12 @@ def main():
         out["batched"] = batched(lbf, W, torch, args.batch_steps)
     if args.adjoint_steps > 0:
         out["adjoint"] = adjoint(lbf, W, torch, args.adjoint_steps)
+    if args.mrt_steps > 0:
+        out["mrt"] = mrt(lbf, W, torch, args.mrt_steps, tile)
     if args.d3q19_steps > 0:
         out["d3q19"] = d3q19(lbf, torch, args.d3q19_steps)
+    if args.ch_iterations > 0:
+        out["ch_smoothing"] = ch_smoothing(torch, args.ch_iterations)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(case, args.cpu_seconds)
     print(json.dumps(out), flush=True)
