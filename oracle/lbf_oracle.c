@@ -56,6 +56,8 @@ typedef struct {
   int32_t pad2_;
   double s_b, s_q;            /* MRT rates: density, e and epsilon moments; energy flux
                                  (0: the BGK rate 1/tau_f) */
+  double s_g;                 /* MRT rate of the phase-field moments above first order
+                                 (0: the BGK rate 1/tau_g) */
 } orc_params;
 
 enum { WB = 0, WT = 1, WL = 2, WR = 3 };
@@ -517,10 +519,21 @@ static void pass2(orc_sim* s, int collide) {
       double geq[9];
       orc_geq(phi, mu, jx, jy, geq);
       double djx = jx - s->phiux_prev[k], djy = jy - s->phiuy_prev[k];
+      double Gv[9], gin[9];
       for (int i = 0; i < 9; ++i) {
-        double Gi = W[i] * (CX[i] * djx + CY[i] * djy) / CS2 + W[i] * phi * mdot;
-        double gi = s->g[i * n + k];
-        s->gc[i * n + k] = gi - (gi - geq[i]) / tau_g + (1.0 - 0.5 / tau_g) * Gi;
+        Gv[i] = W[i] * (CX[i] * djx + CY[i] * djy) / CS2 + W[i] * phi * mdot;
+        gin[i] = s->g[i * n + k];
+      }
+      if (p->mrt) {
+        /* MRT (R53): the zeroth and first moments at 1/tau_g (the mobility),
+         * the moments above first order at s_g */
+        double sv = 1.0 / tau_g, sg = p->s_g > 0 ? p->s_g : sv;
+        double srg[9] = {sv, sg, sg, sv, sg, sv, sg, sg, sg}, go[9];
+        mrt_collide(s->mrtM, s->mrtMinv, srg, gin, geq, Gv, go);
+        for (int i = 0; i < 9; ++i) s->gc[i * n + k] = go[i];
+      } else {
+        for (int i = 0; i < 9; ++i)
+          s->gc[i * n + k] = gin[i] - (gin[i] - geq[i]) / tau_g + (1.0 - 0.5 / tau_g) * Gv[i];
       }
       /* enthalpy TRT collision (Sec. 3.3, eq22; R7, R8, R9) */
       double rhocp = rho * cp;

@@ -62,12 +62,14 @@ class Material:
     pcm_floor: float = 0.01
     latch_fs: int = 1
     h_src_tau_a: int = 0
-    # flow collision: 0 BGK (Sec. 3.1), 1 MRT with the bulk rate s_b (density,
-    # energy and energy-square moments) and the energy-flux rate s_q; 0 stands
-    # for the BGK rate 1/tau_f
+    # flow and phase-field collisions: 0 BGK (Sec. 3.1, 3.2), 1 MRT with the
+    # bulk rate s_b (density, energy and energy-square moments of f), the
+    # energy-flux rate s_q of f and the rate s_g of the moments of g above
+    # first order; 0 stands for the BGK rate (1/tau_f, 1/tau_g)
     mrt: int = 0
     s_b: float = 0.0
     s_q: float = 0.0
+    s_g: float = 0.0
 
     def as_dict(self) -> Dict[str, float]:
         return dataclasses.asdict(self)

@@ -13,7 +13,11 @@
   nu k^2 with nu = mu / rho whatever the other rates are;
 * the static drop under MRT reaches the BGK drop's pressure jump (the
   equilibrium cannot depend on the rates) within the 2D Laplace law's bar:
-  this checks the pressure recovery with a bulk rate away from 1/tau_f.
+  this checks the pressure recovery with a bulk rate away from 1/tau_f;
+* phase field: a perturbation of g along any moment but the zeroth decays
+  by exactly (1 - s) per step, s = 1/tau_g for the first moments and s_g
+  above (the first moment of g does not feed the velocity); the flat
+  interface stays the model's equilibrium under MRT.
 """
 
 import ctypes as C
@@ -124,11 +128,41 @@ def test_shear_wave_viscosity(oracle_mod, mat):
     assert abs(nu / (mat.mu_l / mat.rho_l) - 1.0) < 0.01, nu
 
 
+@pytest.mark.parametrize("row", range(1, 9))
+def test_phase_field_moment_relaxes_at_its_rate(oracle_mod, row):
+    mat = W.Material(mrt=1, s_b=1.5, s_q=1.15, s_g=1.35)
+    o = _rest_lattice(oracle_mod, mat)
+    f, g, h, lag = o.get_state()
+    g0 = g.copy()
+    delta = 1e-3            # g is O(1): the perturbation must stand well above its rounding
+    o.set_state(f, g + delta * polynomials()[row][:, None, None], h, lag)
+    o.step(1)
+    g1 = o.get_state()[1]
+    s = 1.0 / (3.0 * mat.mobility + 0.5) if row in (3, 5) else mat.s_g
+    expect = g0 + (1.0 - s) * delta * polynomials()[row][:, None, None]
+    assert np.abs(g1 - expect).max() < 1e-14, (row, np.abs(g1 - expect).max())
+
+
+def test_flat_interface_stationary_under_mrt(oracle_mod):
+    mat = W.Material(mrt=1, s_b=1.5, s_q=1.2, s_g=1.4)
+    nx, ny = 4, 64
+    yy = np.arange(ny, dtype=float)[:, None] * np.ones((1, nx))
+    phi = np.tanh(2 * (yy - 15.5) / mat.eps) * np.tanh(2 * (47.5 - yy) / mat.eps)
+    z = np.zeros((ny, nx))
+    case = W.Case("flat_mrt", nx, ny, True, True, [0, 0, 0, 0], {}, z.copy(), z.copy(), phi,
+                  np.ones((ny, nx)), mat)
+    o = oracle_mod.Oracle(case)
+    o.step(10000)
+    assert np.abs(o.fields()["phi"] - phi).max() < 2e-2
+    assert o.reduce()["umax"] < 1e-6
+
+
 def test_laplace_law_under_mrt(oracle_mod):
     """8000 steps: BGK gives 0.9636 sigma/R here and the MRT drop (s_b 1.5,
-    s_q 1.2) 0.9627, both converging to 0.9736 by 16000 steps."""
+    s_q 1.2) 0.9627, both converging to 0.9736 by 16000 steps; the phase
+    field under MRT too (s_g 1.4)."""
     n, R = 80, 16.0
-    mat = W.Material(mrt=1, s_b=1.5, s_q=1.2)
+    mat = W.Material(mrt=1, s_b=1.5, s_q=1.2, s_g=1.4)
     yy, xx = np.mgrid[0:n, 0:n].astype(float)
     phi = np.tanh(2 * (R - np.hypot(xx - n / 2, yy - n / 2)) / mat.eps)
     z = np.zeros((n, n))
