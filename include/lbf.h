@@ -103,16 +103,18 @@ typedef struct lbf_params {
   double pcm_floor;            /* liquid weight below which a node holds no phase-change
                                   material, in [0, 1) (0.01 keeps gas fluctuations from
                                   freezing) */
-  /* Flow collision (Sec. 3.1 uses BGK and names MRT as the extension): 0 BGK;
-   * 1 MRT in the orthogonal D2Q9 moment basis (density, energy e, energy
-   * square epsilon, momentum j, energy flux q, stresses p_xx, p_xy), with
+  /* Flow and phase-field collisions (Sec. 3.1 and 3.2 use BGK and name MRT
+   * as the extension): 0 BGK; 1 MRT in the orthogonal D2Q9 moment basis
+   * (density, energy e, energy square epsilon, momentum j, energy flux q,
+   * stresses p_xx, p_xy) with the source terms applied in moment space.  f:
    * j and the stresses at the viscous rate 1/tau_f, density, e and epsilon at
-   * the bulk rate s_b, q at s_q, and the forcing applied in moment space.
-   * A rate of 0 stands for 1/tau_f (mrt = 1 with both 0 is BGK).  Rates in
+   * the bulk rate s_b, q at s_q.  g: the zeroth and first moments at 1/tau_g
+   * (the mobility), the moments above first order at s_g.  A rate of 0
+   * stands for the BGK rate (mrt = 1 with all three 0 is BGK).  Rates in
    * [0, 2).  The adjoint (lbf_tape_*) supports BGK only. */
   int32_t mrt;
   int32_t reserved2;
-  double s_b, s_q;
+  double s_b, s_q, s_g;
 } lbf_params;
 
 typedef struct lbf_sim lbf_sim;

@@ -101,8 +101,10 @@ int validate(const lbf_params* p) {
     if (p->thermal_bc[w] != LBF_ADIABATIC && p->thermal_bc[w] != LBF_DIRICHLET)
       return fail(LBF_EINVAL, "thermal_bc[%d] = %d", w, p->thermal_bc[w]);
   if (p->mrt != 0 && p->mrt != 1) return fail(LBF_EINVAL, "mrt = %d", p->mrt);
-  if (p->mrt && !(p->s_b >= 0.0 && p->s_b < 2.0 && p->s_q >= 0.0 && p->s_q < 2.0))
-    return fail(LBF_EINVAL, "MRT rates s_b = %g, s_q = %g must be in [0, 2)", p->s_b, p->s_q);
+  if (p->mrt && !(p->s_b >= 0.0 && p->s_b < 2.0 && p->s_q >= 0.0 && p->s_q < 2.0 &&
+                  p->s_g >= 0.0 && p->s_g < 2.0))
+    return fail(LBF_EINVAL, "MRT rates s_b = %g, s_q = %g, s_g = %g must be in [0, 2)", p->s_b,
+                p->s_q, p->s_g);
   const double cpref = 2.0 * p->cp_s * p->cp_l / (p->cp_s + p->cp_l);
   const double kmin = std::min({p->rho_l, p->rho_g, p->rho_s}) *
                       std::min({p->cp_l, p->cp_g, p->cp_s});
@@ -140,6 +142,7 @@ void fill_phys(const lbf_params* p, Phys& ph) {
   ph.mrt = p->mrt ? 1 : 0;
   ph.s_b = p->mrt ? (float)p->s_b : 0.0f;
   ph.s_q = p->mrt ? (float)p->s_q : 0.0f;
+  ph.s_g = p->mrt ? (float)p->s_g : 0.0f;
 }
 
 // ---------------------------------------------------------------- kernels

@@ -55,12 +55,15 @@ __host__ __device__ constexpr float wgt(int i) {
 }
 
 // Values at the D2Q9 velocities of the moment polynomials that an MRT
-// collision relaxes away from the viscous rate: energy -4 + 3c^2, energy
-// square 4 - 21/2 c^2 + 9/2 c^4, energy fluxes (-5 + 3c^2) c_x, (-5 + 3c^2) c_y.
+// collision relaxes away from the BGK rate: energy -4 + 3c^2, energy square
+// 4 - 21/2 c^2 + 9/2 c^4, energy fluxes (-5 + 3c^2) c_x, (-5 + 3c^2) c_y,
+// stresses c_x^2 - c_y^2, c_x c_y.
 __host__ __device__ constexpr float mrt_e(int i) { return i == 0 ? -4.0f : (i <= 4 ? -1.0f : 2.0f); }
 __host__ __device__ constexpr float mrt_eps(int i) { return i == 0 ? 4.0f : (i <= 4 ? -2.0f : 1.0f); }
 __host__ __device__ constexpr float mrt_qx(int i) { return i <= 4 ? -2.0f * cx(i) : (float)cx(i); }
 __host__ __device__ constexpr float mrt_qy(int i) { return i <= 4 ? -2.0f * cy(i) : (float)cy(i); }
+__host__ __device__ constexpr float mrt_pxx(int i) { return (float)(cx(i) * cx(i) - cy(i) * cy(i)); }
+__host__ __device__ constexpr float mrt_pxy(int i) { return (float)(cx(i) * cy(i)); }
 
 // Lattice geometry and boundary types.
 struct Geo {
@@ -86,8 +89,9 @@ struct Phys {
   float pcm_floor;   // liquid weight below which a node holds no phase-change material
   float inv_pcm_span; // 1 / (1 - pcm_floor)
   int latch, src_tau_a, subfix;
-  int mrt;           // 1: MRT flow collision
-  float s_b, s_q;    // MRT bulk and energy-flux rates (0: 1/tau_f)
+  int mrt;           // 1: MRT flow and phase-field collisions
+  float s_b, s_q;    // MRT bulk and energy-flux rates of f (0: 1/tau_f)
+  float s_g;         // MRT rate of the moments of g above first order (0: 1/tau_g)
 };
 
 // Buffers of one lattice.  Device arrays are addressed through buffer
@@ -509,14 +513,42 @@ __device__ __forceinline__ void collide_node(const Phys& ph, const Mom& m, const
   const float pg = ph.pg;
   const float djx = jx - jx_prev, djy = jy - jy_prev;
   const float pm = phi * mdot;
+  if (!(ph.mrt && ph.s_g > 0.0f)) {
 #pragma unroll
-  for (int i = 0; i < 9; ++i) {
-    const float cj = cx(i) * jx + cy(i) * jy;
-    // rest population: equilibrium relative to the node's reference
-    const float geq = (i == 0 ? m.dphi : 0.0f) + (wgt(i) - (i == 0 ? 1.0f : 0.0f)) * mu +
-                      3.0f * wgt(i) * cj;
-    const float Gi = wgt(i) * (3.0f * (cx(i) * djx + cy(i) * djy) + pm);
-    gv[i] = gv[i] - (gv[i] - geq) * inv_tau_g + pg * Gi;
+    for (int i = 0; i < 9; ++i) {
+      const float cj = cx(i) * jx + cy(i) * jy;
+      // rest population: equilibrium relative to the node's reference
+      const float geq = (i == 0 ? m.dphi : 0.0f) + (wgt(i) - (i == 0 ? 1.0f : 0.0f)) * mu +
+                        3.0f * wgt(i) * cj;
+      const float Gi = wgt(i) * (3.0f * (cx(i) * djx + cy(i) * djy) + pm);
+      gv[i] = gv[i] - (gv[i] - geq) * inv_tau_g + pg * Gi;
+    }
+  } else {
+    // MRT: the BGK update plus -(s_g - 1/tau_g) r_k / |r_k|^2 d_k over the
+    // moments above first order (e, epsilon, q_x, q_y, p_xx, p_xy), with
+    // d_k = sum_i r_k(c_i) (g_i - g_i^eq + G_i / 2)
+    float d[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      const float cj = cx(i) * jx + cy(i) * jy;
+      const float geq = (i == 0 ? m.dphi : 0.0f) + (wgt(i) - (i == 0 ? 1.0f : 0.0f)) * mu +
+                        3.0f * wgt(i) * cj;
+      const float Gi = wgt(i) * (3.0f * (cx(i) * djx + cy(i) * djy) + pm);
+      const float neq = gv[i] - geq + 0.5f * Gi;
+      gv[i] = gv[i] - inv_tau_g * neq + Gi;
+      d[0] += mrt_e(i) * neq;
+      d[1] += mrt_eps(i) * neq;
+      d[2] += mrt_qx(i) * neq;
+      d[3] += mrt_qy(i) * neq;
+      d[4] += mrt_pxx(i) * neq;
+      d[5] += mrt_pxy(i) * neq;
+    }
+    const float dg = ph.s_g - inv_tau_g;
+#pragma unroll
+    for (int i = 0; i < 9; ++i)
+      gv[i] -= dg * ((1.0f / 36.0f) * (mrt_e(i) * d[0] + mrt_eps(i) * d[1]) +
+                     (1.0f / 12.0f) * (mrt_qx(i) * d[2] + mrt_qy(i) * d[3]) +
+                     0.25f * (mrt_pxx(i) * d[4] + mrt_pxy(i) * d[5]));
   }
   // renormalise g_0 = hi + lo: hi' = fl(hi + d), lo' = the exact residual
   two_sum(m.ref_g, gv[0], o.ghi, gv[0]);

@@ -54,7 +54,8 @@ class Params(C.Structure):
             "rho_l", "rho_g", "rho_s", "mu_l", "mu_g", "mu_s", "lam_l", "lam_g", "lam_s",
             "cp_l", "cp_g", "cp_s", "latent", "T_m", "sigma", "eps", "mobility", "cos_psi",
             "rho_ref", "T_substrate", "pcm_floor")] + [
-        ("mrt", C.c_int32), ("reserved2", C.c_int32), ("s_b", C.c_double), ("s_q", C.c_double)]
+        ("mrt", C.c_int32), ("reserved2", C.c_int32), ("s_b", C.c_double), ("s_q", C.c_double),
+        ("s_g", C.c_double)]
 
 
 _lib = None
@@ -140,6 +141,7 @@ def make_params(case) -> Params:
     p.T_substrate = float(case.T_substrate)
     p.mrt = int(getattr(m, "mrt", 0))
     p.s_b, p.s_q = float(getattr(m, "s_b", 0.0)), float(getattr(m, "s_q", 0.0))
+    p.s_g = float(getattr(m, "s_g", 0.0))
     return p
 
 

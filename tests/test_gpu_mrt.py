@@ -1,10 +1,11 @@
-"""GPU parity of the MRT flow collision (needs a device): element by element
-against the FP64 oracle's MRT on the same seeded inputs after 1 and 300
-steps (freezing drops with flow, a porous medium with walls, a held curved
-substrate, a ragged lattice, two rate sets), the full 2048 x 2048 workload
-in its benchmark launch shape after 20 steps, zero rates equal to BGK, the
-batched launch equal to single-lattice steps bit for bit, and the adjoint's
-refusal."""
+"""GPU parity of the MRT flow and phase-field collisions (needs a device):
+element by element against the FP64 oracle's MRT on the same seeded inputs
+after 1 and 300 steps (freezing drops with flow, a porous medium with
+walls, a held curved substrate, a ragged lattice; three rate sets: flow
+only, flow and phase field, phase field only), the full 2048 x 2048
+workload in its benchmark launch shape after 20 steps, zero rates equal to
+BGK, the batched launch equal to single-lattice steps bit for bit, and the
+adjoint's refusal."""
 
 import numpy as np
 import pytest
@@ -44,7 +45,8 @@ def compare(gpu, orc, names, tol, label):
     print(label, {k: f"{v:.1e}" for k, v in worst.items()}, flush=True)
 
 
-RATES = {"b1.5_q1.2": dict(s_b=1.5, s_q=1.2), "b0.9_q1.8": dict(s_b=0.9, s_q=1.8)}
+RATES = {"b1.5_q1.2": dict(s_b=1.5, s_q=1.2), "b0.9_q1.8_g1.4": dict(s_b=0.9, s_q=1.8, s_g=1.4),
+         "g0.8": dict(s_g=0.8)}
 
 
 def mrt_cases(rates):
@@ -80,7 +82,7 @@ def test_mrt_matches_oracle(lbf_mod, O, rates, name):
 def test_mrt_full_size(lbf_mod, O):
     from paper_2510_18688_amd import autotune
     case = W.curved_substrate()
-    case.mat.mrt, case.mat.s_b, case.mat.s_q = 1, 1.5, 1.2
+    case.mat.mrt, case.mat.s_b, case.mat.s_q, case.mat.s_g = 1, 1.5, 1.2, 1.4
     sim = lbf_mod.Sim(case, tile=autotune.lookup(case.nx, case.ny))
     orc = O.Oracle(case)
     sim.step(20)
@@ -104,7 +106,7 @@ def test_zero_rates_are_bgk(lbf_mod):
 def test_mrt_batch_equals_single(lbf_mod):
     cases = W.batch_instances(count=5, seed=4, lo=40, hi=150)
     for c in cases:
-        c.mat.mrt, c.mat.s_b, c.mat.s_q = 1, 1.4, 1.1
+        c.mat.mrt, c.mat.s_b, c.mat.s_q, c.mat.s_g = 1, 1.4, 1.1, 1.3
     singles = [lbf_mod.Sim(c) for c in cases]
     for s in singles:
         s.step(25)
