@@ -125,3 +125,18 @@ def test_adjoint_refuses_mrt(lbf_mod):
     sim = lbf_mod.Sim(case)
     with pytest.raises(lbf_mod.LbfError, match="BGK"):
         lbf_mod.Tape(sim, 10)
+
+
+def test_mrt_long_run(lbf_mod, O):
+    """3000 steps of the freezing sessile drop under MRT flow and phase
+    field: phi, T and the liquid fraction within 1e-4 of the oracle."""
+    case = mrt_cases(RATES["b0.9_q1.8_g1.4"])["sessile_64x48"]
+    sim, orc = lbf_mod.Sim(case), O.Oracle(case)
+    sim.step(3000)
+    orc.step(3000)
+    g, o = sim.fields(), orc.fields()
+    assert o["fs"].max() > 0.5
+    for k in ("phi", "T", "fl"):
+        err = float(np.abs(g[k].astype(np.float64) - o[k]).max())
+        print("MRT 3000", k, f"{err:.1e}", flush=True)
+        assert err <= 1e-4, (k, err)

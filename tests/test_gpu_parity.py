@@ -10,7 +10,8 @@ bar:
   three times the oracle's own divergence under FP32-sized perturbations
   (its initial phi perturbed by one FP32 rounding, and its state rounded to
   FP32 after every step) should that be larger.  Every field's error is
-  written to gpurun_out/parity_report.json.
+  written to parity_report.json in the directory LBF_REPORT_DIR names, when
+  it is set.
 Tiling never changes a node's arithmetic, so every tile shape gives
 bit-identical states.
 """
@@ -60,11 +61,13 @@ def compare(gpu, orc, names, tol, label=""):
     return worst
 
 
-REPORT = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
-                      "gpurun_out", "parity_report.json")
+REPORT_DIR = os.environ.get("LBF_REPORT_DIR")
+REPORT = os.path.join(REPORT_DIR, "parity_report.json") if REPORT_DIR else None
 
 
 def report(key, value):
+    if REPORT is None:
+        return
     os.makedirs(os.path.dirname(REPORT), exist_ok=True)
     data = json.load(open(REPORT)) if os.path.exists(REPORT) else {}
     data[key] = value
@@ -121,8 +124,9 @@ def test_sessile_workload_5000_steps(lbf_mod, oracle_mod):
         rep[k] = {"linf": err, "rel_l2": rel_l2, "oracle_self_divergence": self_div,
                   "nodes_over_1e-4": int((np.abs(g[k] - o[k]) > 1e-4).sum())}
     report("sessile_flat_128x96_5000_steps", rep)
-    np.savez_compressed(os.path.join(os.path.dirname(REPORT), "sessile_5000_fields.npz"),
-                        **{"gpu_" + k: g[k] for k in FIELDS}, **{"orc_" + k: o[k] for k in FIELDS})
+    if REPORT_DIR:
+        np.savez_compressed(os.path.join(REPORT_DIR, "sessile_5000_fields.npz"),
+                            **{"gpu_" + k: g[k] for k in FIELDS}, **{"orc_" + k: o[k] for k in FIELDS})
     for k in ("phi", "T", "fl"):
         bound = max(1e-4, 3.0 * rep[k]["oracle_self_divergence"])
         assert rep[k]["linf"] <= bound, (k, rep[k])

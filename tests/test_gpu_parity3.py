@@ -112,3 +112,15 @@ def test_degenerate_lattices(lbf_mod, O3, shape):
     orc.step(3)
     compare(sim.fields(), orc.fields(), 2e-5, case.name, ["phi", "T", "fs", "rhoH", "C", "chi"])
 
+
+
+def test_long_run_sessile(lbf_mod, O3):
+    """1000 steps of the freezing sessile drop (30 x 26 x 22): phi, T and the
+    liquid fraction within 1e-4 of the oracle, the bar of the 2D long run."""
+    case = cases()["sessile3_30x26x22"]
+    sim, orc = lbf_mod.Sim3(case), O3.Oracle3(case)
+    sim.step(1000)
+    orc.step(1000)
+    g, o = sim.fields(), orc.fields()
+    assert o["fs"].max() > 0.5
+    compare(g, o, 1e-4, "sessile3 1000 steps", ["phi", "T", "fl", "fs"])
