@@ -31,11 +31,12 @@ struct ChGeo {
 // Index of v along an axis of n nodes: wrapped (any offset), or clamped to
 // the first and last node (the mirror ghost).
 __device__ __forceinline__ int wrap_or_clamp(int v, int n, int periodic) {
+  if (v >= 0 && v < n) return v;   // interior: no division
   if (periodic) {
     v %= n;
     return v < 0 ? v + n : v;
   }
-  return v < 0 ? 0 : (v >= n ? n - 1 : v);
+  return v < 0 ? 0 : n - 1;
 }
 
 // 6 sum_i w_i (X(x + c_i) - X(x)) over an LDS box with row length SX and
