@@ -85,6 +85,12 @@ int lbf3_read_fields(lbf3_sim* sim, float* dst, int32_t dst_on_device);
  * step count.  Returns LBF_EUNSTABLE (after filling out) like lbf_reduce. */
 int lbf3_reduce(lbf3_sim* sim, double* out);
 
+/* Node order of the step kernel: strips of `rows` rows (default 16), each
+ * walked slab by slab in z, so a node's z neighbours were read shortly
+ * before (rows >= ny: the x-fastest order).  The same arithmetic per node:
+ * the fields do not depend on it.  LBF_EINVAL for rows < 1. */
+int lbf3_set_strip(lbf3_sim* sim, int32_t rows);
+
 /* HIP-event timing of the step kernels: average milliseconds per step of
  * the last lbf3_step call (0 if timing is off). */
 int lbf3_set_timing(lbf3_sim* sim, int32_t on);

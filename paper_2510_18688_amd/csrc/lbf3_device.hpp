@@ -51,6 +51,7 @@ struct Geo3 {
   int n[3];          // nx, ny, nz
   int per[3];        // periodic flags
   int tmask;         // bit f: face f is Dirichlet (0 x-low .. 5 z-high)
+  int strip;         // rows per strip of the step pass's node order (>= ny: x-fastest)
   int P;             // plane stride (floats)
   float Tw[6];       // face temperatures
 };

@@ -31,7 +31,7 @@ EXPORTS = ["lbf_workspace_bytes", "lbf_create", "lbf_set_geometry", "lbf_set_wal
            "lbf_tape_forward", "lbf_tape_backward", "lbf_tape_destroy", "lbf_profiles",
            "lbf3_workspace_bytes", "lbf3_create", "lbf3_set_geometry", "lbf3_init_fields",
            "lbf3_step", "lbf3_read_fields", "lbf3_reduce", "lbf3_set_timing",
-           "lbf3_last_step_ms", "lbf3_destroy"]
+           "lbf3_last_step_ms", "lbf3_destroy", "lbf3_set_strip"]
 COLS = ["ice", "pcm", "pcm_top", "ice_top"]
 ROWS = ["ice", "pcm", "pcm_left", "pcm_right", "ice_left", "ice_right"]
 
@@ -498,6 +498,7 @@ def _declare3(L):
     L.lbf3_read_fields.argtypes = [vp, vp, i32]
     L.lbf3_reduce.argtypes = [vp, C.POINTER(C.c_double)]
     L.lbf3_set_timing.argtypes = [vp, i32]
+    L.lbf3_set_strip.argtypes = [vp, i32]
     L.lbf3_last_step_ms.restype = C.c_double
     L.lbf3_last_step_ms.argtypes = [vp]
     L.lbf3_destroy.argtypes = [vp]
@@ -550,6 +551,10 @@ class Sim3:
 
     def step(self, n: int = 1) -> None:
         check(_lib.lbf3_step(self.h, int(n)))
+
+    def set_strip(self, rows: int) -> None:
+        """Rows per strip of the step kernel's node order (>= ny: x-fastest)."""
+        check(_lib.lbf3_set_strip(self.h, int(rows)))
 
     def set_timing(self, on: bool) -> None:
         check(_lib.lbf3_set_timing(self.h, int(bool(on))))
