@@ -58,6 +58,8 @@ typedef struct {
                                  (0: the BGK rate 1/tau_f) */
   double s_g;                 /* MRT rate of the phase-field moments above first order
                                  (0: the BGK rate 1/tau_g) */
+  double grav[2];             /* body force G = rho g (R32) */
+  double u_solid[2];          /* solid-phase velocity u_s of the drag */
 } orc_params;
 
 enum { WB = 0, WT = 1, WL = 2, WR = 3 };
@@ -471,7 +473,8 @@ static void pass2(orc_sim* s, int collide) {
       grad_lap(s, s->p_prev, x, y, &gpx, &gpy, NULL); /* lagged pressure (R14) */
       double mu = chem_pot(p, phi, lphi, s->phi0[k], s->cth[k], s->lap_phi0[k], fs, lfs);
       /* surface tension F_s = mu grad phi; no body force (R32) */
-      double Fx = mu * gphx, Fy = mu * gphy;
+      /* total force F = F_s + G with G = rho g (R32) */
+      double Fx = mu * gphx + rho * p->grav[0], Fy = mu * gphy + rho * p->grav[1];
       double mx = 0, my = 0, sum_nz = 0;
       for (int i = 0; i < 9; ++i) {
         double fi = s->f[i * n + k];
@@ -482,7 +485,7 @@ static void pass2(orc_sim* s, int collide) {
       /* rho u* = sum c f + F/2; drag f = f_s (u_s - u*) with u_s = 0; u = u* + f/2
        * (Sec. 3.1), with the total solid fraction in the drag (R2) */
       double usx = (mx + 0.5 * Fx) / rho, usy = (my + 0.5 * Fy) / rho;
-      double fdx = -fstot * usx, fdy = -fstot * usy;
+      double fdx = fstot * (p->u_solid[0] - usx), fdy = fstot * (p->u_solid[1] - usy);
       double ux = usx + 0.5 * fdx, uy = usy + 0.5 * fdy;
       double S = rho * mdot + ux * grx + uy * gry;
       double Ftx = Fx - gpx + CS2 * grx, Fty = Fy - gpy + CS2 * gry; /* R10 */

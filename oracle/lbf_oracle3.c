@@ -57,6 +57,8 @@ typedef struct {
   double latent, T_m, sigma, eps, mobility, cos_psi, rho_ref, T_substrate;
   double pcm_floor;
   double wall_T[6];           /* temperature of each Dirichlet face (R49) */
+  double grav[3];             /* body force G = rho g (R32) */
+  double u_solid[3];          /* solid-phase velocity u_s of the drag */
 } orc3_params;
 
 typedef struct {
@@ -328,7 +330,7 @@ static void pass2(orc3_sim* s, int collide) {
         grad_lap(s, s->p_prev, x, y, z, gp, NULL);
         double mu = chem_pot(p, phi, lphi, s->phi0[k], s->cth[k], s->lap_phi0[k], fs, lfs);
         double F[3], m[3] = {0, 0, 0}, sum_nz = 0;
-        for (int a = 0; a < 3; ++a) F[a] = mu * gph[a];
+        for (int a = 0; a < 3; ++a) F[a] = mu * gph[a] + rho * p->grav[a];
         for (int i = 0; i < Q; ++i) {
           double fi = s->f[i * n + k];
           m[0] += CX[i] * fi;
@@ -339,7 +341,7 @@ static void pass2(orc3_sim* s, int collide) {
         double us[3], fd[3], u[3], Ft[3], rf[3];
         for (int a = 0; a < 3; ++a) {
           us[a] = (m[a] + 0.5 * F[a]) / rho;
-          fd[a] = -fstot * us[a];
+          fd[a] = fstot * (p->u_solid[a] - us[a]);
           u[a] = us[a] + 0.5 * fd[a];
         }
         double S = rho * mdot + u[0] * gr[0] + u[1] * gr[1] + u[2] * gr[2];

@@ -34,7 +34,7 @@ class OrcParams(C.Structure):
             "cp_l", "cp_g", "cp_s", "latent", "T_m", "sigma", "eps", "mobility",
             "cos_psi", "rho_ref", "T_substrate", "pcm_floor")] + [
         ("mrt", C.c_int32), ("pad2_", C.c_int32), ("s_b", C.c_double), ("s_q", C.c_double),
-        ("s_g", C.c_double)]
+        ("s_g", C.c_double), ("grav", C.c_double * 2), ("u_solid", C.c_double * 2)]
 
 
 def build(force: bool = False) -> str:
@@ -111,6 +111,8 @@ def make_params(case) -> OrcParams:
     p.mrt = int(getattr(m, "mrt", 0))
     p.s_b, p.s_q = float(getattr(m, "s_b", 0.0)), float(getattr(m, "s_q", 0.0))
     p.s_g = float(getattr(m, "s_g", 0.0))
+    p.grav[0], p.grav[1] = float(m.g_x), float(m.g_y)
+    p.u_solid[0], p.u_solid[1] = float(m.us_x), float(m.us_y)
     return p
 
 

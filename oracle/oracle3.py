@@ -32,7 +32,8 @@ class Orc3Params(C.Structure):
         (k, C.c_double) for k in (
             "rho_l", "rho_g", "rho_s", "mu_l", "mu_g", "mu_s", "lam_l", "lam_g", "lam_s",
             "cp_l", "cp_g", "cp_s", "latent", "T_m", "sigma", "eps", "mobility",
-            "cos_psi", "rho_ref", "T_substrate", "pcm_floor")] + [("wall_T", C.c_double * 6)]
+            "cos_psi", "rho_ref", "T_substrate", "pcm_floor")] + [
+        ("wall_T", C.c_double * 6), ("grav", C.c_double * 3), ("u_solid", C.c_double * 3)]
 
 
 def build(force: bool = False) -> str:
@@ -99,6 +100,9 @@ def make_params(case) -> Orc3Params:
               "mobility", "cos_psi", "rho_ref", "pcm_floor"):
         setattr(p, k, float(getattr(m, k)))
     p.T_substrate = float(case.T_substrate)
+    for a, k in enumerate("xyz"):
+        p.grav[a] = float(getattr(m, "g_" + k))
+        p.u_solid[a] = float(getattr(m, "us_" + k))
     return p
 
 

@@ -70,6 +70,14 @@ class Material:
     s_b: float = 0.0
     s_q: float = 0.0
     s_g: float = 0.0
+    # body force G = rho g (gravitational acceleration g) and the velocity
+    # u_s of the solid phase in the drag (Sec. 3.1); z components for 3D
+    g_x: float = 0.0
+    g_y: float = 0.0
+    g_z: float = 0.0
+    us_x: float = 0.0
+    us_y: float = 0.0
+    us_z: float = 0.0
 
     def as_dict(self) -> Dict[str, float]:
         return dataclasses.asdict(self)
