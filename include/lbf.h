@@ -115,6 +115,12 @@ typedef struct lbf_params {
   int32_t mrt;
   int32_t reserved2;
   double s_b, s_q, s_g;
+  /* Body force G = rho * grav (a uniform acceleration acting on the local
+   * density) and the solid-phase velocity u_s of the drag f_s (u_s - u*)
+   * (Sec. 3.1); zero in the paper's droplet cases.  Finite.  The adjoint
+   * supports zero values only. */
+  double grav[2];
+  double u_solid[2];
 } lbf_params;
 
 typedef struct lbf_sim lbf_sim;

@@ -52,6 +52,8 @@ typedef struct lbf3_params {
   double T_substrate;
   double pcm_floor;
   double wall_T[6];            /* temperature of each Dirichlet face */
+  double grav[3];              /* body force G = rho * grav, as in lbf_params */
+  double u_solid[3];           /* solid-phase velocity of the drag */
 } lbf3_params;
 
 typedef struct lbf3_sim lbf3_sim;

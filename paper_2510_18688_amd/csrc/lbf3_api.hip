@@ -323,6 +323,9 @@ int validate3(const lbf3_params* p) {
   for (int f = 0; f < 6; ++f)
     if (p->thermal_bc[f] != LBF_ADIABATIC && p->thermal_bc[f] != LBF_DIRICHLET)
       return fail(LBF_EINVAL, "thermal_bc[%d] = %d", f, p->thermal_bc[f]);
+  for (int a = 0; a < 3; ++a)
+    if (!std::isfinite(p->grav[a]) || !std::isfinite(p->u_solid[a]))
+      return fail(LBF_EINVAL, "grav and u_solid must be finite");
   const double cpref = 2.0 * p->cp_s * p->cp_l / (p->cp_s + p->cp_l);
   const double kmin = std::min({p->rho_l, p->rho_g, p->rho_s}) *
                       std::min({p->cp_l, p->cp_g, p->cp_s});
@@ -355,6 +358,10 @@ void fill_phys3(const lbf3_params* p, Phys& ph) {
   ph.latch = p->latch_fs ? 1 : 0;
   ph.src_tau_a = p->h_src_tau_a ? 1 : 0;
   ph.subfix = p->substrate_fixed ? 1 : 0;
+  for (int a = 0; a < 3; ++a) {
+    ph.grav[a] = (float)p->grav[a];
+    ph.vsol[a] = (float)p->u_solid[a];
+  }
 }
 
 }  // namespace

@@ -280,7 +280,7 @@ __device__ __forceinline__ void collide3_prepare(const Phys& ph, const Mom& m, c
   c.mu = lbf::chem_pot(ph, phi, S.lphi, phi0, cth, lap_phi0, m.fs, S.lfs);
   float F[3], mm[3] = {0, 0, 0}, snz = 0;
 #pragma unroll
-  for (int a = 0; a < 3; ++a) F[a] = c.mu * S.gph[a];
+  for (int a = 0; a < 3; ++a) F[a] = c.mu * S.gph[a] + rho * ph.grav[a];   // F_s + G
 #pragma unroll
   for (int i = 0; i < NQ; ++i) {
     mm[0] += cx(i) * fv[i];
@@ -292,7 +292,7 @@ __device__ __forceinline__ void collide3_prepare(const Phys& ph, const Mom& m, c
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     const float us = (mm[a] + 0.5f * F[a]) * inv_rho;
-    fd[a] = -fstot * us;
+    fd[a] = fstot * (ph.vsol[a] - us);
     c.u[a] = us + 0.5f * fd[a];
     c.Ft[a] = F[a] - S.gp[a] + (1.0f / 3.0f) * S.gr[a];
     c.rf[a] = rho * fd[a] + F[a];

@@ -164,6 +164,9 @@ int lbf_tape_create(lbf_sim* sim, int32_t nsteps, int32_t segment, lbf_tape** ou
   *out = nullptr;
   if (!sim) return fail(LBF_EINVAL, "sim is NULL");
   if (sim->prm.mrt) return fail(LBF_EINVAL, "the adjoint supports the BGK flow collision only");
+  if (sim->prm.grav[0] != 0.0 || sim->prm.grav[1] != 0.0 || sim->prm.u_solid[0] != 0.0 ||
+      sim->prm.u_solid[1] != 0.0)
+    return fail(LBF_EINVAL, "the adjoint supports grav = u_solid = 0 only");
   if (nsteps < 0) return fail(LBF_EINVAL, "nsteps %d", nsteps);
   if (segment < 0) return fail(LBF_EINVAL, "segment %d", segment);
   lbf_tape* t = new lbf_tape();

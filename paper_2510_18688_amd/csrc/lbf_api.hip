@@ -101,6 +101,9 @@ int validate(const lbf_params* p) {
     if (p->thermal_bc[w] != LBF_ADIABATIC && p->thermal_bc[w] != LBF_DIRICHLET)
       return fail(LBF_EINVAL, "thermal_bc[%d] = %d", w, p->thermal_bc[w]);
   if (p->mrt != 0 && p->mrt != 1) return fail(LBF_EINVAL, "mrt = %d", p->mrt);
+  for (int a = 0; a < 2; ++a)
+    if (!std::isfinite(p->grav[a]) || !std::isfinite(p->u_solid[a]))
+      return fail(LBF_EINVAL, "grav and u_solid must be finite");
   if (p->mrt && !(p->s_b >= 0.0 && p->s_b < 2.0 && p->s_q >= 0.0 && p->s_q < 2.0 &&
                   p->s_g >= 0.0 && p->s_g < 2.0))
     return fail(LBF_EINVAL, "MRT rates s_b = %g, s_q = %g, s_g = %g must be in [0, 2)", p->s_b,
@@ -143,6 +146,11 @@ void fill_phys(const lbf_params* p, Phys& ph) {
   ph.s_b = p->mrt ? (float)p->s_b : 0.0f;
   ph.s_q = p->mrt ? (float)p->s_q : 0.0f;
   ph.s_g = p->mrt ? (float)p->s_g : 0.0f;
+  for (int a = 0; a < 2; ++a) {
+    ph.grav[a] = (float)p->grav[a];
+    ph.vsol[a] = (float)p->u_solid[a];
+  }
+  ph.grav[2] = ph.vsol[2] = 0.0f;
 }
 
 // ---------------------------------------------------------------- kernels

@@ -92,6 +92,8 @@ struct Phys {
   int mrt;           // 1: MRT flow and phase-field collisions
   float s_b, s_q;    // MRT bulk and energy-flux rates of f (0: 1/tau_f)
   float s_g;         // MRT rate of the moments of g above first order (0: 1/tau_g)
+  float grav[3];     // body force G = rho grav
+  float vsol[3];     // solid-phase velocity u_s of the drag
 };
 
 // Buffers of one lattice.  Device arrays are addressed through buffer
@@ -431,7 +433,8 @@ __device__ __forceinline__ void collide_node(const Phys& ph, const Mom& m, const
   const float inv_tau_s = 2.0f - inv_tau_a;           // 1/tau_s + 1/tau_a = 2
 
   const float mu = chem_pot(ph, phi, lphi, phi0, cth, lap_phi0, m.fs, lfs);
-  const float Fx = mu * gphx, Fy = mu * gphy;         // F_s = mu grad phi, G = 0
+  // total force F = F_s + G: F_s = mu grad phi, G = rho g
+  const float Fx = mu * gphx + rho * ph.grav[0], Fy = mu * gphy + rho * ph.grav[1];
   float mx = 0, my = 0, sum_nz = 0;
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
@@ -440,7 +443,7 @@ __device__ __forceinline__ void collide_node(const Phys& ph, const Mom& m, const
     if (i) sum_nz += fv[i];
   }
   const float usx = (mx + 0.5f * Fx) * inv_rho, usy = (my + 0.5f * Fy) * inv_rho;
-  const float fdx = -fstot * usx, fdy = -fstot * usy; // drag, u_s = 0
+  const float fdx = fstot * (ph.vsol[0] - usx), fdy = fstot * (ph.vsol[1] - usy);  // drag
   const float ux = usx + 0.5f * fdx, uy = usy + 0.5f * fdy;
   const float Sm = rho * mdot + ux * grx + uy * gry;
   const float Ftx = Fx - gpx + (1.0f / 3.0f) * grx, Fty = Fy - gpy + (1.0f / 3.0f) * gry;

@@ -55,7 +55,7 @@ class Params(C.Structure):
             "cp_l", "cp_g", "cp_s", "latent", "T_m", "sigma", "eps", "mobility", "cos_psi",
             "rho_ref", "T_substrate", "pcm_floor")] + [
         ("mrt", C.c_int32), ("reserved2", C.c_int32), ("s_b", C.c_double), ("s_q", C.c_double),
-        ("s_g", C.c_double)]
+        ("s_g", C.c_double), ("grav", C.c_double * 2), ("u_solid", C.c_double * 2)]
 
 
 _lib = None
@@ -142,6 +142,8 @@ def make_params(case) -> Params:
     p.mrt = int(getattr(m, "mrt", 0))
     p.s_b, p.s_q = float(getattr(m, "s_b", 0.0)), float(getattr(m, "s_q", 0.0))
     p.s_g = float(getattr(m, "s_g", 0.0))
+    p.grav[0], p.grav[1] = float(m.g_x), float(m.g_y)
+    p.u_solid[0], p.u_solid[1] = float(m.us_x), float(m.us_y)
     return p
 
 
@@ -482,7 +484,8 @@ class Params3(C.Structure):
         (k, C.c_double) for k in (
             "rho_l", "rho_g", "rho_s", "mu_l", "mu_g", "mu_s", "lam_l", "lam_g", "lam_s",
             "cp_l", "cp_g", "cp_s", "latent", "T_m", "sigma", "eps", "mobility", "cos_psi",
-            "rho_ref", "T_substrate", "pcm_floor")] + [("wall_T", C.c_double * 6)]
+            "rho_ref", "T_substrate", "pcm_floor")] + [
+        ("wall_T", C.c_double * 6), ("grav", C.c_double * 3), ("u_solid", C.c_double * 3)]
 
 
 def _declare3(L):
@@ -521,6 +524,9 @@ def make_params3(case) -> Params3:
               "rho_ref", "pcm_floor"):
         setattr(p, k, float(getattr(m, k)))
     p.T_substrate = float(case.T_substrate)
+    for a, k in enumerate("xyz"):
+        p.grav[a] = float(getattr(m, "g_" + k))
+        p.u_solid[a] = float(getattr(m, "us_" + k))
     return p
 
 

@@ -101,6 +101,7 @@ def _create_rc(L, case):
     (lambda c: (setattr(c.mat, "mrt", 1), setattr(c.mat, "s_q", -0.1)), "MRT rates"),
     (lambda c: setattr(c.mat, "mrt", 2), "mrt = 2"),
     (lambda c: (setattr(c.mat, "mrt", 1), setattr(c.mat, "s_g", 2.5)), "MRT rates"),
+    (lambda c: setattr(c.mat, "g_x", float("nan")), "finite"),
 ])
 def test_invalid_params_rejected_on_host(L, mutate, needle):
     case = W.sessile_drop(nx=16, ny=8)

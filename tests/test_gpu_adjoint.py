@@ -227,7 +227,7 @@ def test_gradient_workload_256_against_fp64_reference(lbf_mod):
         fds = [ref["fd"][key][k] for key in ref["fd"]]
         rows.append((ours, orc, fds))
         worst = max(worst, abs(ours - orc) / (1e-3 * abs(orc) + 1e-4 * np.linalg.norm(gr)))
-    print("gradient workload", dict(J=float(J), J_ref=ref["J0"], cosine=cos, rel_l2=rel,
+    print("gradient workload", dict(J=Jv, J_ref=ref["J0"], cosine=cos, rel_l2=rel,
                                     dir_ratio=worst), flush=True)
     for r in rows:
         print("  direction", r, flush=True)
