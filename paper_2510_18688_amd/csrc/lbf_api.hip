@@ -277,27 +277,37 @@ int grid_blocks(const lbf_sim* s, dim3& grid) {
   return (int)(grid.x * grid.y);
 }
 
+template <int WX, bool MRT>
+void launch_collide(const lbf_sim* s, int mode, bool red, BufArgs B, hipStream_t st, dim3 grid,
+                    int nbx, int nt) {
+  const dim3 block(WX);
+  if (mode == MODE_STEP && !red)
+    hipLaunchKernelGGL((step_kernel<WX, MODE_STEP, false, MRT>), grid, block, 0, st, s->G, s->ph,
+                       B, s->tile_y, nbx, nt);
+  else if (mode == MODE_STEP && red)
+    hipLaunchKernelGGL((step_kernel<WX, MODE_STEP, true, MRT>), grid, block, 0, st, s->G, s->ph,
+                       B, s->tile_y, nbx, nt);
+  else if (mode == MODE_FIELDS && !red)
+    hipLaunchKernelGGL((step_kernel<WX, MODE_FIELDS, false, MRT>), grid, block, 0, st, s->G,
+                       s->ph, B, s->tile_y, nbx, nt);
+  else
+    hipLaunchKernelGGL((step_kernel<WX, MODE_FIELDS, true, MRT>), grid, block, 0, st, s->G,
+                       s->ph, B, s->tile_y, nbx, nt);
+}
+
 template <int WX>
 int launch_wx(lbf_sim* s, int mode, bool red, BufArgs B, hipStream_t st) {
   dim3 g2;
   const int nt = grid_blocks(s, g2);
   const int nbx = (int)g2.x;
-  const dim3 grid(nt), block(WX);
-  if (mode == MODE_STEP && !red)
-    hipLaunchKernelGGL((step_kernel<WX, MODE_STEP, false>), grid, block, 0, st, s->G, s->ph, B,
-                       s->tile_y, nbx, nt);
-  else if (mode == MODE_STEP && red)
-    hipLaunchKernelGGL((step_kernel<WX, MODE_STEP, true>), grid, block, 0, st, s->G, s->ph, B,
-                       s->tile_y, nbx, nt);
-  else if (mode == MODE_STEP_MOM)
-    hipLaunchKernelGGL((step_kernel<WX, MODE_STEP_MOM, false>), grid, block, 0, st, s->G, s->ph,
-                       B, s->tile_y, nbx, nt);
-  else if (mode == MODE_FIELDS && !red)
-    hipLaunchKernelGGL((step_kernel<WX, MODE_FIELDS, false>), grid, block, 0, st, s->G, s->ph, B,
-                       s->tile_y, nbx, nt);
+  const dim3 grid(nt);
+  if (mode == MODE_STEP_MOM)   // the adjoint's recomputation (BGK only)
+    hipLaunchKernelGGL((step_kernel<WX, MODE_STEP_MOM, false>), grid, dim3(WX), 0, st, s->G,
+                       s->ph, B, s->tile_y, nbx, nt);
+  else if (s->ph.mrt)
+    launch_collide<WX, true>(s, mode, red, B, st, grid, nbx, nt);
   else
-    hipLaunchKernelGGL((step_kernel<WX, MODE_FIELDS, true>), grid, block, 0, st, s->G, s->ph, B,
-                       s->tile_y, nbx, nt);
+    launch_collide<WX, false>(s, mode, red, B, st, grid, nbx, nt);
   HIP_TRY(hipGetLastError());
   return LBF_OK;
 }
@@ -654,6 +664,7 @@ struct lbf_batch {
   std::vector<lbf_sim*> sims;
   hipStream_t stream;
   int tile_x, tile_y;
+  bool mrt;                      // some lattice uses MRT: launch the kernel with its branches
   int grid;                      // persistent workgroups
   InstDesc* d_desc;
   int2* d_items;
@@ -740,20 +751,24 @@ int batch_build(lbf_batch* b) {
   HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
   // as many workgroups as fit on the device at once (register- and
   // LDS-limited), never many more than there are items
+  b->mrt = false;
+  for (lbf_sim* sm : b->sims) b->mrt = b->mrt || sm->ph.mrt;
+  const void* kern = nullptr;
   switch (b->tile_x) {
     case 64:
-      HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          &per_cu, reinterpret_cast<const void*>(batch_step_kernel<64>), 64, 0));
+      kern = b->mrt ? reinterpret_cast<const void*>(batch_step_kernel<64, true>)
+                    : reinterpret_cast<const void*>(batch_step_kernel<64, false>);
       break;
     case 128:
-      HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          &per_cu, reinterpret_cast<const void*>(batch_step_kernel<128>), 128, 0));
+      kern = b->mrt ? reinterpret_cast<const void*>(batch_step_kernel<128, true>)
+                    : reinterpret_cast<const void*>(batch_step_kernel<128, false>);
       break;
     default:
-      HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          &per_cu, reinterpret_cast<const void*>(batch_step_kernel<256>), 256, 0));
+      kern = b->mrt ? reinterpret_cast<const void*>(batch_step_kernel<256, true>)
+                    : reinterpret_cast<const void*>(batch_step_kernel<256, false>);
       break;
   }
+  HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, b->tile_x, 0));
   per_cu = std::max(per_cu, 1);
   b->grid = std::max(8, std::min(per_cu * ncu, (b->nitems + 7) / 8 * 8));
   b->grid = (b->grid + 7) / 8 * 8;
@@ -763,8 +778,12 @@ int batch_build(lbf_batch* b) {
 
 template <int WX>
 void batch_launch_wx(lbf_batch* b, int parity, hipStream_t st) {
-  hipLaunchKernelGGL((batch_step_kernel<WX>), dim3(b->grid), dim3(WX), 0, st,
-                     (const InstDesc*)b->d_desc, (const int2*)b->d_items, b->nitems, parity);
+  if (b->mrt)   // some lattice of the batch uses MRT: the kernel with the MRT branches
+    hipLaunchKernelGGL((batch_step_kernel<WX, true>), dim3(b->grid), dim3(WX), 0, st,
+                       (const InstDesc*)b->d_desc, (const int2*)b->d_items, b->nitems, parity);
+  else
+    hipLaunchKernelGGL((batch_step_kernel<WX, false>), dim3(b->grid), dim3(WX), 0, st,
+                       (const InstDesc*)b->d_desc, (const int2*)b->d_items, b->nitems, parity);
 }
 
 int batch_launch(lbf_batch* b, int parity, hipStream_t st) {

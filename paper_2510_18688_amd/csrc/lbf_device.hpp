@@ -399,7 +399,9 @@ struct Post {
 // Collision of the three populations at one node (Sec. 3.1-3.3), in place
 // on fv, gv, hv (gv[0], hv[0] as deviations from the node's references).
 // When `collide` is false only the diagnostics are filled.
-template <bool COLLIDE>
+// MRT: compile the MRT branches (taken when ph.mrt is set); BGK-only
+// simulations run the instantiation without them.
+template <bool COLLIDE, bool MRT = false>
 __device__ __forceinline__ void collide_node(const Phys& ph, const Mom& m, const Stencil& S,
                                              float phi0, float cth, float lap_phi0, float Q_prev,
                                              float jx_prev, float jy_prev, float ref_h, float* fv,
@@ -453,7 +455,7 @@ __device__ __forceinline__ void collide_node(const Phys& ph, const Mom& m, const
   // the rest population's non-equilibrium part (tau - 1/2) F_0: tau = tau_f,
   // or 1/s_b under MRT (the density, e and epsilon moments it projects on
   // relax at s_b)
-  const bool mrt_b = ph.mrt && ph.s_b > 0.0f;
+  const bool mrt_b = MRT && ph.mrt && ph.s_b > 0.0f;
   const float tau_0 = mrt_b ? rcp(ph.s_b) : tau_f;
   const float p = (1.0f / 3.0f) / (1.0f - wgt(0)) *
                   (sum_nz + 0.5f * Sm + (tau_0 - 0.5f) * F0 - 1.5f * wgt(0) * rho * uu);
@@ -471,7 +473,7 @@ __device__ __forceinline__ void collide_node(const Phys& ph, const Mom& m, const
   const float inv_tau_f = rcp(tau_f);
   const float pf = 1.0f - 0.5f * inv_tau_f;
   const float rfx = rho * fdx + Fx, rfy = rho * fdy + Fy;
-  if (!ph.mrt) {
+  if (!MRT || !ph.mrt) {
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
       const float cu = cx(i) * ux + cy(i) * uy;
@@ -516,7 +518,7 @@ __device__ __forceinline__ void collide_node(const Phys& ph, const Mom& m, const
   const float pg = ph.pg;
   const float djx = jx - jx_prev, djy = jy - jy_prev;
   const float pm = phi * mdot;
-  if (!(ph.mrt && ph.s_g > 0.0f)) {
+  if (!(MRT && ph.mrt && ph.s_g > 0.0f)) {
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
       const float cj = cx(i) * jx + cy(i) * jy;

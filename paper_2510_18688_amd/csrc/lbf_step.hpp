@@ -87,7 +87,7 @@ __device__ __forceinline__ void flow_load(const Geo& G, const Bufs& B, int x, in
 // One strip (bx, by) of the lattice.  MODE_STEP writes the next state;
 // MODE_FIELDS writes the read-out fields of the current state.  With RED,
 // per-block FP64 partial sums go to `red_out` (NRED doubles).
-template <int WX, int MODE, bool RED, bool RECOMP>
+template <int WX, int MODE, bool RED, bool RECOMP, bool MRT = false>
 __device__ __forceinline__ void step_strip(const Geo& G, const Phys& ph, const Bufs& B, int bx,
                                            int by, int CY, int dir, double* red_out,
                                            StepShared<WX>& sh) {
@@ -223,8 +223,8 @@ __device__ __forceinline__ void step_strip(const Geo& G, const Phys& ph, const B
       }
       Post o;
       if (MODE != MODE_FIELDS) {
-        collide_node<true>(ph, cm, S, phi0, fin.cth, fin.lap0, cQp, fin.jxp, fin.jyp, crh, fv, cg,
-                           ch, o);
+        collide_node<true, MRT>(ph, cm, S, phi0, fin.cth, fin.lap0, cQp, fin.jxp, fin.jyp, crh, fv,
+                                cg, ch, o);
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
           stp(B.fout, i, P, k, fv[i]);
@@ -249,8 +249,8 @@ __device__ __forceinline__ void step_strip(const Geo& G, const Phys& ph, const B
           a_reset += o.reset;
         }
       } else {
-        collide_node<false>(ph, cm, S, phi0, fin.cth, fin.lap0, cQp, fin.jxp, fin.jyp, crh, fv,
-                            cg, ch, o);
+        collide_node<false, MRT>(ph, cm, S, phi0, fin.cth, fin.lap0, cQp, fin.jxp, fin.jyp, crh,
+                                 fv, cg, ch, o);
         stp(B.fields, 0, P, k, cm.phi);
         stp(B.fields, 1, P, k, cm.T);
         stp(B.fields, 2, P, k, 1.0f - cm.fs);
@@ -326,7 +326,7 @@ __device__ __forceinline__ int xcd_tile(int w, int ntiles) {
 // Single-lattice step kernel: 1D grid of nbx * nby workgroups.  Strips in
 // even tile rows march up, odd ones down, so two strips that share halo rows
 // reach them at the same time.
-template <int WX, int MODE, bool RED>
+template <int WX, int MODE, bool RED, bool MRT = false>
 __global__ __launch_bounds__(WX) __attribute__((amdgpu_waves_per_eu(LBF_WAVES, 8))) void
 step_kernel(Geo G, Phys ph, BufArgs A, int CY, int nbx, int ntiles) {
   __shared__ StepShared<WX> sh;
@@ -334,7 +334,8 @@ step_kernel(Geo G, Phys ph, BufArgs A, int CY, int nbx, int ntiles) {
   const int t = xcd_tile(blockIdx.x, ntiles);
   const int bx = t % nbx, by = t / nbx;
   double* red = RED ? A.red + (size_t)t * NRED : nullptr;
-  step_strip<WX, MODE, RED, LBF_RECOMP != 0>(G, ph, B, bx, by, CY, (by & 1) ? -1 : 1, red, sh);
+  step_strip<WX, MODE, RED, LBF_RECOMP != 0, MRT>(G, ph, B, bx, by, CY, (by & 1) ? -1 : 1, red,
+                                                 sh);
 }
 
 }  // namespace lbf
@@ -354,7 +355,7 @@ struct InstDesc {
 // tile) items of every lattice of the batch.  In round r workgroup b takes
 // item r * gridDim.x + xcd_tile(b, gridDim.x), so each XCD receives a
 // contiguous run of items (neighbouring tiles of one lattice) per round.
-template <int WX>
+template <int WX, bool MRT = false>
 __global__ __launch_bounds__(WX) __attribute__((amdgpu_waves_per_eu(LBF_WAVES, 8))) void
 batch_step_kernel(const InstDesc* __restrict__ D, const int2* __restrict__ items, int nitems,
                   int parity) {
@@ -372,8 +373,8 @@ batch_step_kernel(const InstDesc* __restrict__ D, const int2* __restrict__ items
     const Bufs B = make_bufs(args, geo.P);
     const int bx = item.y % nbx, by = item.y / nbx;
     __syncthreads();   // the LDS ring of the previous item is free
-    step_strip<WX, MODE_STEP, false, false>(geo, ph, B, bx, by, CY, (by & 1) ? -1 : 1, nullptr,
-                                            sh);
+    step_strip<WX, MODE_STEP, false, false, MRT>(geo, ph, B, bx, by, CY, (by & 1) ? -1 : 1,
+                                                 nullptr, sh);
   }
 }
 
