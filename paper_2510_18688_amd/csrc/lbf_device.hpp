@@ -163,12 +163,11 @@ __device__ __forceinline__ float ldp(Rsrc r, int plane, int P, int k) {
 __device__ __forceinline__ float lda(Rsrc r, uint32_t elem) {
   return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, elem * 4u, 0, 0));
 }
-#ifndef LBF_STORE_POLICY
-#define LBF_STORE_POLICY 2   // non-temporal: the new state is not re-read in this pass
-#endif
+// store policy 2, non-temporal: the new state is not re-read in this pass
+constexpr int kStorePolicy = 2;
 __device__ __forceinline__ void stp(Rsrc r, int plane, int P, int k, float v) {
   __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (uint32_t)k * 4u,
-                                        (uint32_t)plane * (uint32_t)P * 4u, LBF_STORE_POLICY);
+                                        (uint32_t)plane * (uint32_t)P * 4u, kStorePolicy);
 }
 
 // Reciprocal with the hardware approximation (1 ulp), used for every per-node

@@ -16,16 +16,6 @@ namespace lbf {
 
 constexpr int CY_MAX = 256;
 
-// Rows of populations requested ahead of their use (1 or 2), and whether
-// the flow populations of the next row are requested before the collision
-// of the current one (1) or after it (0).
-#ifndef LBF_DEPTH
-#define LBF_DEPTH 1
-#endif
-#ifndef LBF_FLOW_AHEAD
-#define LBF_FLOW_AHEAD 1
-#endif
-
 template <int WX>
 struct StepShared {
   float v[4][4][WX + 2];        // [phi, fs, rho, p_prev][ring slot][column]
@@ -87,7 +77,7 @@ __device__ __forceinline__ void flow_load(const Geo& G, const Bufs& B, int x, in
 // One strip (bx, by) of the lattice.  MODE_STEP writes the next state;
 // MODE_FIELDS writes the read-out fields of the current state.  With RED,
 // per-block FP64 partial sums go to `red_out` (NRED doubles).
-template <int WX, int MODE, bool RED, bool RECOMP, bool MRT = false>
+template <int WX, int MODE, bool RED, bool MRT = false>
 __device__ __forceinline__ void step_strip(const Geo& G, const Phys& ph, const Bufs& B, int bx,
                                            int by, int CY, int dir, double* red_out,
                                            StepShared<WX>& sh) {
@@ -99,7 +89,6 @@ __device__ __forceinline__ void step_strip(const Geo& G, const Phys& ph, const B
   const int y0 = by * CY;
   const int y1 = min(y0 + CY, G.ny);
   const int P = G.P;
-  (void)RECOMP;
 
   double a_sg = 0, a_sh = 0, a_fs = 0, a_liq = 0, a_umax = 0, a_bad = 0;
   double a_sphi = 0, a_heat = 0, a_flux = 0, a_reset = 0;
@@ -127,9 +116,8 @@ __device__ __forceinline__ void step_strip(const Geo& G, const Phys& ph, const B
   const int ys = dir > 0 ? y0 : y1 - 1;
   const int nrow = y1 - y0;
   NodeIn cin, ain;   // current row; row ahead (in flight)
-  NodeIn a2in;       // (LBF_DEPTH 2) two rows ahead, in flight
   FlowIn fin;        // flow data of the current row (in flight)
-  FlowIn fnx;        // (LBF_FLOW_AHEAD) flow data of the next row, in flight
+  FlowIn fnx;        // flow data of the next row, in flight
   Mom cm;
   if (act) {
     NodeIn bin;
@@ -138,7 +126,6 @@ __device__ __forceinline__ void step_strip(const Geo& G, const Phys& ph, const B
     node_load(G, ph, B, x, map_axis(ys - dir, G.ny, G.py), bin);
     node_load(G, ph, B, x, ys, cin);
     node_load(G, ph, B, x, map_axis(ys + dir, G.ny, G.py), ain);
-    if (LBF_DEPTH > 1 && nrow >= 2) node_load(G, ph, B, x, map_axis(ys + 2 * dir, G.ny, G.py), a2in);
     flow_load(G, B, x, ys, fin);
     node_finish(ph, bin, m, st);
 #pragma unroll
@@ -180,13 +167,10 @@ __device__ __forceinline__ void step_strip(const Geo& G, const Phys& ph, const B
 #pragma unroll
       for (int f = 0; f < 4; ++f) sh.v[f][slot_n][l + 1] = st[f];
       next_c = ain;
-      if (LBF_DEPTH > 1) {
-        if (it + 2 <= nrow) ain = a2in;
-        if (it + 3 <= nrow) node_load(G, ph, B, x, map_axis(ya + 2 * dir, G.ny, G.py), a2in);
-      } else if (more) {
+      if (more) {
         node_load(G, ph, B, x, map_axis(ya + dir, G.ny, G.py), ain);
+        flow_load(G, B, x, ya, fnx);   // before this row's collision
       }
-      if (LBF_FLOW_AHEAD && more) flow_load(G, B, x, ya, fnx);
     }
     if (l == 0 || l == lastl) {
       const int r = ya - (y0 - 1);
@@ -271,10 +255,7 @@ __device__ __forceinline__ void step_strip(const Geo& G, const Phys& ph, const B
         if (!isfinite(cm.phi) || !isfinite(cm.T) || !isfinite(um) || !isfinite(o.p)) a_bad += 1;
       }
       // request the next row's flow data; rotate the row registers
-      if (more) {
-        if (LBF_FLOW_AHEAD) fin = fnx;
-        else flow_load(G, B, x, ya, fin);
-      }
+      if (more) fin = fnx;
       cin = next_c;
       cm = am;
     }
@@ -305,13 +286,8 @@ __device__ __forceinline__ void step_strip(const Geo& G, const Phys& ph, const B
   }
 }
 
-#ifndef LBF_RECOMP
-#define LBF_RECOMP 0
-#endif
 // Minimum waves per SIMD the register allocator is asked to keep.
-#ifndef LBF_WAVES
-#define LBF_WAVES 2
-#endif
+constexpr int kWaves = 2;
 
 // Tile of a workgroup: workgroups are dealt to the 8 XCDs round-robin, so
 // workgroup w runs on XCD w % 8; tiles are handed out so that each XCD
@@ -327,15 +303,14 @@ __device__ __forceinline__ int xcd_tile(int w, int ntiles) {
 // even tile rows march up, odd ones down, so two strips that share halo rows
 // reach them at the same time.
 template <int WX, int MODE, bool RED, bool MRT = false>
-__global__ __launch_bounds__(WX) __attribute__((amdgpu_waves_per_eu(LBF_WAVES, 8))) void
+__global__ __launch_bounds__(WX) __attribute__((amdgpu_waves_per_eu(kWaves, 8))) void
 step_kernel(Geo G, Phys ph, BufArgs A, int CY, int nbx, int ntiles) {
   __shared__ StepShared<WX> sh;
   const Bufs B = make_bufs(A, G.P);
   const int t = xcd_tile(blockIdx.x, ntiles);
   const int bx = t % nbx, by = t / nbx;
   double* red = RED ? A.red + (size_t)t * NRED : nullptr;
-  step_strip<WX, MODE, RED, LBF_RECOMP != 0, MRT>(G, ph, B, bx, by, CY, (by & 1) ? -1 : 1, red,
-                                                 sh);
+  step_strip<WX, MODE, RED, MRT>(G, ph, B, bx, by, CY, (by & 1) ? -1 : 1, red, sh);
 }
 
 }  // namespace lbf
@@ -356,7 +331,7 @@ struct InstDesc {
 // item r * gridDim.x + xcd_tile(b, gridDim.x), so each XCD receives a
 // contiguous run of items (neighbouring tiles of one lattice) per round.
 template <int WX, bool MRT = false>
-__global__ __launch_bounds__(WX) __attribute__((amdgpu_waves_per_eu(LBF_WAVES, 8))) void
+__global__ __launch_bounds__(WX) __attribute__((amdgpu_waves_per_eu(kWaves, 8))) void
 batch_step_kernel(const InstDesc* __restrict__ D, const int2* __restrict__ items, int nitems,
                   int parity) {
   __shared__ StepShared<WX> sh;
@@ -373,8 +348,8 @@ batch_step_kernel(const InstDesc* __restrict__ D, const int2* __restrict__ items
     const Bufs B = make_bufs(args, geo.P);
     const int bx = item.y % nbx, by = item.y / nbx;
     __syncthreads();   // the LDS ring of the previous item is free
-    step_strip<WX, MODE_STEP, false, false, MRT>(geo, ph, B, bx, by, CY, (by & 1) ? -1 : 1,
-                                                 nullptr, sh);
+    step_strip<WX, MODE_STEP, false, MRT>(geo, ph, B, bx, by, CY, (by & 1) ? -1 : 1, nullptr,
+                                          sh);
   }
 }
 

@@ -91,17 +91,18 @@ def ch_smooth(solid, periodic: Sequence[bool], iterations: int, eps: float = 4.0
 
 def prepare(solid: np.ndarray, S_w: float, theta_deg: float, ch_iterations: int = 500,
             separation_steps: int = 2000, eps: Optional[float] = None, T0: float = 0.5,
-            tile=None):
+            tile=None, gravity=(0.0, 0.0)):
     """Both pre-processing stages of Sec. 4.6 on a 2D image (ny, nx), walls
     on all sides: smooth it into phi0, fill the pores with the uniform
     mixture of saturation S_w, and let it separate for `separation_steps`
-    steps at T0 (above melting).  Returns (sim, case); set the freezing
-    stage's wall temperatures with `sim.set_wall_temperature` and step on."""
+    steps at T0 (above melting) under the body force rho * gravity.  Returns
+    (sim, case); set the freezing stage's wall temperatures with
+    `sim.set_wall_temperature` and step on."""
     from . import workloads as W
     mat = W.Material()
     phi0 = ch_smooth(solid, (False, False, True), ch_iterations, eps=eps or mat.eps)
     case = W.unsaturated_medium(phi0.astype(np.float64), S_w=S_w, theta_deg=theta_deg, T0=T0,
-                                mat=mat)
+                                mat=mat, gravity=gravity)
     sim = lbf.Sim(case, tile=tile)
     sim.step(separation_steps)
     return sim, case

@@ -386,14 +386,16 @@ def sandpack_image(shape, porosity: float = 0.3585, seed: int = 12, r_median: fl
 
 def unsaturated_medium(phi0: np.ndarray, S_w: float = 0.32, theta_deg: float = 60.0,
                        T0: float = 0.5, steps: int = 0, mat: Optional[Material] = None,
-                       name: str = "unsaturated") -> Case:
+                       name: str = "unsaturated", gravity=(0.0, 0.0)) -> Case:
     """The unsaturated porous set-up of Sec. 4.6 on a 2D solid indicator phi0
     (ny, nx): the pores hold phi = (1 - phi0) phi_i with phi_i = 2 S_w - 1
     (a uniform mixture whose liquid share of the pore volume is S_w), at a
     uniform T0 above melting; walls on all sides, the x walls Dirichlet at
     T0 for the phase-separation stage (`wall_T_freezing` gives the cold and
-    warm x walls of the freezing stage), the y walls adiabatic."""
-    mat = mat or Material()
+    warm x walls of the freezing stage), the y walls adiabatic.  `gravity`:
+    the acceleration (x, y) of the body force rho g, which with cohesion and
+    adhesion sets where the liquid settles."""
+    mat = dataclasses.replace(mat or Material(), g_x=float(gravity[0]), g_y=float(gravity[1]))
     ny, nx = phi0.shape
     phi_i = 2.0 * S_w - 1.0
     phi = (1.0 - phi0) * phi_i

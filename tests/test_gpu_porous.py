@@ -87,6 +87,22 @@ def test_ch_full_size_two_steps(P, CH, shape, per):
     assert err <= 1e-6
 
 
+def test_preparation_with_gravity_matches_oracle(P, CH):
+    """The separation stage under gravity (the body force of the paper's
+    porous stage) against the oracle, 800 steps."""
+    from oracle import oracle as O
+    img = W.sandpack_image((48, 64), seed=22, r_median=5.0)
+    sim, case = P.prepare(img, S_w=0.4, theta_deg=45.0, ch_iterations=300,
+                          separation_steps=800, gravity=(0.0, -2e-5))
+    assert case.mat.g_y == -2e-5
+    phi0 = CH.smooth(img, (False, False, True), 300)
+    orc = O.Oracle(W.unsaturated_medium(phi0, S_w=0.4, theta_deg=45.0, gravity=(0.0, -2e-5)))
+    orc.step(800)
+    g, o = sim.fields(), orc.fields()
+    for k in ("phi", "T", "C"):
+        assert float(np.abs(g[k] - o[k]).max()) <= 2e-5, k
+
+
 def test_preparation_matches_oracle(P, CH):
     """Smoothing, then 1500 steps of phase separation of the uniform pore
     mixture (S_w = 0.32, theta = 60 degrees) against the oracle run on the
