@@ -81,7 +81,7 @@ __global__ __launch_bounds__(256) void k_ch_step(ChGeo G, const float* __restric
     const int gx = wrap_or_clamp(x0 + lx - 2, nx, G.per[0]);
     const int gy = wrap_or_clamp(y0 + ly - 2, ny, G.per[1]);
     const int gz = DIM == 3 ? wrap_or_clamp(z0 + lz - 2, nz, G.per[2]) : 0;
-    cs[i] = c[((size_t)gz * ny + gy) * nx + gx];
+    cs[i] = c[(gz * ny + gy) * nx + gx];   // < 2^31 nodes
   }
   __syncthreads();
   for (int i = threadIdx.x; i < MX * MY * MZ; i += 256) {
@@ -92,24 +92,30 @@ __global__ __launch_bounds__(256) void k_ch_step(ChGeo G, const float* __restric
   }
   __syncthreads();
   // beyond a mirror wall the potential is that of the first node (its
-  // ghost); the source is always an in-domain node of the same box
-  for (int i = threadIdx.x; i < MX * MY * MZ; i += 256) {
-    const int mx = i % MX, my = (i / MX) % MY, mz = i / (MX * MY);
-    const int gx = x0 + mx - 1, gy = y0 + my - 1, gz = z0 + mz - HZ;
-    const int sx = G.per[0] ? gx : min(max(gx, 0), nx - 1);
-    const int sy = G.per[1] ? gy : min(max(gy, 0), ny - 1);
-    const int sz = (DIM == 3 && !G.per[2]) ? min(max(gz, 0), nz - 1) : gz;
-    if (sx != gx || sy != gy || sz != gz)
-      ms[i] = ms[((sz - z0 + HZ) * MY + sy - y0 + 1) * MX + sx - x0 + 1];
+  // ghost); the source is always an in-domain node of the same box.  Only
+  // tiles whose ring reaches past a wall have such cells.
+  const bool at_wall = (!G.per[0] && (x0 == 0 || x0 + TX >= nx)) ||
+                       (!G.per[1] && (y0 == 0 || y0 + TY >= ny)) ||
+                       (DIM == 3 && !G.per[2] && (z0 == 0 || z0 + TZ >= nz));
+  if (at_wall) {
+    for (int i = threadIdx.x; i < MX * MY * MZ; i += 256) {
+      const int mx = i % MX, my = (i / MX) % MY, mz = i / (MX * MY);
+      const int gx = x0 + mx - 1, gy = y0 + my - 1, gz = z0 + mz - HZ;
+      const int sx = G.per[0] ? gx : min(max(gx, 0), nx - 1);
+      const int sy = G.per[1] ? gy : min(max(gy, 0), ny - 1);
+      const int sz = (DIM == 3 && !G.per[2]) ? min(max(gz, 0), nz - 1) : gz;
+      if (sx != gx || sy != gy || sz != gz)
+        ms[i] = ms[((sz - z0 + HZ) * MY + sy - y0 + 1) * MX + sx - x0 + 1];
+    }
+    __syncthreads();
   }
-  __syncthreads();
   for (int o = threadIdx.x; o < TX * TY * TZ; o += 256) {
     const int ox = o % TX, oy = (o / TX) % TY, oz = o / (TX * TY);
     const int gx = x0 + ox, gy = y0 + oy, gz = z0 + oz;
     if (gx >= nx || gy >= ny || gz >= nz) continue;
     const int j = ((oz + 2 * HZ) * LY + oy + 2) * LX + ox + 2;
     const int m = ((oz + HZ) * MY + oy + 1) * MX + ox + 1;
-    cn[((size_t)gz * ny + gy) * nx + gx] = cs[j] + dtM * lds_laplacian<DIM, MX, MX * MY>(ms, m);
+    cn[(gz * ny + gy) * nx + gx] = cs[j] + dtM * lds_laplacian<DIM, MX, MX * MY>(ms, m);
   }
 }
 
