@@ -87,6 +87,15 @@ int lbf3_read_fields(lbf3_sim* sim, float* dst, int32_t dst_on_device);
  * step count.  Returns LBF_EUNSTABLE (after filling out) like lbf_reduce. */
 int lbf3_reduce(lbf3_sim* sim, double* out);
 
+/* Bytes of the checkpointable dynamic state (distributions, lagged fields,
+ * step count) and its copy to / from `buf` (device memory, at least
+ * lbf3_state_bytes).  Loading needs the geometry set and a state of the same
+ * lattice size (LBF_EINVAL otherwise); a loaded state continues
+ * bit-identically.  Synchronises the simulation's stream. */
+size_t lbf3_state_bytes(const lbf3_sim* sim);
+int lbf3_save_state(lbf3_sim* sim, void* dst_device, size_t cap);
+int lbf3_load_state(lbf3_sim* sim, const void* src_device, size_t bytes);
+
 /* Node order of the step kernel: strips of `rows` rows (default 16), each
  * walked slab by slab in z, so a node's z neighbours were read shortly
  * before (rows >= ny: the x-fastest order).  The same arithmetic per node:

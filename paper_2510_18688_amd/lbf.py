@@ -31,7 +31,8 @@ EXPORTS = ["lbf_workspace_bytes", "lbf_create", "lbf_set_geometry", "lbf_set_wal
            "lbf_tape_forward", "lbf_tape_backward", "lbf_tape_destroy", "lbf_profiles",
            "lbf3_workspace_bytes", "lbf3_create", "lbf3_set_geometry", "lbf3_init_fields",
            "lbf3_step", "lbf3_read_fields", "lbf3_reduce", "lbf3_set_timing",
-           "lbf3_last_step_ms", "lbf3_destroy", "lbf3_set_strip"]
+           "lbf3_last_step_ms", "lbf3_destroy", "lbf3_set_strip", "lbf3_state_bytes",
+           "lbf3_save_state", "lbf3_load_state"]
 COLS = ["ice", "pcm", "pcm_top", "ice_top"]
 ROWS = ["ice", "pcm", "pcm_left", "pcm_right", "ice_left", "ice_right"]
 
@@ -502,6 +503,10 @@ def _declare3(L):
     L.lbf3_reduce.argtypes = [vp, C.POINTER(C.c_double)]
     L.lbf3_set_timing.argtypes = [vp, i32]
     L.lbf3_set_strip.argtypes = [vp, i32]
+    L.lbf3_state_bytes.restype = C.c_size_t
+    L.lbf3_state_bytes.argtypes = [vp]
+    L.lbf3_save_state.argtypes = [vp, vp, C.c_size_t]
+    L.lbf3_load_state.argtypes = [vp, vp, C.c_size_t]
     L.lbf3_last_step_ms.restype = C.c_double
     L.lbf3_last_step_ms.argtypes = [vp]
     L.lbf3_destroy.argtypes = [vp]
@@ -557,6 +562,15 @@ class Sim3:
 
     def step(self, n: int = 1) -> None:
         check(_lib.lbf3_step(self.h, int(n)))
+
+    def state_bytes(self) -> int:
+        return int(_lib.lbf3_state_bytes(self.h))
+
+    def save_state(self, buf) -> None:
+        check(_lib.lbf3_save_state(self.h, C.c_void_p(buf.data_ptr()), buf.numel() * buf.element_size()))
+
+    def load_state(self, buf) -> None:
+        check(_lib.lbf3_load_state(self.h, C.c_void_p(buf.data_ptr()), buf.numel() * buf.element_size()))
 
     def set_strip(self, rows: int) -> None:
         """Rows per strip of the step kernel's node order (>= ny: x-fastest)."""

@@ -126,6 +126,9 @@ def test_null_arguments(L):
     assert L.lbf3_read_fields(None, None, 0) == -1
     assert L.lbf3_set_geometry(None, None, None, 0) == -1
     assert L.lbf3_create(None, None, None, 0, C.byref(out)) == -1
+    assert L.lbf3_state_bytes(None) == 0
+    assert L.lbf3_save_state(None, None, 0) == -1
+    assert L.lbf3_load_state(None, None, 0) == -1
     L.lbf3_destroy(None)
 
 

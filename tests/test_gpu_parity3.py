@@ -140,3 +140,30 @@ def test_strip_order_does_not_change_the_fields(lbf_mod):
     for f in out[1:]:
         for k in ("phi", "T", "fs", "ux", "uz", "p", "rhoH"):
             assert np.array_equal(out[0][k], f[k]), k
+
+
+def test_save_and_load_continue_bit_identically(lbf_mod):
+    """A checkpoint taken after 15 steps and loaded into a fresh simulation
+    of the same case continues bit for bit; a state of another lattice is
+    refused."""
+    import torch
+    a = lbf_mod.Sim3(cases()["boxed_21x19x17"])
+    a.step(15)
+    buf = torch.empty(a.state_bytes(), dtype=torch.uint8, device="cuda")
+    a.save_state(buf)
+    a.step(10)
+    b = lbf_mod.Sim3(cases()["boxed_21x19x17"])
+    b.step(3)
+    b.load_state(buf)
+    assert b.reduce()["step"] == 15
+    b.step(10)
+    Fa, Fb = a.fields(), b.fields()
+    for k in FIELDS3:
+        assert np.array_equal(Fa[k], Fb[k]), k
+    other = lbf_mod.Sim3(cases()["sphere_24"])
+    with pytest.raises(lbf_mod.LbfError, match="needed"):
+        other.load_state(buf)
+    big = torch.empty(other.state_bytes(), dtype=torch.uint8, device="cuda")
+    other.save_state(big)
+    with pytest.raises(lbf_mod.LbfError):
+        b.load_state(big)
