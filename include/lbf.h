@@ -89,7 +89,10 @@ typedef struct lbf_params {
   int32_t latch_fs;            /* 1: PCM fraction latched by the previous ice fraction */
   int32_t h_src_tau_a;         /* 1: enthalpy source prefactor with tau_a, 0: tau_s */
   int32_t substrate_fixed;     /* 1: nodes with phi0 >= 1/2 held at T_substrate */
-  int32_t reserved;
+  int32_t plane_pad;           /* extra floats between consecutive planes of the
+                                  workspace, a multiple of 64 in [0, 65536]: moves
+                                  which HBM channels the planes of one step share
+                                  (a tuning knob; results do not depend on it) */
   double rho_l, rho_g, rho_s;  /* densities */
   double mu_l, mu_g, mu_s;     /* dynamic viscosities */
   double lam_l, lam_g, lam_s;  /* thermal conductivities */
@@ -126,17 +129,19 @@ typedef struct lbf_params {
 typedef struct lbf_sim lbf_sim;
 
 /* Bytes of device workspace one simulation needs (distributions, lagged
- * fields, static fields, reduction scratch), or 0 for invalid sizes. */
-size_t lbf_workspace_bytes(int32_t nx, int32_t ny);
+ * fields, static fields, reduction scratch) for lattice nx x ny and
+ * lbf_params.plane_pad, or 0 for invalid sizes or pads. */
+size_t lbf_workspace_bytes(int32_t nx, int32_t ny, int32_t plane_pad);
 
 /* Create a simulation on HIP stream `stream` (a hipStream_t, NULL for the
  * default stream).  `workspace` is caller-owned device memory of at least
- * lbf_workspace_bytes(nx, ny) bytes, 256-byte aligned, that must outlive the
+ * lbf_workspace_bytes(nx, ny, plane_pad) bytes, 256-byte aligned, that must outlive the
  * simulation; with workspace == NULL the library allocates it with hipMalloc
  * and frees it in lbf_destroy.  Rejects with LBF_EINVAL: non-positive sizes,
  * non-positive densities, specific heats, viscosities or conductivities,
- * eps <= 0, mobility <= 0, and rho_ref C_p,ref larger than the smallest
- * possible nodal heat capacity (the enthalpy scheme is then unstable). */
+ * eps <= 0, mobility <= 0, a plane_pad outside its range, and rho_ref C_p,ref
+ * larger than the smallest possible nodal heat capacity (the enthalpy scheme
+ * is then unstable). */
 int lbf_create(const lbf_params* params, void* stream, void* workspace, size_t workspace_bytes,
                lbf_sim** out);
 
@@ -289,9 +294,11 @@ typedef struct lbf_tape lbf_tape;
 /* Device bytes a tape allocates: ceil(nsteps / segment) stored states of
  * 34 planes, two buffers of `segment` recomputed states and their moments
  * (one segment is recomputed on a second stream while the other is
- * reversed), and the adjoint work planes.  segment <= 0 selects
+ * reversed), and the adjoint work planes, all with the simulation's plane
+ * stride (its plane_pad).  segment <= 0 selects
  * ceil(sqrt(nsteps)). */
-size_t lbf_tape_bytes(int32_t nx, int32_t ny, int32_t nsteps, int32_t segment);
+size_t lbf_tape_bytes(int32_t nx, int32_t ny, int32_t plane_pad, int32_t nsteps,
+                      int32_t segment);
 
 /* Create a tape for `sim` (which must outlive it) recording nsteps >= 0
  * steps with a checkpoint every `segment` steps (<= 0: ceil(sqrt(nsteps))).

@@ -1,8 +1,12 @@
-"""Tile-shape autotuner of the step kernel.
+"""Launch-shape and plane-stride autotuner of the step kernel.
 
 For a lattice size it times every candidate launch shape (threads per block
 along x, rows per block along y) with HIP events on the simulation's stream
 and persists the fastest in tiles.json next to this file, keyed by "NXxNY".
+`tune_pad` does the same for the padding between the workspace's planes
+(lbf_params.plane_pad), which decides how the 34 planes that one step
+streams spread over the HBM channels; its effect depends on the exact size,
+so `lookup_pad` answers for measured sizes only.
 """
 
 from __future__ import annotations
@@ -61,6 +65,48 @@ def tune(sim, steps: int = 20, candidates: Iterable[Sequence[int]] = CANDIDATES,
         with open(DB, "w") as f:
             json.dump(db, f, indent=1, sort_keys=True)
     return tile, times
+
+
+PAD_CANDIDATES: Tuple[int, ...] = (0, 64, 128, 192, 320, 576, 1088, 2112, 4160, 4224, 6208,
+                                   8256, 12352, 16448)
+
+
+def lookup_pad(nx: int, ny: int) -> int:
+    """Tuned plane padding of a lattice size, 0 if that size was not measured."""
+    v = _load().get(f"{nx}x{ny}")
+    return int(v.get("pad", 0)) if v else 0
+
+
+def tune_pad(case, tile: Sequence[int], steps: int = 100, repeats: int = 3,
+             candidates: Iterable[int] = PAD_CANDIDATES, save: bool = True
+             ) -> Tuple[int, dict]:
+    """Time the step of `case` with each plane padding (a fresh simulation
+    each, median of `repeats` runs of `steps` steps) and keep the best."""
+    import statistics
+    from . import lbf
+    times = {}
+    for pad in candidates:
+        sim = lbf.Sim(case, tile=tile, plane_pad=pad)
+        sim.step(10)
+        sim.set_timing(True)
+        runs = []
+        for _ in range(repeats):
+            sim.step(steps)
+            runs.append(sim.last_step_kernel_ms())
+        times[str(pad)] = statistics.median(runs)
+        sim.close()
+        del sim
+    best = int(min(times, key=times.get))
+    if save:
+        db = _load()
+        key = f"{case.nx}x{case.ny}"
+        entry = db.get(key, {"tile": list(tile)})
+        entry["pad"], entry["pad_ms"] = best, times[str(best)]
+        entry["pad_all"] = times
+        db[key] = entry
+        with open(DB, "w") as f:
+            json.dump(db, f, indent=1, sort_keys=True)
+    return best, times
 
 
 BATCH_CANDIDATES: Tuple[Tuple[int, int], ...] = tuple(

@@ -55,8 +55,9 @@ namespace {
 
 constexpr int kTapeParts = 14;
 
-size_t tape_layout(int nx, int ny, int nsteps, int seg, size_t offs[kTapeParts]) {
-  const size_t P = (size_t)plane_stride(nx, ny) * sizeof(float);
+size_t tape_layout(int nx, int ny, long long plane, int nsteps, int seg,
+                   size_t offs[kTapeParts]) {
+  const size_t P = (size_t)plane * sizeof(float);
   const int nck = (nsteps + seg - 1) / seg;
   const size_t wstride = round_up((size_t)std::max(nx, ny), 64);
   size_t off = 0;
@@ -152,11 +153,14 @@ int recompute_segment(lbf_tape* t, int sgi, bool buffer_used) {
 
 extern "C" {
 
-size_t lbf_tape_bytes(int32_t nx, int32_t ny, int32_t nsteps, int32_t segment) {
-  if (nx < 1 || ny < 1 || nsteps < 0) return 0;
+size_t lbf_tape_bytes(int32_t nx, int32_t ny, int32_t plane_pad, int32_t nsteps,
+                      int32_t segment) {
+  if (nx < 1 || ny < 1 || nsteps < 0 || plane_pad < 0 || plane_pad > kMaxPlanePad ||
+      plane_pad % 64)
+    return 0;
   const int seg = segment > 0 ? segment : default_segment(nsteps);
   size_t offs[kTapeParts];
-  return tape_layout(nx, ny, nsteps, seg, offs);
+  return tape_layout(nx, ny, plane_stride(nx, ny, plane_pad), nsteps, seg, offs);
 }
 
 int lbf_tape_create(lbf_sim* sim, int32_t nsteps, int32_t segment, lbf_tape** out) {
@@ -176,7 +180,7 @@ int lbf_tape_create(lbf_sim* sim, int32_t nsteps, int32_t segment, lbf_tape** ou
   t->nck = (nsteps + t->seg - 1) / t->seg;
   t->P = (size_t)sim->G.P;
   size_t offs[kTapeParts];
-  t->bytes = tape_layout(sim->G.nx, sim->G.ny, nsteps, t->seg, offs);
+  t->bytes = tape_layout(sim->G.nx, sim->G.ny, sim->G.P, nsteps, t->seg, offs);
   if (hipMalloc((void**)&t->mem, t->bytes) != hipSuccess) {
     const size_t b = t->bytes;
     delete t;

@@ -30,9 +30,9 @@ int fail(int code, const char* fmt, ...) {
   return code;
 }
 
-Layout make_layout(int nx, int ny) {
+Layout make_layout(int nx, int ny, int pad) {
   Layout L{};
-  const size_t P = (size_t)plane_stride(nx, ny) * sizeof(float);
+  const size_t P = (size_t)plane_stride(nx, ny, pad) * sizeof(float);
   size_t off = 0;
   auto take = [&](size_t bytes) {
     size_t o = off;
@@ -83,7 +83,10 @@ BufArgs make_args(lbf_sim* s) {
 int validate(const lbf_params* p) {
   if (!p) return fail(LBF_EINVAL, "params is NULL");
   if (p->nx < 1 || p->ny < 1) return fail(LBF_EINVAL, "lattice size %d x %d", p->nx, p->ny);
-  if (plane_stride(p->nx, p->ny) > kMaxPlane)
+  if (p->plane_pad < 0 || p->plane_pad > kMaxPlanePad || p->plane_pad % 64)
+    return fail(LBF_EINVAL, "plane_pad %d (a multiple of 64 in [0, %d])", p->plane_pad,
+                kMaxPlanePad);
+  if (plane_stride(p->nx, p->ny, p->plane_pad) > kMaxPlane)
     return fail(LBF_EINVAL, "lattice of %d x %d nodes exceeds the %lld-node limit", p->nx, p->ny,
                 kMaxPlane);
   const double pos[] = {p->rho_l, p->rho_g, p->rho_s, p->mu_l, p->mu_g, p->mu_s, p->lam_l,
@@ -347,9 +350,10 @@ extern "C" {
 
 const char* lbf_last_error(void) { return g_err.c_str(); }
 
-size_t lbf_workspace_bytes(int32_t nx, int32_t ny) {
-  if (nx < 1 || ny < 1) return 0;
-  return make_layout(nx, ny).total;
+size_t lbf_workspace_bytes(int32_t nx, int32_t ny, int32_t plane_pad) {
+  if (nx < 1 || ny < 1 || plane_pad < 0 || plane_pad > kMaxPlanePad || plane_pad % 64) return 0;
+  if (plane_stride(nx, ny, plane_pad) > kMaxPlane) return 0;
+  return make_layout(nx, ny, plane_pad).total;
 }
 
 int lbf_create(const lbf_params* params, void* stream, void* workspace, size_t workspace_bytes,
@@ -369,9 +373,9 @@ int lbf_create(const lbf_params* params, void* stream, void* workspace, size_t w
     s->G.tbc[w] = params->thermal_bc[w];
     if (params->thermal_bc[w] == LBF_DIRICHLET) s->G.tmask |= 1 << w;
   }
-  s->G.P = (int)plane_stride(params->nx, params->ny);
+  s->G.P = (int)plane_stride(params->nx, params->ny, params->plane_pad);
   fill_phys(params, s->ph);
-  s->L = make_layout(params->nx, params->ny);
+  s->L = make_layout(params->nx, params->ny, params->plane_pad);
   s->stream = (hipStream_t)stream;
   if (workspace) {
     if (workspace_bytes < s->L.total) {

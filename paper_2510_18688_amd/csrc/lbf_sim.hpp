@@ -26,7 +26,14 @@ constexpr size_t kAlign = 256;
 inline size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 // Plane stride: nx * ny rounded up to 64 floats (256 bytes).
-inline long long plane_stride(int nx, int ny) { return (long long)round_up((size_t)nx * ny, 64); }
+// Floats between consecutive planes: the node count rounded up to 64, plus
+// `pad` (a multiple of 64).  Which HBM channels the 34 planes of a step hit
+// at one time depends on this stride; the autotuner picks the pad per size.
+inline long long plane_stride(int nx, int ny, int pad) {
+  return (long long)round_up((size_t)nx * ny, 64) + pad;
+}
+
+constexpr int kMaxPlanePad = 65536;
 
 // Kernels address each block of planes with 32-bit byte offsets: the 27
 // distribution planes must span less than 4 GiB.

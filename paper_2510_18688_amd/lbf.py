@@ -50,7 +50,7 @@ class Params(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("periodic_x", C.c_int32),
                 ("periodic_y", C.c_int32), ("thermal_bc", C.c_int32 * 4),
                 ("latch_fs", C.c_int32), ("h_src_tau_a", C.c_int32),
-                ("substrate_fixed", C.c_int32), ("reserved", C.c_int32)] + [
+                ("substrate_fixed", C.c_int32), ("plane_pad", C.c_int32)] + [
         (k, C.c_double) for k in (
             "rho_l", "rho_g", "rho_s", "mu_l", "mu_g", "mu_s", "lam_l", "lam_g", "lam_s",
             "cp_l", "cp_g", "cp_s", "latent", "T_m", "sigma", "eps", "mobility", "cos_psi",
@@ -76,7 +76,7 @@ def load(path: str = LIB_PATH):
     L = C.CDLL(path)
     vp, i32, f_p, d_p = C.c_void_p, C.c_int32, C.POINTER(C.c_float), C.POINTER(C.c_double)
     L.lbf_workspace_bytes.restype = C.c_size_t
-    L.lbf_workspace_bytes.argtypes = [i32, i32]
+    L.lbf_workspace_bytes.argtypes = [i32, i32, i32]
     L.lbf_create.argtypes = [C.POINTER(Params), vp, vp, C.c_size_t, C.POINTER(vp)]
     L.lbf_set_geometry.argtypes = [vp, vp, vp, i32]
     L.lbf_set_wall_temperature.argtypes = [vp, i32, vp, i32, i32]
@@ -107,7 +107,7 @@ def load(path: str = LIB_PATH):
     L.lbf_batch_items.argtypes = [vp]
     L.lbf_batch_destroy.argtypes = [vp]
     L.lbf_tape_bytes.restype = C.c_size_t
-    L.lbf_tape_bytes.argtypes = [i32, i32, i32, i32]
+    L.lbf_tape_bytes.argtypes = [i32, i32, i32, i32, i32]
     L.lbf_tape_create.argtypes = [vp, i32, i32, C.POINTER(vp)]
     L.lbf_tape_segment.restype = i32
     L.lbf_tape_segment.argtypes = [vp]
@@ -163,17 +163,18 @@ class Sim:
     """One lattice on the current HIP device; workspace owned by a torch tensor."""
 
     def __init__(self, case, tile: Optional[Sequence[int]] = None, device: str = "cuda",
-                 stream=None):
+                 stream=None, plane_pad: int = 0):
         torch = _torch()
         L = load()
         self.case = case
         self.nx, self.ny = case.nx, case.ny
         self.params = make_params(case)
+        self.params.plane_pad = int(plane_pad)
         self.device = torch.device(device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
-        nbytes = L.lbf_workspace_bytes(self.nx, self.ny)
+        nbytes = L.lbf_workspace_bytes(self.nx, self.ny, self.params.plane_pad)
         if nbytes == 0:
-            raise LbfError(-1, "bad lattice size")
+            raise LbfError(-1, f"bad lattice size {self.nx} x {self.ny} or plane_pad {plane_pad}")
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         h = C.c_void_p()
         check(L.lbf_create(C.byref(self.params), C.c_void_p(self.stream.cuda_stream),

@@ -75,9 +75,14 @@ def test_params3_layout_matches_header(tmp_path):
 
 
 def test_workspace_bytes(L):
-    assert L.lbf_workspace_bytes(0, 5) == 0
-    small = L.lbf_workspace_bytes(64, 48)
-    big = L.lbf_workspace_bytes(2048, 2048)
+    assert L.lbf_workspace_bytes(0, 5, 0) == 0
+    for bad in (-64, 32, 65536 + 64):
+        assert L.lbf_workspace_bytes(64, 48, bad) == 0
+    assert L.lbf_workspace_bytes(64, 48, 64) > L.lbf_workspace_bytes(64, 48, 0)
+    assert L.lbf_tape_bytes(64, 48, 32, 100, 0) == 0
+    assert L.lbf_tape_bytes(64, 48, 128, 100, 0) > L.lbf_tape_bytes(64, 48, 0, 100, 0)
+    small = L.lbf_workspace_bytes(64, 48, 0)
+    big = L.lbf_workspace_bytes(2048, 2048, 0)
     assert small > 64 * 48 * 4 * (27 * 2 + 7 * 2 + 3)
     # 71 resident state planes + 13 read-out planes + reduction scratch
     assert 2048 * 2048 * 4 * 84 <= big <= 2048 * 2048 * 4 * 88
@@ -108,6 +113,15 @@ def test_invalid_params_rejected_on_host(L, mutate, needle):
     mutate(case)
     rc, msg = _create_rc(L, case)
     assert rc == -1 and needle in msg
+
+
+@pytest.mark.parametrize("pad", [-64, 96, 65600])
+def test_invalid_plane_pad_rejected_on_host(L, pad):
+    p = lbf.make_params(W.sessile_drop(nx=16, ny=8))
+    p.plane_pad = pad
+    h = C.c_void_p()
+    assert L.lbf_create(C.byref(p), None, None, 0, C.byref(h)) == -1
+    assert "plane_pad" in L.lbf_last_error().decode()
 
 
 def test_null_arguments(L):
