@@ -39,7 +39,10 @@ typedef struct lbf3_params {
   int32_t nx, ny, nz;          /* lattice size, each >= 1 */
   int32_t periodic[3];         /* per axis: 1 periodic, 0 walls */
   int32_t thermal_bc[6];       /* per face: LBF_ADIABATIC or LBF_DIRICHLET */
-  int32_t latch_fs, h_src_tau_a, substrate_fixed, reserved;
+  int32_t latch_fs, h_src_tau_a, substrate_fixed;
+  int32_t plane_pad;           /* extra floats between consecutive planes, a
+                                  multiple of 64 in [0, 65536]; as in lbf_params
+                                  (layout only, results do not depend on it) */
   double rho_l, rho_g, rho_s;
   double mu_l, mu_g, mu_s;
   double lam_l, lam_g, lam_s;
@@ -58,9 +61,9 @@ typedef struct lbf3_params {
 
 typedef struct lbf3_sim lbf3_sim;
 
-/* Device bytes of one simulation's workspace, 0 for invalid sizes and for
- * lattices above the addressing limit. */
-size_t lbf3_workspace_bytes(int32_t nx, int32_t ny, int32_t nz);
+/* Device bytes of one simulation's workspace with lbf3_params.plane_pad,
+ * 0 for invalid sizes or pads and for lattices above the addressing limit. */
+size_t lbf3_workspace_bytes(int32_t nx, int32_t ny, int32_t nz, int32_t plane_pad);
 
 /* Create on HIP stream `stream` (NULL: default stream); workspace as in
  * lbf_create (caller-owned, 256-byte aligned, or NULL for a library

@@ -35,7 +35,7 @@ def lookup(nx: int, ny: int) -> Optional[Tuple[int, int]]:
     v = db.get(f"{nx}x{ny}")
     if v:
         return tuple(v["tile"])
-    sizes = [k for k in db if not k.startswith("batch")]
+    sizes = [k for k in db if k.count("x") == 1 and "tile" in db[k]]
     if not sizes:
         return None
 
@@ -71,36 +71,43 @@ PAD_CANDIDATES: Tuple[int, ...] = (0, 64, 128, 192, 320, 576, 1088, 2112, 4160, 
                                    8256, 12352, 16448)
 
 
-def lookup_pad(nx: int, ny: int) -> int:
-    """Tuned plane padding of a lattice size, 0 if that size was not measured."""
-    v = _load().get(f"{nx}x{ny}")
+def _key(*size: int) -> str:
+    return "x".join(str(int(v)) for v in size)
+
+
+def lookup_pad(*size: int) -> int:
+    """Tuned plane padding of a lattice size (nx, ny) or (nx, ny, nz), 0 if
+    that size was not measured."""
+    v = _load().get(_key(*size))
     return int(v.get("pad", 0)) if v else 0
 
 
-def tune_pad(case, tile: Sequence[int], steps: int = 100, repeats: int = 3,
+def tune_pad(case, tile: Optional[Sequence[int]] = None, steps: int = 100, repeats: int = 3,
              candidates: Iterable[int] = PAD_CANDIDATES, save: bool = True
              ) -> Tuple[int, dict]:
-    """Time the step of `case` with each plane padding (a fresh simulation
-    each, median of `repeats` runs of `steps` steps) and keep the best."""
+    """Time the step of `case` (2D, with launch shape `tile`, or 3D) with
+    each plane padding (a fresh simulation each, median of `repeats` runs of
+    `steps` steps) and keep the best."""
     import statistics
     from . import lbf
+    three = hasattr(case, "nz")
     times = {}
     for pad in candidates:
-        sim = lbf.Sim(case, tile=tile, plane_pad=pad)
+        sim = lbf.Sim3(case, plane_pad=pad) if three else lbf.Sim(case, tile=tile, plane_pad=pad)
         sim.step(10)
         sim.set_timing(True)
         runs = []
         for _ in range(repeats):
             sim.step(steps)
-            runs.append(sim.last_step_kernel_ms())
+            runs.append(sim.last_step_ms() if three else sim.last_step_kernel_ms())
         times[str(pad)] = statistics.median(runs)
         sim.close()
         del sim
     best = int(min(times, key=times.get))
     if save:
         db = _load()
-        key = f"{case.nx}x{case.ny}"
-        entry = db.get(key, {"tile": list(tile)})
+        key = _key(case.nx, case.ny, case.nz) if three else _key(case.nx, case.ny)
+        entry = db.get(key, {} if three else {"tile": list(tile)})
         entry["pad"], entry["pad_ms"] = best, times[str(best)]
         entry["pad_all"] = times
         db[key] = entry

@@ -32,10 +32,10 @@ struct Layout3 {
   int nblocks;
 };
 
-Layout3 make_layout3(int nx, int ny, int nz) {
+Layout3 make_layout3(int nx, int ny, int nz, int pad) {
   Layout3 L{};
   const size_t n = (size_t)nx * ny * nz;
-  L.P = up3(n, 64);
+  L.P = up3(n, 64) + pad;
   const size_t pb = L.P * sizeof(float);
   L.nblocks = (int)((n + 255) / 256);
   size_t off = 0;
@@ -306,7 +306,10 @@ int validate3(const lbf3_params* p) {
   if (!p) return fail(LBF_EINVAL, "params is NULL");
   if (p->nx < 1 || p->ny < 1 || p->nz < 1)
     return fail(LBF_EINVAL, "lattice size %d x %d x %d", p->nx, p->ny, p->nz);
-  if ((long long)p->nx * p->ny * p->nz > kMaxNodes3)
+  if (p->plane_pad < 0 || p->plane_pad > lbfi::kMaxPlanePad || p->plane_pad % 64)
+    return fail(LBF_EINVAL, "plane_pad %d (a multiple of 64 in [0, %d])", p->plane_pad,
+                lbfi::kMaxPlanePad);
+  if ((long long)up3((size_t)p->nx * p->ny * p->nz, 64) + p->plane_pad > kMaxNodes3)
     return fail(LBF_EINVAL, "lattice of %lld nodes exceeds the %lld-node limit",
                 (long long)p->nx * p->ny * p->nz, kMaxNodes3);
   const double pos[] = {p->rho_l, p->rho_g, p->rho_s, p->mu_l, p->mu_g, p->mu_s, p->lam_l,
@@ -426,10 +429,12 @@ int launch_pair(lbf3_sim* s, bool readout) {
 
 extern "C" {
 
-size_t lbf3_workspace_bytes(int32_t nx, int32_t ny, int32_t nz) {
+size_t lbf3_workspace_bytes(int32_t nx, int32_t ny, int32_t nz, int32_t plane_pad) {
   if (nx < 1 || ny < 1 || nz < 1) return 0;
+  if (plane_pad < 0 || plane_pad > lbfi::kMaxPlanePad || plane_pad % 64) return 0;
   if ((long long)nx * ny * nz > kMaxNodes3) return 0;
-  return make_layout3(nx, ny, nz).total;
+  if ((long long)up3((size_t)nx * ny * nz, 64) + plane_pad > kMaxNodes3) return 0;
+  return make_layout3(nx, ny, nz, plane_pad).total;
 }
 
 int lbf3_create(const lbf3_params* params, void* stream, void* workspace, size_t workspace_bytes,
@@ -449,7 +454,7 @@ int lbf3_create(const lbf3_params* params, void* stream, void* workspace, size_t
     s->G.Tw[f] = (float)params->wall_T[f];
   }
   fill_phys3(params, s->ph);
-  s->L = make_layout3(params->nx, params->ny, params->nz);
+  s->L = make_layout3(params->nx, params->ny, params->nz, params->plane_pad);
   s->G.P = (int)s->L.P;
   s->stream = (hipStream_t)stream;
   if (workspace) {

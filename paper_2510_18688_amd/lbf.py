@@ -482,7 +482,7 @@ class Params3(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
                 ("periodic", C.c_int32 * 3), ("thermal_bc", C.c_int32 * 6),
                 ("latch_fs", C.c_int32), ("h_src_tau_a", C.c_int32),
-                ("substrate_fixed", C.c_int32), ("reserved", C.c_int32)] + [
+                ("substrate_fixed", C.c_int32), ("plane_pad", C.c_int32)] + [
         (k, C.c_double) for k in (
             "rho_l", "rho_g", "rho_s", "mu_l", "mu_g", "mu_s", "lam_l", "lam_g", "lam_s",
             "cp_l", "cp_g", "cp_s", "latent", "T_m", "sigma", "eps", "mobility", "cos_psi",
@@ -495,7 +495,7 @@ def _declare3(L):
         return
     vp, i32 = C.c_void_p, C.c_int32
     L.lbf3_workspace_bytes.restype = C.c_size_t
-    L.lbf3_workspace_bytes.argtypes = [i32, i32, i32]
+    L.lbf3_workspace_bytes.argtypes = [i32, i32, i32, i32]
     L.lbf3_create.argtypes = [C.POINTER(Params3), vp, vp, C.c_size_t, C.POINTER(vp)]
     L.lbf3_set_geometry.argtypes = [vp, vp, vp, i32]
     L.lbf3_init_fields.argtypes = [vp, vp, vp, i32]
@@ -539,18 +539,19 @@ def make_params3(case) -> Params3:
 class Sim3:
     """One D3Q19 lattice on the current HIP device (workspace: a torch tensor)."""
 
-    def __init__(self, case, device: str = "cuda", stream=None):
+    def __init__(self, case, device: str = "cuda", stream=None, plane_pad: int = 0):
         torch = _torch()
         L = load()
         _declare3(L)
         self.case = case
         self.shape = (case.nz, case.ny, case.nx)
         self.params = make_params3(case)
+        self.params.plane_pad = int(plane_pad)
         self.device = torch.device(device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
-        nbytes = L.lbf3_workspace_bytes(case.nx, case.ny, case.nz)
+        nbytes = L.lbf3_workspace_bytes(case.nx, case.ny, case.nz, self.params.plane_pad)
         if nbytes == 0:
-            raise LbfError(-1, "bad lattice size")
+            raise LbfError(-1, f"bad lattice size {self.shape} or plane_pad {plane_pad}")
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         h = C.c_void_p()
         check(L.lbf3_create(C.byref(self.params), C.c_void_p(self.stream.cuda_stream),

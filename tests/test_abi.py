@@ -11,7 +11,7 @@ import tempfile
 
 import pytest
 
-from paper_2510_18688_amd import lbf, workloads as W
+from paper_2510_18688_amd import lbf, workloads as W, workloads3 as W3
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADERS = [os.path.join(ROOT, "include", h) for h in ("lbf.h", "lbf3.h", "lbf_pre.h")]
@@ -122,6 +122,11 @@ def test_invalid_plane_pad_rejected_on_host(L, pad):
     h = C.c_void_p()
     assert L.lbf_create(C.byref(p), None, None, 0, C.byref(h)) == -1
     assert "plane_pad" in L.lbf_last_error().decode()
+    lbf._declare3(L)
+    p3 = lbf.make_params3(W3.sphere_drop(8, 2.0))
+    p3.plane_pad = pad
+    assert L.lbf3_create(C.byref(p3), None, None, 0, C.byref(h)) == -1
+    assert "plane_pad" in L.lbf_last_error().decode()
 
 
 def test_null_arguments(L):
@@ -148,11 +153,17 @@ def test_null_arguments(L):
 
 def test_workspace3_bytes_and_limits(L):
     lbf._declare3(L)
-    assert L.lbf3_workspace_bytes(0, 4, 4) == 0
-    assert L.lbf3_workspace_bytes(4, 4, -1) == 0
-    a, b = L.lbf3_workspace_bytes(16, 16, 16), L.lbf3_workspace_bytes(32, 32, 32)
+    assert L.lbf3_workspace_bytes(0, 4, 4, 0) == 0
+    assert L.lbf3_workspace_bytes(4, 4, -1, 0) == 0
+    for bad in (-64, 32, 65536 + 64):
+        assert L.lbf3_workspace_bytes(4, 4, 4, bad) == 0
+    assert L.lbf3_workspace_bytes(16, 16, 16, 64) > L.lbf3_workspace_bytes(16, 16, 16, 0)
+    a, b = L.lbf3_workspace_bytes(16, 16, 16, 0), L.lbf3_workspace_bytes(32, 32, 32, 0)
     assert 0 < a < b
-    assert L.lbf3_workspace_bytes(1024, 1024, 1024) == 0      # above the addressing limit
+    assert L.lbf3_workspace_bytes(1024, 1024, 1024, 0) == 0      # above the addressing limit
+    kmax = (0xFFFFFFFF // (4 * 19)) // 64 * 64             # nodes addressable per block
+    assert L.lbf3_workspace_bytes(kmax - 64, 1, 1, 64) > 0
+    assert L.lbf3_workspace_bytes(kmax - 64, 1, 1, 128) == 0  # the pad counts against it
 
 
 @pytest.mark.parametrize("mutate, needle", [
