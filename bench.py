@@ -78,6 +78,8 @@ def parse():
                     help="steps of the 256 x 256 gradient workload (0 skips it)")
     ap.add_argument("--d3q19-steps", type=int, default=200,
                     help="steps of the D3Q19 workloads (0 skips them)")
+    ap.add_argument("--porous-steps", type=int, default=1000,
+                    help="steps of the 4096 x 2048 porous-medium leg (0: skip)")
     ap.add_argument("--mrt-steps", type=int, default=1000,
                     help="steps of the headline workload with the MRT flow collision (0 skips)")
     ap.add_argument("--ch-iterations", type=int, default=500,
@@ -269,6 +271,37 @@ def mrt(lbf, W, torch, steps, tile, pad):
             "frac": round(gbs / HBM_PEAK_GBS, 4), "nonfinite": red["nonfinite"]}
 
 
+def porous(lbf, W, torch, steps):
+    """The complex-geometry workload: 4096 x 2048 porous medium of random
+    circular grains (radii 20-60, porosity 0.6), walls on all sides, left
+    half liquid, cold left wall, contact angle 45 degrees, mass source on;
+    tuned tile and plane padding.  The same 284 B per update as the
+    headline workload."""
+    from paper_2510_18688_amd import autotune
+    case = W.porous_medium()
+    tile = autotune.lookup(case.nx, case.ny)
+    pad = autotune.lookup_pad(case.nx, case.ny)
+    sim = lbf.Sim(case, tile=tile, plane_pad=pad)
+    sim.step(50)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    sim.set_timing(True)
+    sim.step(steps)
+    kms = sim.last_step_kernel_ms()
+    red = sim.reduce()
+    sim.close()
+    gbs = BYTES_PER_LU * case.nodes / (kms * 1e-3) / 1e9
+    return {"workload": case.name, "nodes": case.nodes, "steps": steps,
+            "tile": f"{tile[0]}x{tile[1]}", "plane_pad": pad,
+            "mlups": round(case.nodes * steps / wall / 1e6, 1),
+            "kernel_ms": round(kms, 5), "achieved_gbs": round(gbs, 1),
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "nonfinite": red["nonfinite"],
+            "solid_fraction": round(red["sum_fs"] / case.nodes, 6)}
+
+
 def ch_smoothing(torch, iterations):
     """Porous pre-processing: Cahn-Hilliard smoothing of a synthetic sandpack
     image (porosity 0.3585, log-normal grains), 2D 4096 x 2048 with walls and
@@ -400,6 +433,8 @@ def main():
         out["adjoint"] = adjoint(lbf, W, torch, args.adjoint_steps)
     if args.mrt_steps > 0:
         out["mrt"] = mrt(lbf, W, torch, args.mrt_steps, tile, pad)
+    if args.porous_steps > 0:
+        out["porous"] = porous(lbf, W, torch, args.porous_steps)
     if args.d3q19_steps > 0:
         out["d3q19"] = d3q19(lbf, torch, args.d3q19_steps)
     if args.ch_iterations > 0:
