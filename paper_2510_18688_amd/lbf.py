@@ -160,7 +160,12 @@ def _f32_host(a) -> np.ndarray:
 
 
 class Sim:
-    """One lattice on the current HIP device; workspace owned by a torch tensor."""
+    """One lattice on the current HIP device; workspace owned by a torch tensor.
+
+    `tile` is the launch shape (threads along x, rows per block) and
+    `plane_pad` the padding between workspace planes in floats (a multiple
+    of 64); both change speed only, and `autotune.lookup` /
+    `autotune.lookup_pad` return the tuned values for a lattice size."""
 
     def __init__(self, case, tile: Optional[Sequence[int]] = None, device: str = "cuda",
                  stream=None, plane_pad: int = 0):
@@ -537,7 +542,8 @@ def make_params3(case) -> Params3:
 
 
 class Sim3:
-    """One D3Q19 lattice on the current HIP device (workspace: a torch tensor)."""
+    """One D3Q19 lattice on the current HIP device (workspace: a torch tensor);
+    `plane_pad` as for `Sim` (`autotune.lookup_pad(nx, ny, nz)`)."""
 
     def __init__(self, case, device: str = "cuda", stream=None, plane_pad: int = 0):
         torch = _torch()
