@@ -25,9 +25,9 @@ sys.path.insert(0, ROOT)
 
 # Algorithmic HBM bytes per lattice-node update of the step kernel: 27
 # distributions and 7 lagged planes read and written (FP32: f_s, Q, phi u,
-# p and the high parts of g_0, h_0), 3 static planes read (phi0, cos theta,
-# lap phi0).
-BYTES_PER_LU = (27 + 7) * 2 * 4 + 3 * 4
+# p and the high parts of g_0, h_0), 2 static planes read (phi0, cos theta;
+# the Laplacian of phi0 is formed from phi0 in the kernel).
+BYTES_PER_LU = (27 + 7) * 2 * 4 + 2 * 4
 HBM_PEAK_GBS = 8000.0
 # D3Q19, two kernels per step.  Moments pass: g and h pulled (38 planes), the
 # high parts of g_0, h_0, f_s and Q of the previous step, phi0 read; phi,
@@ -275,7 +275,7 @@ def porous(lbf, W, torch, steps):
     """The complex-geometry workload: 4096 x 2048 porous medium of random
     circular grains (radii 20-60, porosity 0.6), walls on all sides, left
     half liquid, cold left wall, contact angle 45 degrees, mass source on;
-    tuned tile and plane padding.  The same 284 B per update as the
+    tuned tile and plane padding.  The same 280 B per update as the
     headline workload."""
     from paper_2510_18688_amd import autotune
     case = W.porous_medium()

@@ -2,8 +2,9 @@
 //
 // A block of WX lanes owns a strip of WX columns and marches up CY rows.
 // Each lane keeps the pulled g and h of its current row in registers.  For
-// the 9-point stencils of phi, f_s, rho (and the lagged p) the block keeps a
-// ring of four rows of those values in LDS, WX + 2 wide; the row above the
+// the 9-point stencils of phi, f_s, rho, the lagged p and the static phi0
+// (its Laplacian is formed here rather than stored) the block keeps a ring
+// of four rows of those values in LDS, WX + 2 wide; the row above the
 // current one is computed (pull + moments) one iteration ahead, so the
 // moments of every node are computed once per block, plus one halo row at
 // each end of the strip.  The two halo columns of all CY + 2 rows are
@@ -15,11 +16,14 @@
 namespace lbf {
 
 constexpr int CY_MAX = 256;
+// values per node in the stencil ring: phi, f_s, rho, p of the previous step
+// and the static phi0 (whose Laplacian is taken from the ring, not stored)
+constexpr int NSV = 5;
 
 template <int WX>
 struct StepShared {
-  float v[4][4][WX + 2];        // [phi, fs, rho, p_prev][ring slot][column]
-  float halo[4][2][CY_MAX + 2]; // [field][left, right][row - (y0 - 1)]
+  float v[NSV][4][WX + 2];        // [phi, fs, rho, p_prev, phi0][ring slot][column]
+  float halo[NSV][2][CY_MAX + 2]; // [field][left, right][row - (y0 - 1)]
   double red[WX / 64][NRED];
 };
 
@@ -65,11 +69,14 @@ struct FlowIn {
   float cth, lap0, jxp, jyp;
 };
 
+// LAP0 = false leaves lap0 to the caller (the step kernel takes it from its
+// stencil ring).
+template <bool LAP0 = true>
 __device__ __forceinline__ void flow_load(const Geo& G, const Bufs& B, int x, int y, FlowIn& in) {
   pull_f(G, B, x, y, in.f);
   const int k = y * G.nx + x;
   in.cth = ldp(B.stat, ST_CTH, G.P, k);
-  in.lap0 = ldp(B.stat, ST_LAP0, G.P, k);
+  in.lap0 = LAP0 ? ldp(B.stat, ST_LAP0, G.P, k) : 0.0f;
   in.jxp = ldp(B.lin, LAG_JX, G.P, k);
   in.jyp = ldp(B.lin, LAG_JY, G.P, k);
 }
@@ -102,11 +109,12 @@ __device__ __forceinline__ void step_strip(const Geo& G, const Phys& ph, const B
       const int side = t & 1, r = t >> 1;
       NodeIn in;
       Mom m;
-      float st[4];
+      float st[NSV];
       node_load(G, ph, B, side ? xr : xl, map_axis(y0 - 1 + r, G.ny, G.py), in);
       node_finish(ph, in, m, st);
+      st[4] = in.phi0;
 #pragma unroll
-      for (int f = 0; f < 4; ++f) sh.halo[f][side][r] = st[f];
+      for (int f = 0; f < NSV; ++f) sh.halo[f][side][r] = st[f];
     }
   }
 
@@ -122,31 +130,33 @@ __device__ __forceinline__ void step_strip(const Geo& G, const Phys& ph, const B
   if (act) {
     NodeIn bin;
     Mom m;
-    float st[4];
+    float st[NSV];
     node_load(G, ph, B, x, map_axis(ys - dir, G.ny, G.py), bin);
     node_load(G, ph, B, x, ys, cin);
     node_load(G, ph, B, x, map_axis(ys + dir, G.ny, G.py), ain);
-    flow_load(G, B, x, ys, fin);
+    flow_load<false>(G, B, x, ys, fin);
     node_finish(ph, bin, m, st);
+    st[4] = bin.phi0;
 #pragma unroll
-    for (int f = 0; f < 4; ++f) sh.v[f][(ys - dir) & 3][l + 1] = st[f];
+    for (int f = 0; f < NSV; ++f) sh.v[f][(ys - dir) & 3][l + 1] = st[f];
     node_finish(ph, cin, cm, st);
+    st[4] = cin.phi0;
 #pragma unroll
-    for (int f = 0; f < 4; ++f) sh.v[f][ys & 3][l + 1] = st[f];
+    for (int f = 0; f < NSV; ++f) sh.v[f][ys & 3][l + 1] = st[f];
   }
   __syncthreads();
   // lane 0 places the left halo column, the last active lane the right one
   // (both, for a one-column strip)
   if (l == 0) {
 #pragma unroll
-    for (int f = 0; f < 4; ++f) {
+    for (int f = 0; f < NSV; ++f) {
       sh.v[f][(ys - dir) & 3][0] = sh.halo[f][0][ys - dir - (y0 - 1)];
       sh.v[f][ys & 3][0] = sh.halo[f][0][ys - (y0 - 1)];
     }
   }
   if (l == lastl) {
 #pragma unroll
-    for (int f = 0; f < 4; ++f) {
+    for (int f = 0; f < NSV; ++f) {
       sh.v[f][(ys - dir) & 3][lastl + 2] = sh.halo[f][1][ys - dir - (y0 - 1)];
       sh.v[f][ys & 3][lastl + 2] = sh.halo[f][1][ys - (y0 - 1)];
     }
@@ -162,20 +172,21 @@ __device__ __forceinline__ void step_strip(const Geo& G, const Phys& ph, const B
     Mom am;
     NodeIn next_c;
     if (act) {
-      float st[4];
+      float st[NSV];
       node_finish(ph, ain, am, st);
+      st[4] = ain.phi0;
 #pragma unroll
-      for (int f = 0; f < 4; ++f) sh.v[f][slot_n][l + 1] = st[f];
+      for (int f = 0; f < NSV; ++f) sh.v[f][slot_n][l + 1] = st[f];
       next_c = ain;
       if (more) {
         node_load(G, ph, B, x, map_axis(ya + dir, G.ny, G.py), ain);
-        flow_load(G, B, x, ya, fnx);   // before this row's collision
+        flow_load<false>(G, B, x, ya, fnx);   // before this row's collision
       }
     }
     if (l == 0 || l == lastl) {
       const int r = ya - (y0 - 1);
 #pragma unroll
-      for (int f = 0; f < 4; ++f) {
+      for (int f = 0; f < NSV; ++f) {
         if (l == 0) sh.v[f][slot_n][0] = sh.halo[f][0][r];
         if (l == lastl) sh.v[f][slot_n][lastl + 2] = sh.halo[f][1][r];
       }
@@ -194,6 +205,14 @@ __device__ __forceinline__ void step_strip(const Geo& G, const Phys& ph, const B
         S.rho[i] = sh.v[2][slot][col];
         S.p[i] = sh.v[3][slot][col];
       }
+      // static Laplacian of phi0 on the same ring (mirror ghosts at walls)
+      float lap = 0.0f;
+#pragma unroll
+      for (int i = 1; i < 9; ++i) {
+        const int slot = cy(i) == 0 ? s0 : (cy(i) > 0 ? sp1 : sm1);
+        lap += wgt(i) * (sh.v[4][slot][l + 1 + cx(i)] - cin.phi0);
+      }
+      const float lap0 = 6.0f * lap;
       float* fv = fin.f;
       float* cg = cin.g;
       float* ch = cin.h;
@@ -207,7 +226,7 @@ __device__ __forceinline__ void step_strip(const Geo& G, const Phys& ph, const B
       }
       Post o;
       if (MODE != MODE_FIELDS) {
-        collide_node<true, MRT>(ph, cm, S, phi0, fin.cth, fin.lap0, cQp, fin.jxp, fin.jyp, crh, fv,
+        collide_node<true, MRT>(ph, cm, S, phi0, fin.cth, lap0, cQp, fin.jxp, fin.jyp, crh, fv,
                                 cg, ch, o);
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
@@ -233,7 +252,7 @@ __device__ __forceinline__ void step_strip(const Geo& G, const Phys& ph, const B
           a_reset += o.reset;
         }
       } else {
-        collide_node<false, MRT>(ph, cm, S, phi0, fin.cth, fin.lap0, cQp, fin.jxp, fin.jyp, crh,
+        collide_node<false, MRT>(ph, cm, S, phi0, fin.cth, lap0, cQp, fin.jxp, fin.jyp, crh,
                                  fv, cg, ch, o);
         stp(B.fields, 0, P, k, cm.phi);
         stp(B.fields, 1, P, k, cm.T);
