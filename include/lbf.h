@@ -224,7 +224,9 @@ int lbf_set_tile(lbf_sim* sim, int32_t tile_x, int32_t tile_y);
 int lbf_get_tile(const lbf_sim* sim, int32_t* tile_x, int32_t* tile_y);
 
 /* Bytes of the checkpointable dynamic state and copy of it to / from `buf`
- * (device memory).  A loaded state continues bit-identically. */
+ * (device memory).  The buffer holds each plane's nx * ny values back to
+ * back, so a state loads into any simulation of the same lattice size
+ * whatever its plane_pad.  A loaded state continues bit-identically. */
 size_t lbf_state_bytes(const lbf_sim* sim);
 int lbf_save_state(lbf_sim* sim, void* dst_device, size_t cap);
 int lbf_load_state(lbf_sim* sim, const void* src_device, size_t bytes);

@@ -587,9 +587,13 @@ int lbf3_reduce(lbf3_sim* s, double* out) {
   return LBF_OK;
 }
 
+// The saved state holds each plane's nx * ny * nz values back to back, so it
+// loads into a simulation of the same lattice whatever its plane_pad.
+constexpr long long kState3Magic = 0x6c626634LL;
+
 size_t lbf3_state_bytes(const lbf3_sim* s) {
   if (!s) return 0;
-  return (size_t)(NDIST + NLAG) * s->L.P * sizeof(float) + 64;
+  return (size_t)(NDIST + NLAG) * N3(s) * sizeof(float) + 64;
 }
 
 int lbf3_save_state(lbf3_sim* s, void* dst, size_t cap) {
@@ -598,11 +602,13 @@ int lbf3_save_state(lbf3_sim* s, void* dst, size_t cap) {
   const size_t need = lbf3_state_bytes(s);
   if (cap < need) return fail(LBF_ENOMEM, "state needs %zu bytes", need);
   char* d = (char*)dst;
-  const size_t pb = s->L.P * sizeof(float), db = NDIST * pb, lb = NLAG * pb;
-  HIP_TRY(hipMemcpyAsync(d, s->ws + s->L.dist[s->cur], db, hipMemcpyDeviceToDevice, s->stream));
-  HIP_TRY(hipMemcpyAsync(d + db, s->ws + s->L.lag[s->cur], lb, hipMemcpyDeviceToDevice,
-                         s->stream));
-  long long hdr[8] = {0x6c626633LL, s->step, s->G.n[0], s->G.n[1], s->G.n[2], 0, 0, 0};
+  const size_t nb = (size_t)N3(s) * sizeof(float), pb = s->L.P * sizeof(float);
+  const size_t db = NDIST * nb, lb = NLAG * nb;
+  HIP_TRY(hipMemcpy2DAsync(d, nb, s->ws + s->L.dist[s->cur], pb, nb, NDIST,
+                           hipMemcpyDeviceToDevice, s->stream));
+  HIP_TRY(hipMemcpy2DAsync(d + db, nb, s->ws + s->L.lag[s->cur], pb, nb, NLAG,
+                           hipMemcpyDeviceToDevice, s->stream));
+  long long hdr[8] = {kState3Magic, s->step, s->G.n[0], s->G.n[1], s->G.n[2], 0, 0, 0};
   HIP_TRY(hipMemcpyAsync(d + db + lb, hdr, sizeof hdr, hipMemcpyHostToDevice, s->stream));
   HIP_TRY(hipStreamSynchronize(s->stream));
   return LBF_OK;
@@ -614,16 +620,18 @@ int lbf3_load_state(lbf3_sim* s, const void* src, size_t bytes) {
   if (bytes < need) return fail(LBF_EINVAL, "state of %zu bytes, %zu needed", bytes, need);
   if (!s->have_geo) return fail(LBF_ESTATE, "lbf3_set_geometry must precede lbf3_load_state");
   const char* d = (const char*)src;
-  const size_t pb = s->L.P * sizeof(float), db = NDIST * pb, lb = NLAG * pb;
+  const size_t nb = (size_t)N3(s) * sizeof(float), pb = s->L.P * sizeof(float);
+  const size_t db = NDIST * nb, lb = NLAG * nb;
   long long hdr[8];
   HIP_TRY(hipMemcpyAsync(hdr, d + db + lb, sizeof hdr, hipMemcpyDeviceToHost, s->stream));
   HIP_TRY(hipStreamSynchronize(s->stream));
-  if (hdr[0] != 0x6c626633LL || hdr[2] != s->G.n[0] || hdr[3] != s->G.n[1] ||
+  if (hdr[0] != kState3Magic || hdr[2] != s->G.n[0] || hdr[3] != s->G.n[1] ||
       hdr[4] != s->G.n[2])
     return fail(LBF_EINVAL, "state buffer does not match this lattice");
-  HIP_TRY(hipMemcpyAsync(s->ws + s->L.dist[s->cur], d, db, hipMemcpyDeviceToDevice, s->stream));
-  HIP_TRY(hipMemcpyAsync(s->ws + s->L.lag[s->cur], d + db, lb, hipMemcpyDeviceToDevice,
-                         s->stream));
+  HIP_TRY(hipMemcpy2DAsync(s->ws + s->L.dist[s->cur], pb, d, nb, nb, NDIST,
+                           hipMemcpyDeviceToDevice, s->stream));
+  HIP_TRY(hipMemcpy2DAsync(s->ws + s->L.lag[s->cur], pb, d + db, nb, nb, NLAG,
+                           hipMemcpyDeviceToDevice, s->stream));
   HIP_TRY(hipStreamSynchronize(s->stream));
   s->step = hdr[1];
   s->have_init = true;

@@ -609,9 +609,14 @@ int lbf_get_tile(const lbf_sim* s, int32_t* tile_x, int32_t* tile_y) {
   return LBF_OK;
 }
 
+// The saved state holds each plane's nx * ny values back to back (not the
+// workspace's padded stride), so it loads into a simulation of the same
+// lattice whatever its plane_pad.
+constexpr long long kStateMagic = 0x6c626674LL;
+
 size_t lbf_state_bytes(const lbf_sim* s) {
   if (!s) return 0;
-  return (size_t)(NDIST + NLAG) * s->G.P * sizeof(float) + 64;
+  return (size_t)(NDIST + NLAG) * s->G.nx * s->G.ny * sizeof(float) + 64;
 }
 
 int lbf_save_state(lbf_sim* s, void* dst, size_t cap) {
@@ -620,11 +625,14 @@ int lbf_save_state(lbf_sim* s, void* dst, size_t cap) {
   const size_t need = lbf_state_bytes(s);
   if (cap < need) return fail(LBF_ENOMEM, "state needs %zu bytes", need);
   char* d = (char*)dst;
+  const size_t nb = (size_t)s->G.nx * s->G.ny * sizeof(float);
   const size_t pb = (size_t)s->G.P * sizeof(float);
-  const size_t db = NDIST * pb, lb = NLAG * pb;
-  HIP_TRY(hipMemcpyAsync(d, s->ws + s->L.dist[s->cur], db, hipMemcpyDeviceToDevice, s->stream));
-  HIP_TRY(hipMemcpyAsync(d + db, s->ws + s->L.lag[s->cur], lb, hipMemcpyDeviceToDevice, s->stream));
-  long long hdr[8] = {0x6c626673LL, s->step, s->G.nx, s->G.ny, 0, 0, 0, 0};
+  HIP_TRY(hipMemcpy2DAsync(d, nb, s->ws + s->L.dist[s->cur], pb, nb, NDIST,
+                           hipMemcpyDeviceToDevice, s->stream));
+  HIP_TRY(hipMemcpy2DAsync(d + NDIST * nb, nb, s->ws + s->L.lag[s->cur], pb, nb, NLAG,
+                           hipMemcpyDeviceToDevice, s->stream));
+  const size_t db = NDIST * nb, lb = NLAG * nb;
+  long long hdr[8] = {kStateMagic, s->step, s->G.nx, s->G.ny, 0, 0, 0, 0};
   HIP_TRY(hipMemcpyAsync(d + db + lb, hdr, sizeof hdr, hipMemcpyHostToDevice, s->stream));
   HIP_TRY(hipStreamSynchronize(s->stream));
   return LBF_OK;
@@ -635,16 +643,19 @@ int lbf_load_state(lbf_sim* s, const void* src, size_t bytes) {
   const size_t need = lbf_state_bytes(s);
   if (bytes < need) return fail(LBF_EINVAL, "state of %zu bytes, %zu needed", bytes, need);
   const char* d = (const char*)src;
+  const size_t nb = (size_t)s->G.nx * s->G.ny * sizeof(float);
   const size_t pb = (size_t)s->G.P * sizeof(float);
-  const size_t db = NDIST * pb, lb = NLAG * pb;
+  const size_t db = NDIST * nb, lb = NLAG * nb;
   long long hdr[8];
   HIP_TRY(hipMemcpyAsync(hdr, d + db + lb, sizeof hdr, hipMemcpyDeviceToHost, s->stream));
   HIP_TRY(hipStreamSynchronize(s->stream));
-  if (hdr[0] != 0x6c626673LL || hdr[2] != s->G.nx || hdr[3] != s->G.ny)
+  if (hdr[0] != kStateMagic || hdr[2] != s->G.nx || hdr[3] != s->G.ny)
     return fail(LBF_EINVAL, "state buffer does not match this lattice");
   if (!s->have_geo) return fail(LBF_ESTATE, "lbf_set_geometry must precede lbf_load_state");
-  HIP_TRY(hipMemcpyAsync(s->ws + s->L.dist[s->cur], d, db, hipMemcpyDeviceToDevice, s->stream));
-  HIP_TRY(hipMemcpyAsync(s->ws + s->L.lag[s->cur], d + db, lb, hipMemcpyDeviceToDevice, s->stream));
+  HIP_TRY(hipMemcpy2DAsync(s->ws + s->L.dist[s->cur], pb, d, nb, nb, NDIST,
+                           hipMemcpyDeviceToDevice, s->stream));
+  HIP_TRY(hipMemcpy2DAsync(s->ws + s->L.lag[s->cur], pb, d + db, nb, nb, NLAG,
+                           hipMemcpyDeviceToDevice, s->stream));
   HIP_TRY(hipStreamSynchronize(s->stream));
   s->step = hdr[1];
   s->have_init = true;

@@ -1,7 +1,8 @@
 """The plane padding of the workspace (lbf_params.plane_pad) is a layout
 choice only (needs a device): with any pad the step, the read-out, the
 reductions, the checkpoint, the batched launch and the adjoint give the
-same bits as without one."""
+same bits as without one, and a checkpoint moves between simulations of
+different pads."""
 
 import numpy as np
 import pytest
@@ -113,3 +114,35 @@ def test_pad_gives_the_same_bits_3d(lbf_mod, pad):
     Fa, Fb = a.fields(), b.fields()
     for k in Fa:
         assert np.array_equal(Fa[k], Fb[k]), k
+
+
+def test_checkpoint_moves_between_pads(lbf_mod):
+    import torch
+    from paper_2510_18688_amd import workloads3 as W3
+    case = lambda: W.porous_medium(nx=131, ny=67, seed=5, rmin=6.0, rmax=10.0, porosity=0.8)
+    a, b = lbf_mod.Sim(case()), lbf_mod.Sim(case(), plane_pad=4160)
+    assert a.state_bytes() == b.state_bytes() == (27 + 7) * 131 * 67 * 4 + 64
+    a.step(25)
+    buf = torch.empty(a.state_bytes(), dtype=torch.uint8, device="cuda")
+    a.save_state(buf)
+    b.load_state(buf)
+    a.step(15)
+    b.step(15)
+    same(a.fields(), b.fields(), "2D checkpoint pad 0 -> 4160")
+    b.save_state(buf)
+    c = lbf_mod.Sim(case(), plane_pad=64)
+    c.load_state(buf)
+    c.step(5)
+    a.step(5)
+    same(a.fields(), c.fields(), "2D checkpoint pad 4160 -> 64")
+    case3 = lambda: W3.fracture(nx=36, ny=20, nz=14, aperture=7.0, roughness=1.5)
+    d, e = lbf_mod.Sim3(case3(), plane_pad=4224), lbf_mod.Sim3(case3())
+    d.step(12)
+    buf3 = torch.empty(d.state_bytes(), dtype=torch.uint8, device="cuda")
+    d.save_state(buf3)
+    e.load_state(buf3)
+    d.step(9)
+    e.step(9)
+    Fd, Fe = d.fields(), e.fields()
+    for k in Fd:
+        assert np.array_equal(Fd[k], Fe[k]), k
