@@ -18,8 +18,14 @@
  * that the implicit and time-derivative terms need (f_s, Q = rho C_p T mdot,
  * phi u and p of the previous step).
  *
- * Readings of the paper where it is silent or garbled are numbered R1..R44
+ * Readings of the paper where it is silent or garbled are numbered R1..R53
  * and listed in the design notes; each is marked below where it applies.
+ *
+ * Parity unpinned: the phase-change fraction chi (R1-R3: which part of the
+ * liquid may freeze, its latch by the previous ice fraction) and its floor
+ * (R45) have no value printed by the paper to pin against; they are checked
+ * only through the enthalpy-map identities, the exact budgets and the
+ * three-phase Stefan problem (Table 1), where no gas is present.
  */
 #include <math.h>
 #include <stdint.h>
