@@ -3,7 +3,8 @@
 // tile of c with a two-node halo into LDS, computes the chemical potential
 // on the tile plus a one-node ring, and updates c on the tile, so HBM sees
 // one read and one write of c per node and step (the halo re-reads hit L2:
-// tiles are dealt to the XCDs in contiguous bands).
+// tiles are dealt to the XCDs in contiguous bands).  Each lane owns columns
+// of the boxes and slides a window of registers along them.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -63,59 +64,211 @@ __device__ __forceinline__ float lds_laplacian(const float* X, int i) {
   return 6.0f * (wa * axis + (1.0f / 36.0f) * diag);
 }
 
-// One Euler step on a TX x TY x TZ tile (TZ = 1 and no z halo in 2D).
-template <int DIM, int TX, int TY, int TZ>
-__global__ __launch_bounds__(256) void k_ch_step(ChGeo G, const float* __restrict__ c,
-                                                 float* __restrict__ cn, float A, float kappa,
-                                                 float dtM, int ntx, int nty, int ntiles) {
-  constexpr int HZ = DIM == 3 ? 1 : 0;
-  constexpr int LX = TX + 4, LY = TY + 4, LZ = TZ + 4 * HZ;   // c box, halo 2
-  constexpr int MX = TX + 2, MY = TY + 2, MZ = TZ + 2 * HZ;   // mu box, halo 1
+// The 2D step with the work laid out by columns: lane (tx, ty) of a 64 x 4
+// block owns column tx of the tile and a run of consecutive rows, and slides
+// a 3 x 3 window of registers up its column, so each stencil reads three new
+// LDS values instead of nine and the box indices are formed once per column.
+// Same operands, in the same order, as lds_laplacian<2, ...>.
+template <int TX, int TY>
+__global__ __launch_bounds__(256) void k_ch_step2(ChGeo G, const float* __restrict__ c,
+                                                  float* __restrict__ cn, float A, float kappa,
+                                                  float dtM, int ntx, int ntiles) {
+  static_assert(TX == 64 && TY % 4 == 0, "64 lanes per row, four row groups");
+  constexpr int LX = TX + 4, LY = TY + 4;   // c box, halo 2
+  constexpr int MX = TX + 2, MY = TY + 2;   // mu box, halo 1
+  constexpr float wa = 1.0f / 9.0f, wd = 1.0f / 36.0f;
+  __shared__ float cs[LX * LY];
+  __shared__ float ms[MX * MY];
+  const int t = lbf::xcd_tile(blockIdx.x, ntiles);
+  const int x0 = (t % ntx) * TX, y0 = (t / ntx) * TY;
+  const int nx = G.n[0], ny = G.n[1];
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  {
+    const int gx = wrap_or_clamp(x0 + tx - 2, nx, G.per[0]);
+    for (int ly = ty; ly < LY; ly += 4) {
+      const int gy = wrap_or_clamp(y0 + ly - 2, ny, G.per[1]);
+      cs[ly * LX + tx] = c[gy * nx + gx];
+    }
+    const int e = threadIdx.x;   // the last four columns of the box
+    if (e < 4 * LY) {
+      const int lx = TX + (e & 3), ly = e >> 2;
+      const int gx2 = wrap_or_clamp(x0 + lx - 2, nx, G.per[0]);
+      const int gy2 = wrap_or_clamp(y0 + ly - 2, ny, G.per[1]);
+      cs[ly * LX + lx] = c[gy2 * nx + gx2];
+    }
+  }
+  __syncthreads();
+  {
+    // mu on rows [r0, r1) of column tx; the window holds c rows my .. my + 2
+    // of box columns tx .. tx + 2 (centre (my + 1, tx + 1))
+    constexpr int RG = (MY + 3) / 4;
+    const int r0 = ty * RG, r1 = min(r0 + RG, MY);
+    float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, b0 = 0.0f, b1 = 0.0f, b2 = 0.0f;
+    if (r0 < r1) {
+      a0 = cs[r0 * LX + tx]; a1 = cs[r0 * LX + tx + 1]; a2 = cs[r0 * LX + tx + 2];
+      b0 = cs[(r0 + 1) * LX + tx]; b1 = cs[(r0 + 1) * LX + tx + 1]; b2 = cs[(r0 + 1) * LX + tx + 2];
+    }
+    for (int my = r0; my < r1; ++my) {
+      const float c0 = cs[(my + 2) * LX + tx], c1 = cs[(my + 2) * LX + tx + 1],
+                  c2 = cs[(my + 2) * LX + tx + 2];
+      const float xc = b1;
+      float axis = 0.0f, diag = 0.0f;
+      diag += a0 - xc; axis += a1 - xc; diag += a2 - xc;
+      axis += b0 - xc; axis += b2 - xc;
+      diag += c0 - xc; axis += c1 - xc; diag += c2 - xc;
+      const float lap = 6.0f * (wa * axis + wd * diag);
+      ms[my * MX + tx] = A * (xc * xc * xc - xc) - kappa * lap;
+      a0 = b0; a1 = b1; a2 = b2;
+      b0 = c0; b1 = c1; b2 = c2;
+    }
+    const int e = threadIdx.x;   // the last two columns of the mu box
+    if (e < 2 * MY) {
+      const int mx = TX + (e & 1), my = e >> 1;
+      const int j = (my + 1) * LX + mx + 1;
+      const float cc = cs[j];
+      ms[my * MX + mx] = A * (cc * cc * cc - cc) - kappa * lds_laplacian<2, LX, LX * LY>(cs, j);
+    }
+  }
+  __syncthreads();
+  if ((!G.per[0] && (x0 == 0 || x0 + TX >= nx)) || (!G.per[1] && (y0 == 0 || y0 + TY >= ny))) {
+    // beyond a mirror wall the potential is that of the first node
+    for (int i = threadIdx.x; i < MX * MY; i += 256) {
+      const int mx = i % MX, my = i / MX;
+      const int gx = x0 + mx - 1, gy = y0 + my - 1;
+      const int sx = G.per[0] ? gx : min(max(gx, 0), nx - 1);
+      const int sy = G.per[1] ? gy : min(max(gy, 0), ny - 1);
+      if (sx != gx || sy != gy) ms[i] = ms[(sy - y0 + 1) * MX + sx - x0 + 1];
+    }
+    __syncthreads();
+  }
+  {
+    // update on rows [o0, o0 + TY / 4) of column tx; window over mu rows
+    constexpr int RO = TY / 4;
+    const int o0 = ty * RO, gx = x0 + tx;
+    float a0 = ms[o0 * MX + tx], a1 = ms[o0 * MX + tx + 1], a2 = ms[o0 * MX + tx + 2];
+    float b0 = ms[(o0 + 1) * MX + tx], b1 = ms[(o0 + 1) * MX + tx + 1],
+          b2 = ms[(o0 + 1) * MX + tx + 2];
+    for (int oy = o0; oy < o0 + RO; ++oy) {
+      const float c0 = ms[(oy + 2) * MX + tx], c1 = ms[(oy + 2) * MX + tx + 1],
+                  c2 = ms[(oy + 2) * MX + tx + 2];
+      const float xc = b1;
+      float axis = 0.0f, diag = 0.0f;
+      diag += a0 - xc; axis += a1 - xc; diag += a2 - xc;
+      axis += b0 - xc; axis += b2 - xc;
+      diag += c0 - xc; axis += c1 - xc; diag += c2 - xc;
+      const float lap = 6.0f * (wa * axis + wd * diag);
+      const int gy = y0 + oy;
+      if (gx < nx && gy < ny) cn[gy * nx + gx] = cs[(oy + 2) * LX + tx + 2] + dtM * lap;
+      a0 = b0; a1 = b1; a2 = b2;
+      b0 = c0; b1 = c1; b2 = c2;
+    }
+  }
+}
+
+// Laplacian of the centre of three 3 x 3 slices (z - 1, z, z + 1; entry
+// 3 (dy + 1) + dx + 1) with the D3Q19 weights, accumulated in the order of
+// lds_laplacian<3, ...>.
+__device__ __forceinline__ float slice_laplacian19(const float* p, const float* q,
+                                                   const float* r) {
+  const float xc = q[4];
+  float axis = 0.0f, diag = 0.0f;
+  diag += p[1] - xc; diag += p[3] - xc; axis += p[4] - xc; diag += p[5] - xc; diag += p[7] - xc;
+  diag += q[0] - xc; axis += q[1] - xc; diag += q[2] - xc;
+  axis += q[3] - xc; axis += q[5] - xc;
+  diag += q[6] - xc; axis += q[7] - xc; diag += q[8] - xc;
+  diag += r[1] - xc; diag += r[3] - xc; axis += r[4] - xc; diag += r[5] - xc; diag += r[7] - xc;
+  return 6.0f * ((1.0f / 18.0f) * axis + (1.0f / 36.0f) * diag);
+}
+
+// the 3 x 3 neighbourhood of (x, y) in slice z of an LDS box
+template <int SX, int SXY>
+__device__ __forceinline__ void load_slice(const float* X, int x, int y, int z, float* out) {
+#pragma unroll
+  for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+    for (int dx = -1; dx <= 1; ++dx) out[(dy + 1) * 3 + dx + 1] = X[z * SXY + (y + dy) * SX + x + dx];
+}
+
+// The 3D step with the work laid out by columns along z: a lane owns an
+// (x, y) column of a box and slides three slices of its 3 x 3 neighbourhood
+// up the column, so each stencil reads nine new LDS values instead of
+// eighteen and the box indices are formed once per column.
+template <int TX, int TY, int TZ>
+__global__ __launch_bounds__(256) void k_ch_step3(ChGeo G, const float* __restrict__ c,
+                                                  float* __restrict__ cn, float A, float kappa,
+                                                  float dtM, int ntx, int nty, int ntiles) {
+  static_assert(TX * TY == 256, "one output column per lane");
+  constexpr int LX = TX + 4, LY = TY + 4, LZ = TZ + 4;   // c box, halo 2
+  constexpr int MX = TX + 2, MY = TY + 2, MZ = TZ + 2;   // mu box, halo 1
   __shared__ float cs[LX * LY * LZ];
   __shared__ float ms[MX * MY * MZ];
   const int t = lbf::xcd_tile(blockIdx.x, ntiles);
   const int x0 = (t % ntx) * TX, y0 = ((t / ntx) % nty) * TY, z0 = (t / (ntx * nty)) * TZ;
   const int nx = G.n[0], ny = G.n[1], nz = G.n[2];
-  for (int i = threadIdx.x; i < LX * LY * LZ; i += 256) {
-    const int lx = i % LX, ly = (i / LX) % LY, lz = i / (LX * LY);
+  for (int col = threadIdx.x; col < LX * LY; col += 256) {
+    const int lx = col % LX, ly = col / LX;
     const int gx = wrap_or_clamp(x0 + lx - 2, nx, G.per[0]);
     const int gy = wrap_or_clamp(y0 + ly - 2, ny, G.per[1]);
-    const int gz = DIM == 3 ? wrap_or_clamp(z0 + lz - 2, nz, G.per[2]) : 0;
-    cs[i] = c[(gz * ny + gy) * nx + gx];   // < 2^31 nodes
+#pragma unroll
+    for (int lz = 0; lz < LZ; ++lz) {
+      const int gz = wrap_or_clamp(z0 + lz - 2, nz, G.per[2]);
+      cs[(lz * LY + ly) * LX + lx] = c[(gz * ny + gy) * nx + gx];   // < 2^31 nodes
+    }
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < MX * MY * MZ; i += 256) {
-    const int mx = i % MX, my = (i / MX) % MY, mz = i / (MX * MY);
-    const int j = ((mz + HZ) * LY + my + 1) * LX + mx + 1;
-    const float cc = cs[j];
-    ms[i] = A * (cc * cc * cc - cc) - kappa * lds_laplacian<DIM, LX, LX * LY>(cs, j);
+  for (int col = threadIdx.x; col < MX * MY; col += 256) {
+    const int mx = col % MX, my = col / MX;
+    float p[9], q[9], r[9];
+    load_slice<LX, LX * LY>(cs, mx + 1, my + 1, 0, p);
+    load_slice<LX, LX * LY>(cs, mx + 1, my + 1, 1, q);
+#pragma unroll
+    for (int mz = 0; mz < MZ; ++mz) {
+      load_slice<LX, LX * LY>(cs, mx + 1, my + 1, mz + 2, r);
+      const float cc = q[4];
+      ms[(mz * MY + my) * MX + mx] = A * (cc * cc * cc - cc) - kappa * slice_laplacian19(p, q, r);
+#pragma unroll
+      for (int k = 0; k < 9; ++k) {
+        p[k] = q[k];
+        q[k] = r[k];
+      }
+    }
   }
   __syncthreads();
-  // beyond a mirror wall the potential is that of the first node (its
-  // ghost); the source is always an in-domain node of the same box.  Only
-  // tiles whose ring reaches past a wall have such cells.
   const bool at_wall = (!G.per[0] && (x0 == 0 || x0 + TX >= nx)) ||
                        (!G.per[1] && (y0 == 0 || y0 + TY >= ny)) ||
-                       (DIM == 3 && !G.per[2] && (z0 == 0 || z0 + TZ >= nz));
+                       (!G.per[2] && (z0 == 0 || z0 + TZ >= nz));
   if (at_wall) {
+    // beyond a mirror wall the potential is that of the first node
     for (int i = threadIdx.x; i < MX * MY * MZ; i += 256) {
       const int mx = i % MX, my = (i / MX) % MY, mz = i / (MX * MY);
-      const int gx = x0 + mx - 1, gy = y0 + my - 1, gz = z0 + mz - HZ;
+      const int gx = x0 + mx - 1, gy = y0 + my - 1, gz = z0 + mz - 1;
       const int sx = G.per[0] ? gx : min(max(gx, 0), nx - 1);
       const int sy = G.per[1] ? gy : min(max(gy, 0), ny - 1);
-      const int sz = (DIM == 3 && !G.per[2]) ? min(max(gz, 0), nz - 1) : gz;
+      const int sz = G.per[2] ? gz : min(max(gz, 0), nz - 1);
       if (sx != gx || sy != gy || sz != gz)
-        ms[i] = ms[((sz - z0 + HZ) * MY + sy - y0 + 1) * MX + sx - x0 + 1];
+        ms[i] = ms[((sz - z0 + 1) * MY + sy - y0 + 1) * MX + sx - x0 + 1];
     }
     __syncthreads();
   }
-  for (int o = threadIdx.x; o < TX * TY * TZ; o += 256) {
-    const int ox = o % TX, oy = (o / TX) % TY, oz = o / (TX * TY);
-    const int gx = x0 + ox, gy = y0 + oy, gz = z0 + oz;
-    if (gx >= nx || gy >= ny || gz >= nz) continue;
-    const int j = ((oz + 2 * HZ) * LY + oy + 2) * LX + ox + 2;
-    const int m = ((oz + HZ) * MY + oy + 1) * MX + ox + 1;
-    cn[(gz * ny + gy) * nx + gx] = cs[j] + dtM * lds_laplacian<DIM, MX, MX * MY>(ms, m);
+  {
+    const int ox = threadIdx.x % TX, oy = threadIdx.x / TX;
+    const int gx = x0 + ox, gy = y0 + oy;
+    float p[9], q[9], r[9];
+    load_slice<MX, MX * MY>(ms, ox + 1, oy + 1, 0, p);
+    load_slice<MX, MX * MY>(ms, ox + 1, oy + 1, 1, q);
+#pragma unroll
+    for (int oz = 0; oz < TZ; ++oz) {
+      load_slice<MX, MX * MY>(ms, ox + 1, oy + 1, oz + 2, r);
+      const int gz = z0 + oz;
+      if (gx < nx && gy < ny && gz < nz)
+        cn[(gz * ny + gy) * nx + gx] = cs[((oz + 2) * LY + oy + 2) * LX + ox + 2] +
+                                       dtM * slice_laplacian19(p, q, r);
+#pragma unroll
+      for (int k = 0; k < 9; ++k) {
+        p[k] = q[k];
+        q[k] = r[k];
+      }
+    }
   }
 }
 
@@ -198,11 +351,11 @@ int lbf_ch_smooth(const lbf_ch_params* p, const uint8_t* solid, int32_t solid_on
     int cur = 0;
     for (int it = 0; it < iterations; ++it) {
       if (is3d)
-        hipLaunchKernelGGL((k_ch_step<3, kTX3, kTY3, kTZ3>), dim3(ntiles), dim3(256), 0, st, G,
+        hipLaunchKernelGGL((k_ch_step3<kTX3, kTY3, kTZ3>), dim3(ntiles), dim3(256), 0, st, G,
                            c[cur], c[1 - cur], A, kap, dtM, ntx, nty, ntiles);
       else
-        hipLaunchKernelGGL((k_ch_step<2, kTX2, kTY2, 1>), dim3(ntiles), dim3(256), 0, st, G,
-                           c[cur], c[1 - cur], A, kap, dtM, ntx, nty, ntiles);
+        hipLaunchKernelGGL((k_ch_step2<kTX2, kTY2>), dim3(ntiles), dim3(256), 0, st, G, c[cur],
+                           c[1 - cur], A, kap, dtM, ntx, ntiles);
       HIP_TRY(hipGetLastError());
       cur = 1 - cur;
     }
