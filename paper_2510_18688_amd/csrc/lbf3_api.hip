@@ -221,7 +221,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
     Mom m;
     node_moments3(G, ph, B, (uint32_t)k, gv, hv, phi0, m);
     Stencil3 S;
-    stencils3(G, B, x, y, z, m.phi, m.fs, S);
+    stencils3(G, B, n, m.phi, m.fs, S);
     pull_f3(G, B, n, fv);
     const float jprev[3] = {lbf::ldp(B.lin, LAG_JX, G.P, k), lbf::ldp(B.lin, LAG_JY, G.P, k),
                             lbf::ldp(B.lin, LAG_JZ, G.P, k)};

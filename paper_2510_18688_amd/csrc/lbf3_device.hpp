@@ -218,15 +218,21 @@ struct Stencil3 {
   float gph[3], gr[3], gp[3], lphi, lfs;
 };
 
-__device__ __forceinline__ void stencils3(const Geo3& G, const Bufs3& B, int x, int y, int z,
+// The neighbour x + c_i is the pull source of direction opp(i), so the
+// pull's offsets serve the stencil; only where that link crosses a wall does
+// the stencil need its own (mirror-ghost) neighbour.
+__device__ __forceinline__ void stencils3(const Geo3& G, const Bufs3& B, const Pull19& n,
                                           float phic, float fsc, Stencil3& S) {
   float gph[3] = {0, 0, 0}, gr[3] = {0, 0, 0}, gp[3] = {0, 0, 0}, lphi = 0, lfs = 0;
 #pragma unroll
   for (int i = 1; i < NQ; ++i) {
-    const int xx = nb3(x + cx(i), G.n[0], G.per[0]);
-    const int yy = nb3(y + cy(i), G.n[1], G.per[1]);
-    const int zz = nb3(z + cz(i), G.n[2], G.per[2]);
-    const uint32_t o = (((uint32_t)zz * G.n[1] + yy) * G.n[0] + xx) * 4u;
+    uint32_t o = n.off[opp(i)];
+    if ((n.wmask >> opp(i)) & 1u) {
+      const int xx = nb3(n.x + cx(i), G.n[0], G.per[0]);
+      const int yy = nb3(n.y + cy(i), G.n[1], G.per[1]);
+      const int zz = nb3(n.z + cz(i), G.n[2], G.per[2]);
+      o = (((uint32_t)zz * G.n[1] + yy) * G.n[0] + xx) * 4u;
+    }
     const float vphi = lbf::ldo(B.mom, o, 0, G.P);
     const float vfs = lbf::ldo(B.mom, o, 1, G.P);
     const float vrho = lbf::ldo(B.mom, o, 2, G.P);
