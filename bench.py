@@ -30,12 +30,13 @@ sys.path.insert(0, ROOT)
 BYTES_PER_LU = (27 + 7) * 2 * 4 + 2 * 4
 HBM_PEAK_GBS = 8000.0
 # D3Q19, two kernels per step.  Moments pass: g and h pulled (38 planes), the
-# high parts of g_0, h_0, f_s and Q of the previous step, phi0 read; phi,
-# f_s, rho written.  Step pass: 57 distributions, 8 lagged, 3 static and the
-# 3 moment planes read; 57 distributions and 8 lagged planes written.  The
-# state itself (one pass, no moment planes) is 532 bytes per update.
-BYTES3_MOMENTS = (38 + 4 + 1) * 4 + 3 * 4
-BYTES3_STEP = (57 + 8 + 3 + 3) * 4 + (57 + 8) * 4
+# high parts of g_0, h_0, f_s, Q and p of the previous step, phi0 read; a
+# 16-byte record (phi, f_s, rho, p) written.  Step pass: 57 distributions,
+# the 7 other lagged planes, 3 static planes and the record read; 57
+# distributions and 8 lagged planes written.  The state itself (one pass, no
+# records) is 532 bytes per update.
+BYTES3_MOMENTS = (38 + 5 + 1) * 4 + 16
+BYTES3_STEP = (57 + 7 + 3) * 4 + 16 + (57 + 8) * 4
 BYTES3_STATE = (57 + 8) * 2 * 4 + 3 * 4
 # Cahn-Hilliard smoothing, per node and Euler step (one fused pass): c read
 # once and the new c written once.

@@ -49,7 +49,7 @@ Layout3 make_layout3(int nx, int ny, int nz, int pad) {
   L.lag[0] = take(NLAG * pb);
   L.lag[1] = take(NLAG * pb);
   L.stat = take(NSTAT * pb);
-  L.mom = take(3 * pb);
+  L.mom = take(4 * pb);   // 16-byte records
   L.fields = take(NFIELD * pb);
   L.red = take((size_t)L.nblocks * kRed3 * sizeof(double));
   L.redfinal = take(kRed3 * sizeof(double));
@@ -194,9 +194,7 @@ __global__ __launch_bounds__(256) void k3_moments(Geo3 G, Phys ph, BufArgs3 A, i
   pull_gh3(G, ph, B, n, gv, hv);
   Mom m;
   node_moments3(G, ph, B, (uint32_t)k, gv, hv, lbf::ldp(B.stat, ST_PHI0, G.P, k), m);
-  lbf::stp(B.mom, 0, G.P, k, m.phi);
-  lbf::stp(B.mom, 1, G.P, k, m.fs);
-  lbf::stp(B.mom, 2, G.P, k, m.rho);
+  st_rec(B.mom, (uint32_t)k * 16u, m.phi, m.fs, m.rho, lbf::ldp(B.lin, LAG_P, G.P, k));
 }
 
 // Step pass (READOUT = false) or read-out of the fields with FP64 block sums

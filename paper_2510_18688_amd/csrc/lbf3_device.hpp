@@ -66,7 +66,8 @@ struct BufArgs3 {
   const float* lin;
   float* lout;
   const float* stat;
-  float* mom;        // 3 planes: phi, f_s, rho of the state read (moments pass)
+  float* mom;        // per node a 16-byte record (phi, f_s, rho of the state read,
+                     // p of the step before), written by the moments pass
 };
 
 __device__ __forceinline__ Bufs3 make_bufs3(const BufArgs3& a, int P) {
@@ -81,7 +82,7 @@ __device__ __forceinline__ Bufs3 make_bufs3(const BufArgs3& a, int P) {
   B.lin = lbf::make_rsrc(a.lin, NLAG * pb);
   B.lout = lbf::make_rsrc(a.lout, a.lout ? NLAG * pb : 0u);
   B.stat = lbf::make_rsrc(a.stat, NSTAT * pb);
-  B.mom = lbf::make_rsrc(a.mom, 3 * pb);
+  B.mom = lbf::make_rsrc(a.mom, 4 * pb);
   return B;
 }
 
@@ -211,6 +212,28 @@ __device__ __forceinline__ int nb3(int v, int n, int periodic) {
   return v;
 }
 
+// The moments pass's record of a node: phi, f_s, rho and the lagged p.
+struct MomRec {
+  float v[4];
+};
+
+// Four dword accesses at consecutive offsets, which the compiler merges into
+// one 16-byte access.
+__device__ __forceinline__ MomRec ld_rec(Rsrc r, uint32_t off) {
+  MomRec m;
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+    m.v[c] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off + 4u * c, 0u, 0));
+  return m;
+}
+
+__device__ __forceinline__ void st_rec(Rsrc r, uint32_t off, float a, float b, float c, float d) {
+  const float v[4] = {a, b, c, d};
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v[j]), r, off + 4u * j, 0u, 0);
+}
+
 // Stencil sums of one node: gradients of phi, rho, p_prev; Laplacians of phi
 // and f_s (isotropic D3Q19 stencils: factor 3 for the gradient, 6 for the
 // Laplacian).
@@ -233,10 +256,9 @@ __device__ __forceinline__ void stencils3(const Geo3& G, const Bufs3& B, const P
       const int zz = nb3(n.z + cz(i), G.n[2], G.per[2]);
       o = (((uint32_t)zz * G.n[1] + yy) * G.n[0] + xx) * 4u;
     }
-    const float vphi = lbf::ldo(B.mom, o, 0, G.P);
-    const float vfs = lbf::ldo(B.mom, o, 1, G.P);
-    const float vrho = lbf::ldo(B.mom, o, 2, G.P);
-    const float vp = lbf::ldo(B.lin, o, LAG_P, G.P);
+    // one 16-byte record per neighbour: phi, f_s, rho, p_prev
+    const MomRec r = ld_rec(B.mom, o * 4u);
+    const float vphi = r.v[0], vfs = r.v[1], vrho = r.v[2], vp = r.v[3];
     const float w = wgt(i);
     const float c[3] = {(float)cx(i), (float)cy(i), (float)cz(i)};
 #pragma unroll
