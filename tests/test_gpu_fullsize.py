@@ -1,8 +1,8 @@
 """Parity at the benchmark sizes, in the launch configuration bench.py times
 (needs a device).
 
-Each workload runs on the GPU with the tile shape bench.py would pick (the
-autotuner's table) and on the FP64 oracle over the whole lattice, and every
+Each workload runs on the GPU with the tile shape and plane padding bench.py
+would pick (the autotuner's table) and on the FP64 oracle over the whole lattice, and every
 read-out field is compared element by element: the O(1) fields (phi, T,
 fractions, enthalpy, density) to an absolute bar, the small dynamic fields
 (u, p, mu_phi) to 1e-4 of their own scale.  The batch is checked on three
@@ -45,7 +45,7 @@ def compare(gpu, orc, tol, label):
 def run_pair(lbf, oracle_mod, case, steps):
     from paper_2510_18688_amd import autotune
     tile = autotune.lookup(case.nx, case.ny)
-    sim = lbf.Sim(case, tile=tile)
+    sim = lbf.Sim(case, tile=tile, plane_pad=autotune.lookup_pad(case.nx, case.ny))
     orc = oracle_mod.Oracle(case)
     sim.step(steps)
     orc.step(steps)

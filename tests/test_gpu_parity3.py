@@ -89,8 +89,11 @@ def test_one_step_and_few_steps(lbf_mod, O3, name):
 
 
 def test_fracture_full_size(lbf_mod, O3):
+    """The full fracture in the benchmark's configuration (its tuned plane
+    padding) after 5 steps."""
+    from paper_2510_18688_amd import autotune
     case = W3.fracture()
-    sim = lbf_mod.Sim3(case)
+    sim = lbf_mod.Sim3(case, plane_pad=autotune.lookup_pad(case.nx, case.ny, case.nz))
     orc = O3.Oracle3(case)
     sim.step(5)
     orc.step(5)
