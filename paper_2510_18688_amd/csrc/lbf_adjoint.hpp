@@ -462,26 +462,38 @@ __device__ __forceinline__ void gather_pull_adjoint(const Geo& G, const Phys& ph
                                                     float* ag, float* ah) {
   const size_t P = (size_t)G.P;
   const int k = y * G.nx + x;
+  // every lane requests the five values of each slot first (source node and
+  // plane chosen per lane, no branch around the loads), so the 45 loads are
+  // in flight together; the sums and the wall rules follow
+  float vf[9], vg[9], vsg[9], vh[9], vsh[9];
+  uint32_t wmask = 0u, ymask = 0u;
 #pragma unroll
   for (int j = 0; j < 9; ++j) {
     const int tx = pull_axis(x, -cx(j), G.nx, G.px), ty = pull_axis(y, -cy(j), G.ny, G.py);
     const bool wy = ty < 0, w = wy || tx < 0;
-    if (!w) {
-      const size_t r = (size_t)ty * G.nx + tx;
-      af[j] = lamD[j * P + r];
-      ag[j] = lamD[(9 + j) * P + r] + lamD[AD_SG * P + r];
-      ah[j] = lamD[(18 + j) * P + r] + lamD[AD_SH * P + r];
-    } else {
-      const int i = opp(j);   // the node pulls slot j back as population i
-      af[j] = lamD[i * P + k];
-      ag[j] = lamD[(9 + i) * P + k] + lamD[AD_SG * P + k];
-      const float A = lamD[(18 + i) * P + k] + lamD[AD_SH * P + k];
-      const int wall = wy ? (cy(i) > 0 ? 0 : 1) : (cx(i) > 0 ? 2 : 3);
+    wmask |= (uint32_t)w << j;
+    ymask |= (uint32_t)wy << j;
+    // across a wall the node pulls slot j back as population opp(j)
+    const size_t r = w ? (size_t)k : (size_t)ty * G.nx + tx;
+    const int pj = w ? opp(j) : j;
+    vf[j] = lamD[pj * P + r];
+    vg[j] = lamD[(9 + pj) * P + r];
+    vsg[j] = lamD[AD_SG * P + r];
+    vh[j] = lamD[(18 + pj) * P + r];
+    vsh[j] = lamD[AD_SH * P + r];
+  }
+#pragma unroll
+  for (int j = 0; j < 9; ++j) {
+    af[j] = vf[j];
+    ag[j] = vg[j] + vsg[j];
+    const float A = vh[j] + vsh[j];
+    ah[j] = A;
+    if ((wmask >> j) & 1u) {
+      const int i = opp(j);
+      const int wall = ((ymask >> j) & 1u) ? (cy(i) > 0 ? 0 : 1) : (cx(i) > 0 ? 2 : 3);
       if ((G.tmask >> wall) & 1) {
         ah[j] = -A;
         gwall[wall * wstride + (wall < 2 ? x : y)] += 2.0 * (double)wgt(i) * (double)ph.Eref * A;
-      } else {
-        ah[j] = A;
       }
     }
   }
