@@ -592,21 +592,49 @@ __global__ __launch_bounds__(256) void k_adj_gather(AdjGatherArgs a) {
   const int k = y * G.nx + x;
   const float* __restrict__ st = a.st;
   float dphi = 0.0f, dfs = 0.0f, drho = 0.0f, dp = 0.0f;
+  // contribution of one source node s through link i
+  auto add = [&](int i, size_t s) {
+    const float w = wgt(i);
+    dphi += 3.0f * w * (cx(i) * st[AS_GPHX * P + s] + cy(i) * st[AS_GPHY * P + s]) +
+            6.0f * w * st[AS_LPHI * P + s];
+    dfs += 6.0f * w * st[AS_LFS * P + s];
+    drho += 3.0f * w * (cx(i) * st[AS_GRX * P + s] + cy(i) * st[AS_GRY * P + s]);
+    dp += 3.0f * w * (cx(i) * st[AS_GPX * P + s] + cy(i) * st[AS_GPY * P + s]);
+  };
+  // first the first source of each link: one per link away from a wall,
+  // requested by every lane (a valid node either way, the term dropped where
+  // the link has none), so these loads are in flight together; then, in a
+  // separate pass, the mirror-ghost sources that only boundary nodes have
+  int vx[9][2], vy[9][2], nxs[9], nys[9];
 #pragma unroll
   for (int i = 1; i < 9; ++i) {
-    int vx[2], vy[2];
-    const int nxs = stencil_sources(x, cx(i), G.nx, G.px, vx);
-    const int nys = stencil_sources(y, cy(i), G.ny, G.py, vy);
-    const float w = wgt(i);
-    for (int b = 0; b < nys; ++b)
-      for (int c = 0; c < nxs; ++c) {
-        const size_t s = (size_t)vy[b] * G.nx + vx[c];
-        dphi += 3.0f * w * (cx(i) * st[AS_GPHX * P + s] + cy(i) * st[AS_GPHY * P + s]) +
-                6.0f * w * st[AS_LPHI * P + s];
-        dfs += 6.0f * w * st[AS_LFS * P + s];
-        drho += 3.0f * w * (cx(i) * st[AS_GRX * P + s] + cy(i) * st[AS_GRY * P + s]);
-        dp += 3.0f * w * (cx(i) * st[AS_GPX * P + s] + cy(i) * st[AS_GPY * P + s]);
-      }
+    nxs[i] = stencil_sources(x, cx(i), G.nx, G.px, vx[i]);
+    nys[i] = stencil_sources(y, cy(i), G.ny, G.py, vy[i]);
+  }
+  float t8[9][8];
+#pragma unroll
+  for (int i = 1; i < 9; ++i) {
+    const size_t s = (size_t)(nys[i] > 0 ? vy[i][0] : y) * G.nx + (nxs[i] > 0 ? vx[i][0] : x);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) t8[i][q] = st[q * P + s];
+  }
+#pragma unroll
+  for (int i = 1; i < 9; ++i) {
+    if (nxs[i] > 0 && nys[i] > 0) {
+      const float w = wgt(i);
+      dphi += 3.0f * w * (cx(i) * t8[i][AS_GPHX] + cy(i) * t8[i][AS_GPHY]) + 6.0f * w * t8[i][AS_LPHI];
+      dfs += 6.0f * w * t8[i][AS_LFS];
+      drho += 3.0f * w * (cx(i) * t8[i][AS_GRX] + cy(i) * t8[i][AS_GRY]);
+      dp += 3.0f * w * (cx(i) * t8[i][AS_GPX] + cy(i) * t8[i][AS_GPY]);
+    }
+  }
+#pragma unroll
+  for (int i = 1; i < 9; ++i) {
+    if (nxs[i] > 1 || nys[i] > 1) {
+      for (int b = 0; b < nys[i]; ++b)
+        for (int c = 0; c < nxs[i]; ++c)
+          if (b > 0 || c > 0) add(i, (size_t)vy[i][b] * G.nx + vx[i][c]);
+    }
   }
   // the node's own value in its Laplacians (weights of the moving links: 5/9)
   dphi -= 6.0f * (5.0f / 9.0f) * st[AS_LPHI * P + k];
