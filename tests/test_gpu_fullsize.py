@@ -66,6 +66,15 @@ def test_benchmark_lattice_against_oracle(lbf_mod, oracle_mod, make):
         assert abs(r[k] - ro[k]) <= 1e-6 * max(abs(ro[k]), 1.0), (k, r[k], ro[k])
 
 
+def test_headline_lattice_1000_steps(lbf_mod, oracle_mod):
+    """The 2048 x 2048 workload in the benchmark's configuration over 1000
+    steps: no drift from the oracle at full size."""
+    case = W.curved_substrate()
+    sim, orc, tile = run_pair(lbf_mod, oracle_mod, case, 1000)
+    worst = compare(sim.fields(), orc.fields(), 2e-5, f"{case.name} step 1000")
+    assert worst["phi"] <= 2e-5 and worst["fl"] <= 2e-5
+
+
 def test_batched_lattices_against_oracle(lbf_mod, oracle_mod):
     from paper_2510_18688_amd import autotune
     cases = W.batch_instances(64, seed=4)
