@@ -90,7 +90,7 @@ def test_one_step_and_few_steps(lbf_mod, O3, name):
 
 def test_fracture_full_size(lbf_mod, O3):
     """The full fracture in the benchmark's configuration (its tuned plane
-    padding) after 5 steps."""
+    padding) after 5 steps, and the freezing fields after 300."""
     from paper_2510_18688_amd import autotune
     case = W3.fracture()
     sim = lbf_mod.Sim3(case, plane_pad=autotune.lookup_pad(case.nx, case.ny, case.nz))
@@ -98,6 +98,10 @@ def test_fracture_full_size(lbf_mod, O3):
     sim.step(5)
     orc.step(5)
     compare(sim.fields(), orc.fields(), 2e-5, "fracture 256x128x30 step 5")
+    sim.step(295)
+    orc.step(295)
+    compare(sim.fields(), orc.fields(), 5e-5, "fracture 256x128x30 step 300",
+            ["phi", "T", "fl", "fs", "rhoH", "C", "chi", "rho"])
 
 
 @pytest.mark.parametrize("shape", [(1, 1, 1), (5, 1, 3), (1, 4, 1), (3, 2, 7)])
