@@ -66,12 +66,14 @@ def test_benchmark_lattice_against_oracle(lbf_mod, oracle_mod, make):
         assert abs(r[k] - ro[k]) <= 1e-6 * max(abs(ro[k]), 1.0), (k, r[k], ro[k])
 
 
-def test_headline_lattice_1000_steps(lbf_mod, oracle_mod):
-    """The 2048 x 2048 workload in the benchmark's configuration over 1000
+@pytest.mark.parametrize("make, steps", [(W.curved_substrate, 1000), (W.porous_medium, 200)],
+                         ids=["curved_substrate_2048x2048_1000", "porous_4096x2048_200"])
+def test_long_run_full_size(lbf_mod, oracle_mod, make, steps):
+    """The benchmark workloads in the benchmark's configuration over many
     steps: no drift from the oracle at full size."""
-    case = W.curved_substrate()
-    sim, orc, tile = run_pair(lbf_mod, oracle_mod, case, 1000)
-    worst = compare(sim.fields(), orc.fields(), 2e-5, f"{case.name} step 1000")
+    case = make()
+    sim, orc, tile = run_pair(lbf_mod, oracle_mod, case, steps)
+    worst = compare(sim.fields(), orc.fields(), 2e-5, f"{case.name} step {steps}")
     assert worst["phi"] <= 2e-5 and worst["fl"] <= 2e-5
 
 
