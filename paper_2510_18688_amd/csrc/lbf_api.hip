@@ -874,18 +874,17 @@ int lbf_batch_step(lbf_batch* b, int32_t nsteps) {
   if (nsteps >= kGraphSteps) {
     if (!b->have_graph) {
       // one graph of kGraphSteps persistent launches, parities alternating
-      hipGraph_t g;
+      hipGraph_t g = nullptr;
       HIP_TRY(hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal));
-      for (int k = 0; k < kGraphSteps; ++k) {
-        int rc = batch_launch(b, k & 1, b->capture);
-        if (rc) {
-          (void)hipStreamEndCapture(b->capture, &g);
-          return rc;
-        }
-      }
-      HIP_TRY(hipStreamEndCapture(b->capture, &g));
-      HIP_TRY(hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0));
-      HIP_TRY(hipGraphDestroy(g));
+      int rc = LBF_OK;
+      for (int k = 0; k < kGraphSteps && rc == LBF_OK; ++k) rc = batch_launch(b, k & 1, b->capture);
+      const hipError_t ec = hipStreamEndCapture(b->capture, &g);
+      if (rc == LBF_OK && ec != hipSuccess)
+        rc = fail(LBF_EHIP, "hipStreamEndCapture failed: %s", hipGetErrorString(ec));
+      if (rc == LBF_OK && hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0) != hipSuccess)
+        rc = fail(LBF_EHIP, "hipGraphInstantiate failed");
+      if (g) (void)hipGraphDestroy(g);   // the executable graph keeps its own copy
+      if (rc) return rc;
       b->have_graph = true;
     }
     // kGraphSteps is even: each replay leaves every parity where it started
