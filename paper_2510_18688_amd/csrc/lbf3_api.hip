@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <new>
 
 #include "lbf3.h"
 #include "lbf3_device.hpp"
@@ -441,7 +442,8 @@ int lbf3_create(const lbf3_params* params, void* stream, void* workspace, size_t
   *out = nullptr;
   int rc = validate3(params);
   if (rc) return rc;
-  lbf3_sim* s = new lbf3_sim();
+  lbf3_sim* s = new (std::nothrow) lbf3_sim();
+  if (!s) return fail(LBF_ENOMEM, "host allocation failed");
   s->prm = *params;
   s->G.n[0] = params->nx; s->G.n[1] = params->ny; s->G.n[2] = params->nz;
   s->G.tmask = 0;

@@ -14,6 +14,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <new>
 
 #include "lbf.h"
 #include "lbf_adjoint.hpp"
@@ -173,7 +174,8 @@ int lbf_tape_create(lbf_sim* sim, int32_t nsteps, int32_t segment, lbf_tape** ou
     return fail(LBF_EINVAL, "the adjoint supports grav = u_solid = 0 only");
   if (nsteps < 0) return fail(LBF_EINVAL, "nsteps %d", nsteps);
   if (segment < 0) return fail(LBF_EINVAL, "segment %d", segment);
-  lbf_tape* t = new lbf_tape();
+  lbf_tape* t = new (std::nothrow) lbf_tape();
+  if (!t) return fail(LBF_ENOMEM, "host allocation failed");
   t->sim = sim;
   t->nsteps = nsteps;
   t->seg = segment > 0 ? std::min<int>(segment, std::max(nsteps, 1)) : default_segment(nsteps);

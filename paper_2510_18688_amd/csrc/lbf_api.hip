@@ -6,7 +6,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
-#include <string>
+#include <new>
 #include <vector>
 
 #include "lbf.h"
@@ -18,15 +18,13 @@ using namespace lbf;
 
 namespace lbfi {
 
-thread_local std::string g_err;
+thread_local char g_err[512];
 
 int fail(int code, const char* fmt, ...) {
-  char buf[512];
   va_list ap;
   va_start(ap, fmt);
-  vsnprintf(buf, sizeof buf, fmt, ap);
+  vsnprintf(g_err, sizeof g_err, fmt, ap);
   va_end(ap);
-  g_err = buf;
   return code;
 }
 
@@ -348,7 +346,7 @@ int copy_in(lbf_sim* s, void* dst, const void* src, size_t bytes, int on_device)
 // ================================================================ C ABI
 extern "C" {
 
-const char* lbf_last_error(void) { return g_err.c_str(); }
+const char* lbf_last_error(void) { return g_err; }
 
 size_t lbf_workspace_bytes(int32_t nx, int32_t ny, int32_t plane_pad) {
   if (nx < 1 || ny < 1 || plane_pad < 0 || plane_pad > kMaxPlanePad || plane_pad % 64) return 0;
@@ -362,7 +360,8 @@ int lbf_create(const lbf_params* params, void* stream, void* workspace, size_t w
   *out = nullptr;
   int rc = validate(params);
   if (rc) return rc;
-  lbf_sim* s = new lbf_sim();
+  lbf_sim* s = new (std::nothrow) lbf_sim();
+  if (!s) return fail(LBF_ENOMEM, "host allocation failed");
   s->prm = *params;
   s->G.nx = params->nx;
   s->G.ny = params->ny;
@@ -728,11 +727,12 @@ int batch_upload_desc(lbf_batch* b) {
     }
     d.CY = b->tile_y;
     d.nbx = (s->G.nx + b->tile_x - 1) / b->tile_x;
-    b->desc_cur[i] = s->cur;
   }
   HIP_TRY(hipMemcpyAsync(b->d_desc, b->h_desc.data(), n * sizeof(InstDesc),
                          hipMemcpyHostToDevice, b->stream));
   HIP_TRY(hipStreamSynchronize(b->stream));
+  // recorded only once the device copy is in place
+  for (int i = 0; i < n; ++i) b->desc_cur[i] = b->sims[i]->cur;
   return LBF_OK;
 }
 
@@ -827,9 +827,15 @@ int lbf_batch_create(lbf_sim* const* sims, int32_t n, lbf_batch** out) {
     for (int j = 0; j < i; ++j)
       if (sims[j] == sims[i]) return fail(LBF_EINVAL, "simulation %d appears twice", i);
   }
-  lbf_batch* b = new lbf_batch();
-  b->sims.assign(sims, sims + n);
-  b->desc_cur.assign(n, -1);
+  lbf_batch* b = new (std::nothrow) lbf_batch();
+  if (!b) return fail(LBF_ENOMEM, "host allocation failed");
+  try {
+    b->sims.assign(sims, sims + n);
+    b->desc_cur.assign(n, -1);
+  } catch (const std::bad_alloc&) {
+    delete b;
+    return fail(LBF_ENOMEM, "host allocation failed");
+  }
   b->stream = sims[0]->stream;
   b->tile_x = 128;
   b->tile_y = 32;
@@ -858,16 +864,20 @@ int lbf_batch_step(lbf_batch* b, int32_t nsteps) {
   if (!b) return fail(LBF_EINVAL, "batch is NULL");
   if (nsteps < 0) return fail(LBF_EINVAL, "nsteps %d", nsteps);
   if (nsteps == 0) return LBF_OK;
-  if (!b->built) {
-    int rc = batch_build(b);
-    if (rc) return rc;
-  } else {
-    for (size_t i = 0; i < b->sims.size(); ++i)
-      if (b->sims[i]->cur != b->desc_cur[i]) {
-        int rc = batch_upload_desc(b);
-        if (rc) return rc;
-        break;
-      }
+  try {   // the work-item list and descriptors are built in host vectors
+    if (!b->built) {
+      int rc = batch_build(b);
+      if (rc) return rc;
+    } else {
+      for (size_t i = 0; i < b->sims.size(); ++i)
+        if (b->sims[i]->cur != b->desc_cur[i]) {
+          int rc = batch_upload_desc(b);
+          if (rc) return rc;
+          break;
+        }
+    }
+  } catch (const std::bad_alloc&) {
+    return fail(LBF_ENOMEM, "host allocation failed");
   }
   if (b->timing) HIP_TRY(hipEventRecord(b->ev0, b->stream));
   int done = 0;
