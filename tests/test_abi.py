@@ -224,3 +224,25 @@ def test_ch_invalid_params_rejected_on_host(L, change, needle):
     assert L.lbf_ch_workspace_bytes(0, 1, 1) == 0
     assert L.lbf_ch_workspace_bytes(65536, 65536, 1) == 0
     assert L.lbf_ch_workspace_bytes(10, 10, 1) == 2 * 512
+
+
+def test_last_error_is_per_thread(L):
+    """lbf_last_error() reports the calling thread's last failure: a failure
+    in another thread leaves this thread's text unchanged."""
+    import threading
+    case = W.sessile_drop(nx=16, ny=8)
+    case.nx = 0
+    rc, msg = _create_rc(L, case)
+    assert rc == -1 and "lattice size" in msg
+    other = {}
+
+    def worker():
+        c2 = W.sessile_drop(nx=16, ny=8)
+        c2.mat.pcm_floor = 1.0
+        other["rc"], other["msg"] = _create_rc(L, c2)
+
+    t = threading.Thread(target=worker)
+    t.start()
+    t.join()
+    assert other["rc"] == -1 and "pcm_floor" in other["msg"]
+    assert "lattice size" in L.lbf_last_error().decode()
