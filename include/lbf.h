@@ -116,7 +116,13 @@ typedef struct lbf_params {
    * stands for the BGK rate (mrt = 1 with all three 0 is BGK).  Rates in
    * [0, 2).  The adjoint (lbf_tape_*) supports BGK only. */
   int32_t mrt;
-  int32_t reserved2;
+  /* Stability check of lbf_step: with check_every = k > 0, every step that
+   * starts at a time level divisible by k also forms the FP64 reduction of
+   * the state it reads, and lbf_step returns LBF_EUNSTABLE right after that
+   * step (which has run) when the state held a non-finite phi, T, u or p or
+   * max |u| > 0.3.  Each check waits for the stream once.  0: no checks
+   * (lbf_step stays fully asynchronous). */
+  int32_t check_every;
   double s_b, s_q, s_g;
   /* Body force G = rho * grav (a uniform acceleration acting on the local
    * density) and the solid-phase velocity u_s of the drag f_s (u_s - u*)
@@ -171,7 +177,10 @@ int lbf_set_poststream_state(lbf_sim* sim, const float* dist, const float* lag, 
                              int32_t on_device);
 
 /* Advance nsteps coupled time steps (nsteps >= 0).  Asynchronous on the
- * simulation's stream. */
+ * simulation's stream, except for the stability checks that
+ * lbf_params.check_every asks for: LBF_EUNSTABLE (message naming the time
+ * level) when one fails; the steps up to and including the checking step
+ * have then been taken and the simulation's step count says so. */
 int lbf_step(lbf_sim* sim, int32_t nsteps);
 
 /* Compute one read-out field (LBF_FIELD_*) of the current state into dst
@@ -261,7 +270,8 @@ int lbf_batch_set_tile(lbf_batch* batch, int32_t tile_x, int32_t tile_y);
 
 /* Advance every lattice of the batch by nsteps (asynchronous unless timing
  * is on).  A simulation stepped on its own in between is picked up at its
- * current state. */
+ * current state; LBF_ESTATE if a simulation has lost its state since (new
+ * geometry without lbf_init_fields or a loaded state). */
 int lbf_batch_step(lbf_batch* batch, int32_t nsteps);
 
 /* With timing on, lbf_batch_step brackets its launches with HIP events and

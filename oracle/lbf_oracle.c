@@ -408,6 +408,13 @@ static double chem_pot(const orc_params* p, double phi, double lap_phi, double p
   return m;
 }
 
+/* Exported for the pins: mu_phi of one node from its values and the three
+ * Laplacians. */
+double orc_chem_pot(const orc_params* p, double phi, double lap_phi, double phi0, double cth,
+                    double lap_phi0, double fs, double lap_fs) {
+  return chem_pot(p, phi, lap_phi, phi0, cth, lap_phi0, fs, lap_fs);
+}
+
 /* -------------------------------------------------------- pass 1 */
 /* Node-local moments (O1-O6 of the design notes). */
 static void pass1(orc_sim* s) {

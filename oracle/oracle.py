@@ -76,6 +76,8 @@ def lib():
         L.orc_forcing.argtypes = [C.c_double] * 9 + [dp]
         L.orc_hmap.argtypes = [C.POINTER(OrcParams)] + [C.c_double] * 4 + [dp]
         L.orc_stencil.argtypes = [C.c_int] * 4 + [dp, dp, dp, dp]
+        L.orc_chem_pot.restype = C.c_double
+        L.orc_chem_pot.argtypes = [C.POINTER(OrcParams)] + [C.c_double] * 7
         L.orc_set_threads.argtypes = [C.c_int]
         L.orc_max_threads.restype = C.c_int
         L.orc_set_store_f32.argtypes = [C.c_void_p, C.c_int]
@@ -215,6 +217,12 @@ def hmap(case, rhoH, phi0, Cw, chi):
     p = make_params(case)
     lib().orc_hmap(C.byref(p), rhoH, phi0, Cw, chi, _ptr(out))
     return dict(T=out[0], fl=out[1], Ksol=out[2], Kliq=out[3])
+
+
+def chem_pot(case, phi, lap_phi, phi0, cth, lap_phi0, fs, lap_fs) -> float:
+    """mu_phi of one node (the oracle's chemical potential)."""
+    p = make_params(case)
+    return float(lib().orc_chem_pot(C.byref(p), phi, lap_phi, phi0, cth, lap_phi0, fs, lap_fs))
 
 
 def stencil(X: np.ndarray, periodic_x: bool, periodic_y: bool):

@@ -102,6 +102,7 @@ int validate(const lbf_params* p) {
     if (p->thermal_bc[w] != LBF_ADIABATIC && p->thermal_bc[w] != LBF_DIRICHLET)
       return fail(LBF_EINVAL, "thermal_bc[%d] = %d", w, p->thermal_bc[w]);
   if (p->mrt != 0 && p->mrt != 1) return fail(LBF_EINVAL, "mrt = %d", p->mrt);
+  if (p->check_every < 0) return fail(LBF_EINVAL, "check_every = %d", p->check_every);
   for (int a = 0; a < 2; ++a)
     if (!std::isfinite(p->grav[a]) || !std::isfinite(p->u_solid[a]))
       return fail(LBF_EINVAL, "grav and u_solid must be finite");
@@ -341,6 +342,26 @@ int copy_in(lbf_sim* s, void* dst, const void* src, size_t bytes, int on_device)
   return LBF_OK;
 }
 
+// Stability check of lbf_step: fixed-order sum of the partials a step wrote
+// for the state it read (time level `level`), then non-finite count and
+// max |u| on the host.
+int check_stable(lbf_sim* s, const double* part, long long level) {
+  dim3 grid;
+  const int nb = grid_blocks(s, grid);
+  double* fin = dptr(s, s->L.redfinal) + NRED;
+  hipLaunchKernelGGL(k_reduce_blocks, dim3(1), dim3(256), 0, s->stream, part, nb, fin);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(s->host_red + NRED, fin, NRED * sizeof(double), hipMemcpyDeviceToHost,
+                         s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  const double bad = s->host_red[NRED + LBF_RED_NONFINITE];
+  const double umax = s->host_red[NRED + LBF_RED_UMAX];
+  if (bad > 0 || !(umax <= 0.3))
+    return fail(LBF_EUNSTABLE, "unstable at time level %lld: %g non-finite nodes, max |u| = %g",
+                level, bad, umax);
+  return LBF_OK;
+}
+
 }  // namespace
 
 // ================================================================ C ABI
@@ -508,12 +529,25 @@ int lbf_step(lbf_sim* s, int32_t nsteps) {
   if (!s->have_init) return fail(LBF_ESTATE, "lbf_init_fields must precede lbf_step");
   if (nsteps == 0) return LBF_OK;
   if (s->timing) HIP_TRY(hipEventRecord(s->ev0, s->stream));
+  const int k = s->prm.check_every;
   for (int it = 0; it < nsteps; ++it) {
     const bool last = it == nsteps - 1;
-    int rc = launch_step(s, MODE_STEP, last, last ? dptr(s, s->L.red[0]) : nullptr);
+    // a checking step reduces the state it reads (time level s->step)
+    const bool chk = k > 0 && s->step % k == 0;
+    double* rb = last ? dptr(s, s->L.red[0]) : (chk ? dptr(s, s->L.red[1]) : nullptr);
+    int rc = launch_step(s, MODE_STEP, last || chk, rb);
     if (rc) return rc;
     s->cur = 1 - s->cur;
     s->step++;
+    if (chk) {
+      rc = check_stable(s, rb, s->step - 1);
+      if (rc) {
+        dim3 grid;
+        s->budget_blocks = grid_blocks(s, grid);
+        s->have_budget = last;
+        return rc;
+      }
+    }
   }
   if (s->timing) {
     HIP_TRY(hipEventRecord(s->ev1, s->stream));
@@ -864,6 +898,10 @@ int lbf_batch_step(lbf_batch* b, int32_t nsteps) {
   if (!b) return fail(LBF_EINVAL, "batch is NULL");
   if (nsteps < 0) return fail(LBF_EINVAL, "nsteps %d", nsteps);
   if (nsteps == 0) return LBF_OK;
+  for (size_t i = 0; i < b->sims.size(); ++i)
+    if (!b->sims[i]->have_init)
+      return fail(LBF_ESTATE, "simulation %zu of the batch has no state (new geometry without "
+                              "lbf_init_fields or a loaded state)", i);
   try {   // the work-item list and descriptors are built in host vectors
     if (!b->built) {
       int rc = batch_build(b);

@@ -55,7 +55,7 @@ class Params(C.Structure):
             "rho_l", "rho_g", "rho_s", "mu_l", "mu_g", "mu_s", "lam_l", "lam_g", "lam_s",
             "cp_l", "cp_g", "cp_s", "latent", "T_m", "sigma", "eps", "mobility", "cos_psi",
             "rho_ref", "T_substrate", "pcm_floor")] + [
-        ("mrt", C.c_int32), ("reserved2", C.c_int32), ("s_b", C.c_double), ("s_q", C.c_double),
+        ("mrt", C.c_int32), ("check_every", C.c_int32), ("s_b", C.c_double), ("s_q", C.c_double),
         ("s_g", C.c_double), ("grav", C.c_double * 2), ("u_solid", C.c_double * 2)]
 
 
@@ -165,16 +165,20 @@ class Sim:
     `tile` is the launch shape (threads along x, rows per block) and
     `plane_pad` the padding between workspace planes in floats (a multiple
     of 64); both change speed only, and `autotune.lookup` /
-    `autotune.lookup_pad` return the tuned values for a lattice size."""
+    `autotune.lookup_pad` return the tuned values for a lattice size.
+    `check_every`: `step` raises LbfError(LBF_EUNSTABLE) after a step that
+    starts at a time level divisible by it found a non-finite or too fast
+    state (0: no checks)."""
 
     def __init__(self, case, tile: Optional[Sequence[int]] = None, device: str = "cuda",
-                 stream=None, plane_pad: int = 0):
+                 stream=None, plane_pad: int = 0, check_every: int = 1000):
         torch = _torch()
         L = load()
         self.case = case
         self.nx, self.ny = case.nx, case.ny
         self.params = make_params(case)
         self.params.plane_pad = int(plane_pad)
+        self.params.check_every = int(check_every)
         self.device = torch.device(device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         nbytes = L.lbf_workspace_bytes(self.nx, self.ny, self.params.plane_pad)
@@ -297,11 +301,24 @@ class Sim:
     def state_bytes(self) -> int:
         return int(_lib.lbf_state_bytes(self.h))
 
+    def _state_buffer(self, buf):
+        """Pointer and size of a checkpoint buffer: contiguous device memory of
+        at least state_bytes() bytes (the library copies device to device)."""
+        import torch
+        if not isinstance(buf, torch.Tensor) or buf.device.type != "cuda" or not buf.is_contiguous():
+            raise LbfError(-1, "a state buffer must be a contiguous tensor in device memory")
+        nbytes = buf.numel() * buf.element_size()
+        if nbytes < self.state_bytes():
+            raise LbfError(-5, f"state buffer of {nbytes} bytes, {self.state_bytes()} needed")
+        return C.c_void_p(buf.data_ptr()), nbytes
+
     def save_state(self, buf) -> None:
-        check(_lib.lbf_save_state(self.h, C.c_void_p(buf.data_ptr()), buf.numel() * buf.element_size()))
+        ptr, nbytes = self._state_buffer(buf)
+        check(_lib.lbf_save_state(self.h, ptr, nbytes))
 
     def load_state(self, buf) -> None:
-        check(_lib.lbf_load_state(self.h, C.c_void_p(buf.data_ptr()), buf.numel() * buf.element_size()))
+        ptr, nbytes = self._state_buffer(buf)
+        check(_lib.lbf_load_state(self.h, ptr, nbytes))
 
 
 class Batch:
@@ -575,10 +592,12 @@ class Sim3:
         return int(_lib.lbf3_state_bytes(self.h))
 
     def save_state(self, buf) -> None:
-        check(_lib.lbf3_save_state(self.h, C.c_void_p(buf.data_ptr()), buf.numel() * buf.element_size()))
+        ptr, nbytes = Sim._state_buffer(self, buf)
+        check(_lib.lbf3_save_state(self.h, ptr, nbytes))
 
     def load_state(self, buf) -> None:
-        check(_lib.lbf3_load_state(self.h, C.c_void_p(buf.data_ptr()), buf.numel() * buf.element_size()))
+        ptr, nbytes = Sim._state_buffer(self, buf)
+        check(_lib.lbf3_load_state(self.h, ptr, nbytes))
 
     def set_strip(self, rows: int) -> None:
         """Rows per strip of the step kernel's node order (>= ny: x-fastest)."""

@@ -45,10 +45,10 @@ def test_exports_every_declared_symbol(L):
 def test_params_layout_matches_header(tmp_path):
     src = tmp_path / "sz.c"
     src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "lbf.h"\n'
-                   'int main(void){printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(lbf_params),'
+                   'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu\\n", sizeof(lbf_params),'
                    ' offsetof(lbf_params, rho_l), offsetof(lbf_params, T_substrate),'
                    ' offsetof(lbf_params, thermal_bc), offsetof(lbf_params, mrt),'
-                   ' offsetof(lbf_params, s_q));return 0;}\n')
+                   ' offsetof(lbf_params, s_q), offsetof(lbf_params, check_every));return 0;}\n')
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()
@@ -58,6 +58,7 @@ def test_params_layout_matches_header(tmp_path):
     assert int(out[2]) == P.T_substrate.offset
     assert int(out[3]) == P.thermal_bc.offset
     assert int(out[4]) == P.mrt.offset and int(out[5]) == P.s_q.offset
+    assert int(out[6]) == P.check_every.offset
 
 
 def test_params3_layout_matches_header(tmp_path):
@@ -90,6 +91,7 @@ def test_workspace_bytes(L):
 
 def _create_rc(L, case):
     p = lbf.make_params(case)
+    p.check_every = getattr(case, "check_every", 0)
     h = C.c_void_p()
     rc = L.lbf_create(C.byref(p), None, None, 0, C.byref(h))
     return rc, L.lbf_last_error().decode()
@@ -107,6 +109,7 @@ def _create_rc(L, case):
     (lambda c: setattr(c.mat, "mrt", 2), "mrt = 2"),
     (lambda c: (setattr(c.mat, "mrt", 1), setattr(c.mat, "s_g", 2.5)), "MRT rates"),
     (lambda c: setattr(c.mat, "g_x", float("nan")), "finite"),
+    (lambda c: setattr(c, "check_every", -1), "check_every"),
 ])
 def test_invalid_params_rejected_on_host(L, mutate, needle):
     case = W.sessile_drop(nx=16, ny=8)

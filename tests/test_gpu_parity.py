@@ -242,6 +242,70 @@ def test_errors_from_device_path(lbf_mod):
         sim.reduce()
 
 
+def test_step_reports_instability(lbf_mod):
+    """With check_every = k, lbf_step itself returns LBF_EUNSTABLE after the
+    step that starts at the first time level divisible by k that holds a
+    non-finite node; the steps before it ran and are counted."""
+    case = W.sessile_drop(nx=32, ny=16)
+    phi = case.phi.copy()
+    phi[5, 5] = np.nan
+    for k, taken in ((1, 1), (4, 1)):
+        sim = lbf_mod.Sim(case, check_every=k)
+        sim.init_fields(phi, case.T)
+        with pytest.raises(lbf_mod.LbfError, match="UNSTABLE.*time level 0"):
+            sim.step(10)
+        assert sim.reduce(check_stable=False)["step"] == taken
+    # a bad state loaded at time level 5 is caught at level 6, the next
+    # multiple of 3, after the step that starts there
+    sim = lbf_mod.Sim(case, check_every=3)
+    z = np.zeros((9, case.ny, case.nx), dtype=np.float32)
+    f = z.copy()
+    f[0, 5, 5] = np.nan
+    sim.set_poststream_state(f, z, z, np.zeros((5, case.ny, case.nx), np.float32), step=5)
+    with pytest.raises(lbf_mod.LbfError, match="time level 6"):
+        sim.step(5)
+    assert sim.reduce(check_stable=False)["step"] == 7
+    # no checks: the run goes on and only an explicit reduction reports it
+    sim = lbf_mod.Sim(case, check_every=0)
+    sim.init_fields(phi, case.T)
+    sim.step(10)
+    with pytest.raises(lbf_mod.LbfError, match="UNSTABLE"):
+        sim.reduce()
+    # a healthy run passes every check and matches an unchecked run bit for bit
+    a = lbf_mod.Sim(case, check_every=1)
+    b = lbf_mod.Sim(case, check_every=0)
+    a.step(12)
+    b.step(12)
+    fa, fb = a.fields(), b.fields()
+    for kname in FIELDS:
+        assert np.array_equal(fa[kname], fb[kname]), kname
+    assert a.reduce() == b.reduce()
+
+
+def test_state_buffers_must_be_device_memory(lbf_mod):
+    import torch
+    case = W.sessile_drop(nx=32, ny=16)
+    sim = lbf_mod.Sim(case)
+    with pytest.raises(lbf_mod.LbfError, match="device memory"):
+        sim.save_state(torch.empty(sim.state_bytes(), dtype=torch.uint8))
+    with pytest.raises(lbf_mod.LbfError, match="device memory"):
+        sim.load_state(np.zeros(sim.state_bytes(), dtype=np.uint8))
+    with pytest.raises(lbf_mod.LbfError, match="ENOMEM"):
+        sim.save_state(torch.empty(sim.state_bytes() - 1, dtype=torch.uint8, device="cuda"))
+
+
+def test_batch_refuses_a_member_without_state(lbf_mod):
+    case = W.sessile_drop(nx=32, ny=16)
+    a, b = lbf_mod.Sim(case), lbf_mod.Sim(case)
+    batch = lbf_mod.Batch([a, b])
+    batch.step(2)
+    b.set_geometry(case.phi0, case.cos_theta)   # drops b's state
+    with pytest.raises(lbf_mod.LbfError, match="ESTATE"):
+        batch.step(1)
+    b.init_fields(case.phi, case.T)
+    batch.step(1)
+
+
 @pytest.mark.parametrize("steps", [1500, 4000])
 def test_one_step_from_developed_oracle_state(lbf_mod, oracle_mod, steps):
     """One step from the oracle's own state deep into the freezing run: the

@@ -278,3 +278,94 @@ def test_volume_change_sign(oracle_mod):
         j = np.where(col > 0)[0].max()
         tops[rr] = j + col[j] / (col[j] - col[j + 1])
     assert tops[0.8] > 20.5 > tops[1.25]
+
+
+@pytest.mark.parametrize("T_sub", [-1.0, 0.6])
+def test_held_region_reads_its_temperature(oracle_mod, T_sub):
+    """Nodes with phi0 >= 1/2 are held at T_substrate (R21): the reset puts
+    them at the equilibrium of the enthalpy that the enthalpy map inverts to
+    T_substrate -- frozen phase-change material below T_m, liquid above.
+
+    (a) A lattice held everywhere, with phase-change material in every node
+    (phi0 = 0.6, chi = 0.4 > 0, so the frozen and liquid heat capacities
+    differ): a uniform state streams onto itself, so after the lagged mass
+    source has died out (two steps) every node reads T_substrate, and its
+    ice fraction is chi below T_m and 0 above.
+    (b) The cold-cylinder workload: every node inside the cylinder whose
+    whole 3 x 3 neighbourhood is held and that holds no phase-change
+    material reads T_substrate (to the creep of its heat capacity)."""
+    mat = W.Material()
+    n = 6
+    z = np.zeros((n, n))
+    case = W.Case("held", n, n, True, True, [0, 0, 0, 0], {}, np.full((n, n), 0.6),
+                  np.full((n, n), 0.3), np.ones((n, n)), np.zeros((n, n)), mat,
+                  substrate_fixed=True, T_substrate=T_sub)
+    o = oracle_mod.Oracle(case)
+    o.step(5)
+    F = o.fields()
+    assert np.abs(F["chi"] - 0.4).max() < 1e-15
+    assert np.abs(F["T"] - T_sub).max() <= 1e-12, F["T"]
+    assert np.abs(F["fs"] - (0.4 if T_sub < mat.T_m else 0.0)).max() < 1e-12
+    del z
+
+    case = W.curved_substrate(n=96, R_s=20.0, R_0=15.0, T_sub=T_sub)
+    o = oracle_mod.Oracle(case)
+    o.step(30)
+    F = o.fields()
+    held = case.phi0 >= 0.5
+    inner = held.copy()
+    for dy in (-1, 0, 1):
+        for dx in (-1, 0, 1):
+            inner &= np.roll(held, (dy, dx), axis=(0, 1))
+    # nodes with phase-change material see the lagged mass source of their
+    # own ice (case (a) covers them once it has died out)
+    inner &= F["chi"] == 0.0
+    assert inner.sum() > 500
+    # the held enthalpy was formed with the heat capacity of the previous
+    # step's liquid weight; where phi still creeps inside the diffuse solid
+    # the capacity, and so the temperature read back, moves by ~1e-6
+    assert np.abs(F["T"][inner] - T_sub).max() <= 1e-5
+    # outside the held region the temperature is free (the drop is at 0)
+    assert np.abs(F["T"][~held] - T_sub).max() > 0.1
+
+
+def _cap_case(theta, area, nx=112, ny=48, h_s=8.0, mat=None):
+    """Drop of liquid area `area` resting on a cold slab as the circular cap
+    with contact angle theta (circle centre h_s - R cos(theta) above the
+    wall, R from the cap area R^2 (theta - sin theta cos theta))."""
+    mat = mat or W.Material()
+    t = math.radians(theta)
+    R = math.sqrt(area / (t - math.sin(t) * math.cos(t)))
+    case = W.slab_drop(nx, ny, 1.0, theta, -1.0, h_s=h_s, mat=mat)
+    y, x = np.mgrid[0:ny, 0:nx].astype(float)
+    r = np.hypot(x - nx / 2.0, y - (h_s - R * math.cos(t)))
+    case.phi = (1.0 - case.phi0) * np.tanh(2.0 * (R - r) / mat.eps)
+    return case
+
+
+def test_smaller_contact_angle_freezes_faster(oracle_mod):
+    """Sec. 4.6 (Fig. 13): the more the liquid wets the cold solid, the
+    faster it freezes.  Two drops of equal area on a cold slab, each set at
+    the cap of its own contact angle (60 and 120 degrees; the wetting terms
+    hold that shape): the flatter, wetting one has the larger ice fraction
+    of its phase-change material at every time.  And the freezing rate falls
+    as the front moves away from the cold wall (Fig. 13, rate against Fo)."""
+    mat = W.Material(sigma=0.01)
+    steps = [300, 600, 900, 1200]
+    frac = {}
+    for theta in (60.0, 120.0):
+        o = oracle_mod.Oracle(_cap_case(theta, 0.5 * math.pi * 16.0 ** 2, mat=mat))
+        out = []
+        for s in steps:
+            o.step(s - o.step_count)
+            F = o.fields()
+            out.append(F["fs"].sum() / F["chi"].sum())
+        frac[theta] = np.array(out)
+    wet, dry = frac[60.0], frac[120.0]
+    assert np.all(wet > 1.2 * dry), (wet, dry)
+    for f in (wet, dry):
+        assert f[-1] < 0.95
+        rate = np.diff(np.concatenate([[0.0], f]))
+        # (the first interval includes the time the cold front needs to
+        # cross the slab)
+        assert np.all(rate > 0) and np.all(np.diff(rate[1:]) < 0), rate
