@@ -123,6 +123,19 @@ typedef struct lbf_params {
    * max |u| > 0.3.  Each check waits for the stream once.  0: no checks
    * (lbf_step stays fully asynchronous). */
   int32_t check_every;
+  /* div u in the source phi div u of the phase-field equation and in the
+   * recovery phi = sum g + phi div u / 2 (Sec. 3.2): 0 (default) the
+   * isotropic divergence of the previous step's velocity, the flow's own
+   * divergence, which keeps the bulk phi at its equilibrium value where the
+   * discrete flow is not exactly divergence free: a drop freezing on a cold
+   * wall, a drop dewetting a cylinder or a porous medium over thousands of
+   * steps at a gas/liquid density ratio of 0.1 need it to stay stable; it
+   * stores the previous step's velocity (two more lagged planes, 16 more
+   * bytes per node update).  1: the model's mass source mdot of eq1 (sum phi
+   * changes by exactly sum phi mdot; stable only over shorter runs).  The
+   * adjoint (lbf_tape_*) supports 1 only. */
+  int32_t phi_src_mdot;
+  int32_t reserved3;
   double s_b, s_q, s_g;
   /* Body force G = rho * grav (a uniform acceleration acting on the local
    * density) and the solid-phase velocity u_s of the drag f_s (u_s - u*)
@@ -156,6 +169,20 @@ int lbf_create(const lbf_params* params, void* stream, void* workspace, size_t w
  * The static Laplacian of phi0 is computed on the device. */
 int lbf_set_geometry(lbf_sim* sim, const float* phi0, const float* cos_theta, int32_t on_device);
 
+/* Isothermal region given node by node: every node whose mask byte is
+ * nonzero is held at its own temperature T_hold[k] -- after each collision
+ * its enthalpy populations are reset to the equilibrium, at rest, of the
+ * enthalpy that the enthalpy map (Sec. 2, eq. Hfl) inverts to that
+ * temperature (frozen phase-change material at or below T_m, liquid above).
+ * This generalises the cold substrate of Sec. 4.4, which substrate_fixed
+ * gives as the nodes with phi0 >= 1/2 at T_substrate, and replaces that rule
+ * while it is set.  mask (nx * ny bytes) and T_hold (nx * ny floats) are
+ * both host or both device memory; mask = NULL removes the per-node region
+ * (substrate_fixed's rule applies again).  The region survives
+ * lbf_set_geometry and lbf_init_fields.  The adjoint (lbf_tape_*) refuses a
+ * simulation with a per-node region. */
+int lbf_set_isothermal(lbf_sim* sim, const uint8_t* mask, const float* T_hold, int32_t on_device);
+
 /* Temperature profile of one wall, used by its anti-bounce-back rule when the
  * wall is LBF_DIRICHLET: n = nx floats for bottom/top (indexed by x),
  * n = ny floats for left/right (indexed by y). */
@@ -170,9 +197,10 @@ int lbf_init_fields(lbf_sim* sim, const float* phi, const float* T, int32_t on_d
 /* Replace the state by an externally given one at time level `step`: the
  * post-streaming distributions (27 planes of nx * ny floats: f_0..f_8,
  * g_0..g_8, h_0..h_8, the populations each node holds at the start of a
- * step) and the lagged fields of the previous step (5 planes: f_s,
- * rho C_p T mdot, (phi u)_x, (phi u)_y, p).  Geometry and wall temperatures
- * must be set; they define the wall links that the state is mapped through. */
+ * step) and the lagged fields of the previous step (7 planes: f_s,
+ * rho C_p T mdot, (phi u)_x, (phi u)_y, p, u_x, u_y).  Geometry and wall
+ * temperatures must be set; they define the wall links that the state is
+ * mapped through. */
 int lbf_set_poststream_state(lbf_sim* sim, const float* dist, const float* lag, int64_t step,
                              int32_t on_device);
 

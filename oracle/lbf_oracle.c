@@ -18,7 +18,7 @@
  * that the implicit and time-derivative terms need (f_s, Q = rho C_p T mdot,
  * phi u and p of the previous step).
  *
- * Readings of the paper where it is silent or garbled are numbered R1..R53
+ * Readings of the paper where it is silent or garbled are numbered R1..R55
  * and listed in the design notes; each is marked below where it applies.
  *
  * Parity unpinned: the phase-change fraction chi (R1-R3: which part of the
@@ -60,6 +60,10 @@ typedef struct {
   double pcm_floor;           /* R45 */
   int32_t mrt;                /* 1: MRT flow collision (R53) */
   int32_t pad2_;
+  int32_t phi_src_mdot;       /* div u in the phase-field source and recovery: 0 the
+                                 discrete divergence of the previous step's velocity
+                                 (R54), 1 the mass source mdot (R12) */
+  int32_t pad3_;
   double s_b, s_q;            /* MRT rates: density, e and epsilon moments; energy flux
                                  (0: the BGK rate 1/tau_f) */
   double s_g;                 /* MRT rate of the phase-field moments above first order
@@ -79,12 +83,17 @@ typedef struct {
   double *fs_prev, *Q_prev, *phiux_prev, *phiuy_prev, *p_prev;
   double *fs_new, *Q_new, *phiux_new, *phiuy_new, *p_new;
   double *phi0, *cth, *lap_phi0;
+  double *thold;                /* per-node held temperature (NaN: free); used when
+                                   held_per_node is set (O14 with a given region) */
+  int held_per_node;
   double *wallT[4];
   /* pass-1 arrays */
   double *phihat, *C, *chi, *rhoH, *T, *fl, *fs, *fstot, *mdot, *phi, *rho, *Ksol, *Kliq;
   /* pass-2 diagnostics */
   double *ux, *uy, *pr, *mu;
-  double budget[4];             /* sum phi*mdot, heat source, wall flux, reset */
+  double *ux_lag, *uy_lag, *ux_new, *uy_new; /* velocity of the previous step (R54) */
+  double *divu;                 /* div u of the phase-field source: R54 or R12 */
+  double budget[4];             /* sum phi div u, heat source, wall flux, reset */
   long step;
   int store_f32;                /* conditioning probe: round the state to binary32 each step */
   double mrtM[81], mrtMinv[81]; /* MRT basis and its inverse (R53) */
@@ -349,10 +358,11 @@ orc_sim* orc_create(const orc_params* p) {
   s->fc = alloc0(9 * n); s->gc = alloc0(9 * n); s->hc = alloc0(9 * n);
   double** one[] = {&s->fs_prev, &s->Q_prev, &s->phiux_prev, &s->phiuy_prev, &s->p_prev,
                     &s->fs_new, &s->Q_new, &s->phiux_new, &s->phiuy_new, &s->p_new,
-                    &s->phi0, &s->cth, &s->lap_phi0,
+                    &s->phi0, &s->cth, &s->lap_phi0, &s->thold,
                     &s->phihat, &s->C, &s->chi, &s->rhoH, &s->T, &s->fl, &s->fs,
                     &s->fstot, &s->mdot, &s->phi, &s->rho, &s->Ksol, &s->Kliq,
-                    &s->ux, &s->uy, &s->pr, &s->mu};
+                    &s->ux, &s->uy, &s->pr, &s->mu, &s->ux_lag, &s->uy_lag,
+                    &s->ux_new, &s->uy_new, &s->divu};
   for (size_t k = 0; k < sizeof one / sizeof one[0]; ++k) *one[k] = alloc0(n);
   s->wallT[WB] = alloc0(p->nx); s->wallT[WT] = alloc0(p->nx);
   s->wallT[WL] = alloc0(p->ny); s->wallT[WR] = alloc0(p->ny);
@@ -366,9 +376,10 @@ void orc_destroy(orc_sim* s) {
   double* all[] = {s->f, s->g, s->h, s->fc, s->gc, s->hc, s->fs_prev, s->Q_prev,
                    s->phiux_prev, s->phiuy_prev, s->p_prev, s->fs_new, s->Q_new,
                    s->phiux_new, s->phiuy_new, s->p_new, s->phi0, s->cth, s->lap_phi0,
-                   s->phihat, s->C, s->chi, s->rhoH, s->T, s->fl, s->fs, s->fstot,
+                   s->thold, s->phihat, s->C, s->chi, s->rhoH, s->T, s->fl, s->fs, s->fstot,
                    s->mdot, s->phi, s->rho, s->Ksol, s->Kliq, s->ux, s->uy, s->pr,
-                   s->mu, s->wallT[0], s->wallT[1], s->wallT[2], s->wallT[3]};
+                   s->mu, s->ux_lag, s->uy_lag, s->ux_new, s->uy_new, s->divu,
+                   s->wallT[0], s->wallT[1], s->wallT[2], s->wallT[3]};
   for (size_t k = 0; k < sizeof all / sizeof all[0]; ++k) free(all[k]);
   free(s);
 }
@@ -445,8 +456,19 @@ static void pass1(orc_sim* s) {
       double fstot = fmin(1.0, phi0 + fs); /* R2 */
       /* mass source mdot = (1 - rho_s/rho_l) d fs/dt (eq1), backward difference (R13) */
       double mdot = (1.0 - p->rho_s / p->rho_l) * (fs - s->fs_prev[k]);
-      /* phi = sum g + (dt/2) phi div u with div u = mdot (Sec. 3.2; R12) */
-      double phi = sg / (1.0 - 0.5 * mdot);
+      /* div u of the phase-field equation (Sec. 3.2): the model's mdot (R12),
+       * or the divergence of the flow's own velocity, the previous step's,
+       * with the isotropic stencil (R54) */
+      double divu = mdot;
+      if (!p->phi_src_mdot) {
+        double gxx, gxy, gyx, gyy;
+        grad_lap(s, s->ux_lag, x, y, &gxx, &gxy, NULL);
+        grad_lap(s, s->uy_lag, x, y, &gyx, &gyy, NULL);
+        divu = gxx + gyy;
+      }
+      /* phi = sum g + (dt/2) phi div u (Sec. 3.2) */
+      double phi = sg / (1.0 - 0.5 * divu);
+      s->divu[k] = divu;
       s->phihat[k] = sg; s->C[k] = C; s->chi[k] = chi; s->rhoH[k] = rhoH;
       s->T[k] = T; s->fl[k] = fl; s->fs[k] = fs; s->fstot[k] = fstot;
       s->mdot[k] = mdot; s->phi[k] = phi; s->Ksol[k] = Ksol; s->Kliq[k] = Kliq;
@@ -517,6 +539,8 @@ static void pass2(orc_sim* s, int collide) {
       double pr = CS2 / (1.0 - W[0]) * (sum_nz + 0.5 * S + f0neq + rho * s0);
       s->ux[k] = ux; s->uy[k] = uy; s->pr[k] = pr; s->mu[k] = mu;
       if (!collide) continue;
+      s->ux_new[k] = ux;
+      s->uy_new[k] = uy;
       /* flow collision (Sec. 3.1; MRT: R53) */
       double feq[9], fin[9];
       orc_feq(pr, rho, ux, uy, feq);
@@ -537,7 +561,7 @@ static void pass2(orc_sim* s, int collide) {
       double djx = jx - s->phiux_prev[k], djy = jy - s->phiuy_prev[k];
       double Gv[9], gin[9];
       for (int i = 0; i < 9; ++i) {
-        Gv[i] = W[i] * (CX[i] * djx + CY[i] * djy) / CS2 + W[i] * phi * mdot;
+        Gv[i] = W[i] * (CX[i] * djx + CY[i] * djy) / CS2 + W[i] * phi * s->divu[k];
         gin[i] = s->g[i * n + k];
       }
       if (p->mrt) {
@@ -571,10 +595,13 @@ static void pass2(orc_sim* s, int collide) {
       /* expected energy gain of the collision, from the TRT moment algebra:
        * sum h* - sum h = (1/tau_s) Q_prev/2 + (1 - 1/(2 tau_src)) Q */
       acc_heat += 0.5 * s->Q_prev[k] / tau_s + (1.0 - 0.5 / tau_src) * Q;
-      acc_phi += phi * mdot;
-      /* isothermal solid region (R21) */
-      if (p->substrate_fixed && s->phi0[k] >= 0.5) {
-        double Tw = p->T_substrate;
+      acc_phi += phi * s->divu[k];
+      /* isothermal region (O14): the nodes with phi0 >= 1/2 at T_substrate
+       * (R21), or a region given node by node with its own temperatures */
+      int held = s->held_per_node ? !isnan(s->thold[k])
+                                  : (p->substrate_fixed && s->phi0[k] >= 0.5);
+      if (held) {
+        double Tw = s->held_per_node ? s->thold[k] : p->T_substrate;
         double rH = enthalpy_at(p, Tw, s->Ksol[k], s->Kliq[k], s->chi[k]);
         double e[9], es = 0.0;
         orc_heq(rH, Tw, rhocp, Eref, 0.0, 0.0, e);
@@ -669,6 +696,8 @@ static void swap_lagged(orc_sim* s) {
   t = s->phiux_prev; s->phiux_prev = s->phiux_new; s->phiux_new = t;
   t = s->phiuy_prev; s->phiuy_prev = s->phiuy_new; s->phiuy_new = t;
   t = s->p_prev; s->p_prev = s->p_new; s->p_new = t;
+  t = s->ux_lag; s->ux_lag = s->ux_new; s->ux_new = t;
+  t = s->uy_lag; s->uy_lag = s->uy_new; s->uy_new = t;
 }
 
 /* Conditioning probe (off by default): with store_f32 set, the state is
@@ -679,8 +708,9 @@ static void round_state_f32(orc_sim* s) {
   double* arrs[] = {s->f, s->g, s->h};
   for (int a = 0; a < 3; ++a)
     for (size_t k = 0; k < 9 * s->n; ++k) arrs[a][k] = (double)(float)arrs[a][k];
-  double* lag[] = {s->fs_prev, s->Q_prev, s->phiux_prev, s->phiuy_prev, s->p_prev};
-  for (int a = 0; a < 5; ++a)
+  double* lag[] = {s->fs_prev, s->Q_prev, s->phiux_prev, s->phiuy_prev, s->p_prev,
+                   s->ux_lag, s->uy_lag};
+  for (int a = 0; a < 7; ++a)
     for (size_t k = 0; k < s->n; ++k) lag[a][k] = (double)(float)lag[a][k];
 }
 
@@ -714,6 +744,17 @@ void orc_set_wall_T(orc_sim* s, int wall, const double* Tw) {
                                  sizeof(double));
 }
 
+/* Per-node isothermal region: T[k] is the held temperature of node k, NaN
+ * where the node is free; T = NULL goes back to the substrate_fixed rule. */
+void orc_set_isothermal(orc_sim* s, const double* T) {
+  if (!T) {
+    s->held_per_node = 0;
+    return;
+  }
+  memcpy(s->thold, T, s->n * sizeof(double));
+  s->held_per_node = 1;
+}
+
 void orc_set_cos_theta(orc_sim* s, const double* cth) { memcpy(s->cth, cth, s->n * sizeof(double)); }
 
 /* Initial state: u = 0, p = 0 (R29), so f = 0; g = g^eq(phi, mu_phi, 0);
@@ -730,6 +771,8 @@ int orc_init(orc_sim* s, const double* phi0, const double* cth, const double* ph
   memset(s->phiux_prev, 0, n * sizeof(double));
   memset(s->phiuy_prev, 0, n * sizeof(double));
   memset(s->p_prev, 0, n * sizeof(double));
+  memset(s->ux_lag, 0, n * sizeof(double));   /* u = 0 initially (R29) */
+  memset(s->uy_lag, 0, n * sizeof(double));
   memcpy(s->phi, phi, n * sizeof(double));
   for (size_t k = 0; k < n; ++k) s->fs[k] = 0.0;
   for (int y = 0; y < s->ny; ++y)
@@ -786,7 +829,7 @@ void orc_fields(orc_sim* s, double* out) {
 }
 
 /* Global sums (a12): 0 sum sum g, 1 sum sum h, 2 sum f_s, 3 sum (chi - f_s),
- * 4 max |u|, 5 non-finite count, 6..9 budget of the last step (sum phi mdot,
+ * 4 max |u|, 5 non-finite count, 6..9 budget of the last step (sum phi div u,
  * heat source, wall flux, isothermal reset), 10 step count. */
 #define ORC_NRED 11
 int orc_nred(void) { return ORC_NRED; }
@@ -814,7 +857,7 @@ void orc_reduce(orc_sim* s, double* out) {
 }
 
 /* Raw post-stream distributions and lagged fields (test access). */
-void orc_get_state(orc_sim* s, double* f, double* g, double* h, double* lag /* 5n */) {
+void orc_get_state(orc_sim* s, double* f, double* g, double* h, double* lag /* 7n */) {
   const size_t n = s->n;
   memcpy(f, s->f, 9 * n * sizeof(double));
   memcpy(g, s->g, 9 * n * sizeof(double));
@@ -824,6 +867,8 @@ void orc_get_state(orc_sim* s, double* f, double* g, double* h, double* lag /* 5
   memcpy(lag + 2 * n, s->phiux_prev, n * sizeof(double));
   memcpy(lag + 3 * n, s->phiuy_prev, n * sizeof(double));
   memcpy(lag + 4 * n, s->p_prev, n * sizeof(double));
+  memcpy(lag + 5 * n, s->ux_lag, n * sizeof(double));
+  memcpy(lag + 6 * n, s->uy_lag, n * sizeof(double));
 }
 
 void orc_set_state(orc_sim* s, const double* f, const double* g, const double* h,
@@ -837,6 +882,8 @@ void orc_set_state(orc_sim* s, const double* f, const double* g, const double* h
   memcpy(s->phiux_prev, lag + 2 * n, n * sizeof(double));
   memcpy(s->phiuy_prev, lag + 3 * n, n * sizeof(double));
   memcpy(s->p_prev, lag + 4 * n, n * sizeof(double));
+  memcpy(s->ux_lag, lag + 5 * n, n * sizeof(double));
+  memcpy(s->uy_lag, lag + 6 * n, n * sizeof(double));
 }
 
 long orc_step_count(orc_sim* s) { return s->step; }

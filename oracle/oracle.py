@@ -20,6 +20,9 @@ SRC = os.path.join(HERE, "lbf_oracle.c")
 LIB = os.path.join(HERE, "liblbf_oracle.so")
 
 FIELDS = ["phi", "T", "fl", "fs", "ux", "uy", "p", "rhoH", "mu", "C", "chi", "rho", "phihat"]
+# lagged fields of the state: f_s, Q = rho C_p T mdot, (phi u)_x, (phi u)_y,
+# p and u_x, u_y of the previous step
+NLAG = 7
 REDS = ["sum_g", "sum_h", "sum_fs", "sum_liq", "umax", "nonfinite",
         "src_phi", "src_heat", "wall_flux", "reset", "step"]
 
@@ -33,7 +36,8 @@ class OrcParams(C.Structure):
             "rho_l", "rho_g", "rho_s", "mu_l", "mu_g", "mu_s", "lam_l", "lam_g", "lam_s",
             "cp_l", "cp_g", "cp_s", "latent", "T_m", "sigma", "eps", "mobility",
             "cos_psi", "rho_ref", "T_substrate", "pcm_floor")] + [
-        ("mrt", C.c_int32), ("pad2_", C.c_int32), ("s_b", C.c_double), ("s_q", C.c_double),
+        ("mrt", C.c_int32), ("pad2_", C.c_int32), ("phi_src_mdot", C.c_int32),
+        ("pad3_", C.c_int32), ("s_b", C.c_double), ("s_q", C.c_double),
         ("s_g", C.c_double), ("grav", C.c_double * 2), ("u_solid", C.c_double * 2)]
 
 
@@ -66,6 +70,7 @@ def lib():
         L.orc_reduce.argtypes = [C.c_void_p, dp]
         L.orc_set_wall_T.argtypes = [C.c_void_p, C.c_int, dp]
         L.orc_set_cos_theta.argtypes = [C.c_void_p, dp]
+        L.orc_set_isothermal.argtypes = [C.c_void_p, dp]
         L.orc_get_state.argtypes = [C.c_void_p, dp, dp, dp, dp]
         L.orc_set_state.argtypes = [C.c_void_p, dp, dp, dp, dp]
         L.orc_feq.argtypes = [C.c_double] * 4 + [dp]
@@ -111,6 +116,7 @@ def make_params(case) -> OrcParams:
         setattr(p, k, float(getattr(m, k)))
     p.T_substrate = float(case.T_substrate)
     p.mrt = int(getattr(m, "mrt", 0))
+    p.phi_src_mdot = int(getattr(m, "phi_src_mdot", 0))
     p.s_b, p.s_q = float(getattr(m, "s_b", 0.0)), float(getattr(m, "s_q", 0.0))
     p.s_g = float(getattr(m, "s_g", 0.0))
     p.grav[0], p.grav[1] = float(m.g_x), float(m.g_y)
@@ -135,6 +141,16 @@ class Oracle:
             L.orc_set_wall_T(self.h, w, _ptr(case.wall_profile(w)))
         self._keep = [_f64(case.phi0), _f64(case.cos_theta), _f64(case.phi), _f64(case.T)]
         L.orc_init(self.h, *[_ptr(a) for a in self._keep])
+        if getattr(case, "T_hold", None) is not None:
+            self.set_isothermal(case.T_hold)
+
+    def set_isothermal(self, T_hold) -> None:
+        """Per-node held temperatures (NaN where free); None: the substrate rule."""
+        if T_hold is None:
+            lib().orc_set_isothermal(self.h, None)
+            return
+        self._thold = _f64(T_hold)
+        lib().orc_set_isothermal(self.h, _ptr(self._thold))
 
     def __del__(self):
         try:
@@ -172,10 +188,10 @@ class Oracle:
     def get_state(self):
         n = self.nx * self.ny
         f, g, h = (np.empty(9 * n) for _ in range(3))
-        lag = np.empty(5 * n)
+        lag = np.empty(NLAG * n)
         lib().orc_get_state(self.h, _ptr(f), _ptr(g), _ptr(h), _ptr(lag))
         sh = (9, self.ny, self.nx)
-        return f.reshape(sh), g.reshape(sh), h.reshape(sh), lag.reshape(5, self.ny, self.nx)
+        return f.reshape(sh), g.reshape(sh), h.reshape(sh), lag.reshape(NLAG, self.ny, self.nx)
 
     def set_state(self, f, g, h, lag) -> None:
         lib().orc_set_state(self.h, _ptr(_f64(f).ravel()), _ptr(_f64(g).ravel()),

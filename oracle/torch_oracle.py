@@ -8,8 +8,8 @@ the wall temperatures (through the initialisation and every step).  Its
 forward map is checked against the C oracle to round-off.
 
 State (the paper's notation): post-streaming f, g, h [9, ny, nx] and the
-lagged fields f_s, Q = rho C_p T mdot, (phi u)_x, (phi u)_y, p of the previous
-step.  Readings R1-R45 as in the C oracle.
+lagged fields f_s, Q = rho C_p T mdot, (phi u)_x, (phi u)_y, p, u_x, u_y of the
+previous step.  Readings R1-R54 as in the C oracle.
 """
 
 from __future__ import annotations
@@ -167,7 +167,7 @@ class TorchLattice:
         ET = self.Eref * T0
         h = d0 * (rhoH - ET) + self.w * ET
         f = torch.zeros((9,) + phi.shape, dtype=DT)
-        lag = tuple(torch.zeros_like(phi) for _ in range(5))
+        lag = tuple(torch.zeros_like(phi) for _ in range(7))
         return f, g, h, lag
 
     # ---- one step
@@ -183,16 +183,22 @@ class TorchLattice:
         fs = chi * (1.0 - fl)
         fstot = torch.clamp(self.phi0 + fs, max=1.0)
         mdot = (1.0 - m.rho_s / m.rho_l) * (fs - fs_prev)
-        phi = phihat / (1.0 - 0.5 * mdot)
+        # div u of the phase-field source: mdot (R12) or the divergence of
+        # the previous step's velocity (R54)
+        if getattr(m, "phi_src_mdot", 0):
+            divu = mdot
+        else:
+            divu = self.grad(lag[5])[0] + self.grad(lag[6])[1]
+        phi = phihat / (1.0 - 0.5 * divu)
         rho = self.zeta(fstot, C, m.rho_s, m.rho_l, m.rho_g)
         return dict(phihat=phihat, C=C, chi=chi, rhoH=rhoH, T=T, fl=fl, fs=fs, fstot=fstot,
-                    mdot=mdot, phi=phi, rho=rho, Ksol=Ksol, Kliq=Kliq)
+                    mdot=mdot, divu=divu, phi=phi, rho=rho, Ksol=Ksol, Kliq=Kliq)
 
     def step(self, state, cth, wallT):
         """wallT: tensor [4, max(nx, ny)] of wall temperatures."""
         m = self.m
         f, g, h, lag = state
-        fs_prev, Q_prev, jx_prev, jy_prev, p_prev = lag
+        fs_prev, Q_prev, jx_prev, jy_prev, p_prev = lag[:5]
         M = self.moments(g, h, lag)
         phi, rho, C, fs, fstot, mdot, T = (M[k] for k in ("phi", "rho", "C", "fs", "fstot",
                                                             "mdot", "T"))
@@ -232,7 +238,8 @@ class TorchLattice:
         fc = f - (f - feq) / tau_f + (1.0 - 0.5 / tau_f) * Fi
         jx, jy = phi * ux, phi * uy
         geq = d0 * phi + (self.w - d0) * mu + self.w * (self.cx * jx + self.cy * jy) / CS2
-        Gi = self.w * (self.cx * (jx - jx_prev) + self.cy * (jy - jy_prev)) / CS2 + self.w * phi * mdot
+        Gi = self.w * (self.cx * (jx - jx_prev) + self.cy * (jy - jy_prev)) / CS2 \
+            + self.w * phi * M["divu"]
         gc = g - (g - geq) / tau_g + (1.0 - 0.5 / tau_g) * Gi
         rhocp = rho * cp
         ET = self.Eref * T
@@ -265,7 +272,7 @@ class TorchLattice:
             twv = wallT[wl, self.along].view(9, self.ny, self.nx)
             d = self.dirich.view(9, self.ny, self.nx)
             hn = torch.where(d, -hn + 2.0 * self.w * self.Eref * twv, hn)
-        lag_new = (fs, Q, jx, jy, pr)
+        lag_new = (fs, Q, jx, jy, pr, ux, uy)
         return (fn, gn, hn, lag_new)
 
     def fields(self, state):
@@ -309,7 +316,7 @@ def run_checkpointed(case, steps: int, cth: torch.Tensor, wallT: torch.Tensor,
     flat = [state[0], state[1], state[2], *state[3]]
 
     def seg_fn(n, c, w, *xs):
-        st = (xs[0], xs[1], xs[2], tuple(xs[3:8]))
+        st = (xs[0], xs[1], xs[2], tuple(xs[3:10]))
         for _ in range(n):
             st = lat.step(st, c, w)
         return (st[0], st[1], st[2], *st[3])
@@ -319,5 +326,5 @@ def run_checkpointed(case, steps: int, cth: torch.Tensor, wallT: torch.Tensor,
         n = min(segment, steps - done)
         flat = list(checkpoint(seg_fn, n, cth, wallT, *flat, use_reentrant=True))
         done += n
-    state = (flat[0], flat[1], flat[2], tuple(flat[3:8]))
+    state = (flat[0], flat[1], flat[2], tuple(flat[3:10]))
     return lat.fields(state), lat

@@ -360,6 +360,7 @@ void fill_phys3(const lbf3_params* p, Phys& ph) {
   ph.latch = p->latch_fs ? 1 : 0;
   ph.src_tau_a = p->h_src_tau_a ? 1 : 0;
   ph.subfix = p->substrate_fixed ? 1 : 0;
+  ph.phi_src_flow = 0;   // the D3Q19 step takes div u = mdot (no lagged velocity planes)
   for (int a = 0; a < 3; ++a) {
     ph.grav[a] = (float)p->grav[a];
     ph.vsol[a] = (float)p->u_solid[a];

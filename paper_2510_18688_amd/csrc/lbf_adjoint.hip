@@ -172,6 +172,12 @@ int lbf_tape_create(lbf_sim* sim, int32_t nsteps, int32_t segment, lbf_tape** ou
   if (sim->prm.grav[0] != 0.0 || sim->prm.grav[1] != 0.0 || sim->prm.u_solid[0] != 0.0 ||
       sim->prm.u_solid[1] != 0.0)
     return fail(LBF_EINVAL, "the adjoint supports grav = u_solid = 0 only");
+  if (sim->ph.subfix == 2)
+    return fail(LBF_EINVAL, "the adjoint supports the phi0 >= 1/2 held region only, not a "
+                            "per-node isothermal region");
+  if (sim->ph.phi_src_flow)
+    return fail(LBF_EINVAL, "the adjoint supports phi_src_mdot = 1 only (the phase-field "
+                            "source from the mass source)");
   if (nsteps < 0) return fail(LBF_EINVAL, "nsteps %d", nsteps);
   if (segment < 0) return fail(LBF_EINVAL, "segment %d", segment);
   lbf_tape* t = new (std::nothrow) lbf_tape();
@@ -220,6 +226,9 @@ int lbf_tape_forward(lbf_tape* t) {
   if (!t) return fail(LBF_EINVAL, "tape is NULL");
   lbf_sim* s = t->sim;
   if (!s->have_init) return fail(LBF_ESTATE, "the simulation is not initialised");
+  if (s->ph.subfix == 2)
+    return fail(LBF_EINVAL, "the adjoint supports the phi0 >= 1/2 held region only, not a "
+                            "per-node isothermal region");
   t->with_init = s->from_fields && s->step == 0;
   for (int c = 0; c < t->nsteps; c += t->seg) {
     int rc = copy_state_out(t, state_ptr(t, 0, c / t->seg));

@@ -514,7 +514,7 @@ __global__ __launch_bounds__(256) void k_adj_collide(AdjStepArgs a) {
   float s4[4];
   node_finish(ph, in, m, s4);
   FlowIn fl;
-  flow_load(G, B, x, y, fl);
+  flow_load(G, ph, B, x, y, fl);
   Stencil S;
 #pragma unroll
   for (int i = 0; i < 9; ++i) {

@@ -103,6 +103,8 @@ int validate(const lbf_params* p) {
       return fail(LBF_EINVAL, "thermal_bc[%d] = %d", w, p->thermal_bc[w]);
   if (p->mrt != 0 && p->mrt != 1) return fail(LBF_EINVAL, "mrt = %d", p->mrt);
   if (p->check_every < 0) return fail(LBF_EINVAL, "check_every = %d", p->check_every);
+  if (p->phi_src_mdot != 0 && p->phi_src_mdot != 1)
+    return fail(LBF_EINVAL, "phi_src_mdot = %d", p->phi_src_mdot);
   for (int a = 0; a < 2; ++a)
     if (!std::isfinite(p->grav[a]) || !std::isfinite(p->u_solid[a]))
       return fail(LBF_EINVAL, "grav and u_solid must be finite");
@@ -145,6 +147,7 @@ void fill_phys(const lbf_params* p, Phys& ph) {
   ph.src_tau_a = p->h_src_tau_a ? 1 : 0;
   ph.subfix = p->substrate_fixed ? 1 : 0;
   ph.mrt = p->mrt ? 1 : 0;
+  ph.phi_src_flow = p->phi_src_mdot ? 0 : 1;
   ph.s_b = p->mrt ? (float)p->s_b : 0.0f;
   ph.s_q = p->mrt ? (float)p->s_q : 0.0f;
   ph.s_g = p->mrt ? (float)p->s_g : 0.0f;
@@ -168,6 +171,15 @@ __global__ void k_lap_static(Geo G, float* stat) {
     lap += wgt(i) * (phi0[yy * G.nx + xx] - c);
   }
   stat[ST_LAP0 * G.P + y * G.nx + x] = 6.0f * lap;
+}
+
+// Held temperature per node from a byte mask and a temperature field (both
+// staged in device memory): T where the mask is set, NaN elsewhere.
+__global__ void k_set_thold(Geo G, const uint8_t* mask, const float* T, float* stat) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+  if (x >= G.nx || y >= G.ny) return;
+  const int k = y * G.nx + x;
+  stat[ST_THOLD * G.P + k] = mask[k] ? T[k] : __builtin_nanf("");
 }
 
 // Equilibrium populations of the initial state, in post-stream form, into
@@ -459,6 +471,28 @@ int lbf_set_geometry(lbf_sim* s, const float* phi0, const float* cos_theta, int3
   return LBF_OK;
 }
 
+int lbf_set_isothermal(lbf_sim* s, const uint8_t* mask, const float* T_hold, int32_t on_device) {
+  if (!s) return fail(LBF_EINVAL, "sim is NULL");
+  if (!mask) {
+    s->ph.subfix = s->prm.substrate_fixed ? 1 : 0;
+    return LBF_OK;
+  }
+  if (!T_hold) return fail(LBF_EINVAL, "T_hold is NULL");
+  const size_t n = (size_t)s->G.nx * s->G.ny;
+  // stage both arrays in the read-out planes (free between calls)
+  float* stage = fptr(s, s->L.fields);
+  uint8_t* mstage = reinterpret_cast<uint8_t*>(stage + s->G.P);
+  int rc = copy_in(s, stage, T_hold, n * sizeof(float), on_device);
+  if (rc) return rc;
+  rc = copy_in(s, mstage, mask, n, on_device);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_set_thold, node_grid(s), dim3(256), 0, s->stream, s->G,
+                     (const uint8_t*)mstage, (const float*)stage, fptr(s, s->L.stat));
+  HIP_TRY(hipGetLastError());
+  s->ph.subfix = 2;
+  return LBF_OK;
+}
+
 int lbf_set_wall_temperature(lbf_sim* s, int32_t wall, const float* Tw, int32_t n,
                              int32_t on_device) {
   if (!s || !Tw) return fail(LBF_EINVAL, "NULL argument");
@@ -507,8 +541,12 @@ int lbf_set_poststream_state(lbf_sim* s, const float* dist, const float* lag, in
     if (rc) return rc;
   }
   float* lg = fptr(s, s->L.lag[s->cur]);
-  for (int pl = 0; pl < LAG_GHI; ++pl) {   // the high parts come from dist
-    int rc = copy_in(s, lg + (size_t)pl * s->G.P, lag + pl * n, n * sizeof(float), on_device);
+  // planes f_s, Q, (phi u), p, u of the caller's order; the high parts of
+  // the rest populations come from dist
+  const int dst_plane[7] = {LAG_FS, LAG_Q, LAG_JX, LAG_JY, LAG_P, LAG_UX, LAG_UY};
+  for (int pl = 0; pl < 7; ++pl) {
+    int rc = copy_in(s, lg + (size_t)dst_plane[pl] * s->G.P, lag + pl * n, n * sizeof(float),
+                     on_device);
     if (rc) return rc;
   }
   hipLaunchKernelGGL(k_unstream, node_grid(s), dim3(256), 0, s->stream, s->G, s->ph,

@@ -7,9 +7,12 @@
 //                  at the node itself, so every store is row-coalesced and
 //                  aligned and the pull loads are row-coalesced with a
 //                  +-1 element shift;
-//   lagged fields  7 planes: f_s, Q = rho C_p T mdot, (phi u)_x, (phi u)_y, p
-//                  of the previous step, and the high parts of g_0 and h_0;
-//   static fields  3 planes: phi0, cos(theta), lap(phi0).
+//   lagged fields  9 planes: f_s, Q = rho C_p T mdot, (phi u)_x, (phi u)_y, p
+//                  of the previous step, the high parts of g_0 and h_0, and
+//                  the previous step's velocity u_x, u_y (written and read only
+//                  when the phase-field source takes its divergence);
+//   static fields  4 planes: phi0, cos(theta), lap(phi0), and the temperature
+//                  of the per-node isothermal region (NaN where not held).
 // Both distributions and lagged fields are double-buffered (ping-pong).
 // Storage is deviation-form: f^eq vanishes at the rest state (p = 0, u = 0)
 // exactly; the moving g_i, h_i (i > 0) carry only O(mu) and O(rho_ref C_p T)
@@ -25,16 +28,20 @@
 namespace lbf {
 
 constexpr int NDIST = 27;
-constexpr int NLAG = 7;
-constexpr int NSTAT = 3;
+constexpr int NLAG = 9;
+constexpr int NSTAT = 4;
 constexpr int NFIELD = 13;
 constexpr int NRED = 11;
 
 // lagged planes: f_s, Q = rho C_p T mdot, (phi u)_x, (phi u)_y, p of the
-// previous step, and the high parts of the rest populations g_0, h_0
-enum { LAG_FS = 0, LAG_Q = 1, LAG_JX = 2, LAG_JY = 3, LAG_P = 4, LAG_GHI = 5, LAG_HHI = 6 };
-// static planes: phi0, cos(theta), lap(phi0)
-enum { ST_PHI0 = 0, ST_CTH = 1, ST_LAP0 = 2 };
+// previous step, the high parts of the rest populations g_0, h_0, and the
+// previous step's velocity
+enum {
+  LAG_FS = 0, LAG_Q = 1, LAG_JX = 2, LAG_JY = 3, LAG_P = 4, LAG_GHI = 5, LAG_HHI = 6,
+  LAG_UX = 7, LAG_UY = 8
+};
+// static planes: phi0, cos(theta), lap(phi0), held temperature (NaN: free)
+enum { ST_PHI0 = 0, ST_CTH = 1, ST_LAP0 = 2, ST_THOLD = 3 };
 // MODE_STEP_MOM: a step that also stores phi, f_s and rho of the state it
 // reads (planes 0-2 of the fields buffer), for the reverse sweep's stencils
 enum { MODE_STEP = 0, MODE_FIELDS = 1, MODE_STEP_MOM = 2 };
@@ -88,8 +95,12 @@ struct Phys {
   float mdot_coef;   // 1 - rho_s / rho_l
   float pcm_floor;   // liquid weight below which a node holds no phase-change material
   float inv_pcm_span; // 1 / (1 - pcm_floor)
-  int latch, src_tau_a, subfix;
+  int latch, src_tau_a;
+  int subfix;        // isothermal region: 0 none, 1 nodes with phi0 >= 1/2 at
+                     // T_sub, 2 the per-node plane ST_THOLD (NaN: not held)
   int mrt;           // 1: MRT flow and phase-field collisions
+  int phi_src_flow;  // div u of the phase-field source: 0 mdot, 1 the
+                     // divergence of the previous step's velocity
   float s_b, s_q;    // MRT bulk and energy-flux rates of f (0: 1/tau_f)
   float s_g;         // MRT rate of the moments of g above first order (0: 1/tau_g)
   float grav[3];     // body force G = rho grav
@@ -290,7 +301,7 @@ __device__ __forceinline__ void pull_f(const Geo& G, const Bufs& B, int x, int y
 // enthalpy map, ice fraction, mass source, order parameter and density.
 // dphi = phi - ref_g and dH = rho H - ref_h keep the small parts.
 struct Mom {
-  float C, chi, rhoH, T, fs, fstot, mdot, phi, rho, Ksol, Kliq, dphi, dH;
+  float C, chi, rhoH, T, fs, fstot, mdot, divu, phi, rho, Ksol, Kliq, dphi, dH;
   float ref_g, sg, sh;   // references and stored sums (for exact global sums)
   // intermediate values and branch decisions, read only by the reverse sweep
   // (dead code in the forward kernels)
@@ -299,10 +310,12 @@ struct Mom {
 };
 
 // ref_g, ref_h: references of the rest populations; sg, sh: sums of the
-// stored populations (rest population as its deviation).
+// stored populations (rest population as its deviation); dlag: the
+// divergence of the previous step's velocity at the node (used when the
+// phase-field source takes div u from the flow).
 __device__ __forceinline__ void moments(const Phys& ph, float ref_g, float sg, float ref_h,
                                         float sh, float fs_prev, float Q_prev, float phi0,
-                                        Mom& m) {
+                                        Mom& m, float dlag = 0.0f) {
   const float phihat = ref_g + sg;
   const float Craw = 0.5f * (1.0f - phi0 + phihat);
   const float C = clampf(Craw, 0.0f, 1.0f);
@@ -340,9 +353,14 @@ __device__ __forceinline__ void moments(const Phys& ph, float ref_g, float sg, f
   m.fs = fs;
   m.fstot = fstot;
   m.mdot = mdot;
-  // Sec. 3.2 with div u = mdot: phi = phihat / (1 - mdot/2), formed on the
-  // deviation from the reference
-  m.dphi = (sg + 0.5f * mdot * ref_g) * rcp(1.0f - 0.5f * mdot);
+  // div u of the phase-field equation: the model's mdot, or the flow's own
+  // divergence of the previous step
+  const float divu = ph.phi_src_flow ? dlag : mdot;
+  m.divu = divu;
+  // Sec. 3.2: phi = phihat / (1 - div u / 2), formed on the deviation from
+  // the reference
+  const float hd = 0.5f * divu;   // exact
+  m.dphi = __builtin_fmaf(hd, ref_g, sg) * rcp(1.0f - hd);
   m.phi = ref_g + m.dphi;
   m.dH = dH;
   m.ref_g = ref_g;
@@ -374,6 +392,18 @@ __device__ __forceinline__ float chem_pot(const Phys& ph, float phi, float lap_p
   return m;
 }
 
+// Isothermal region (R21 and its per-node form): whether the node is held,
+// and at which temperature.  `thold` is the node's ST_THOLD value (read only
+// when subfix == 2).
+__device__ __forceinline__ bool held_node(const Phys& ph, float phi0, float thold, float& Tw) {
+  if (ph.subfix == 2) {
+    Tw = thold;
+    return !__builtin_isnan(thold);
+  }
+  Tw = ph.T_sub;
+  return ph.subfix == 1 && phi0 >= 0.5f;
+}
+
 // Enthalpy of a node held at temperature Tw: frozen at or below T_m.
 __device__ __forceinline__ float enthalpy_at(const Phys& ph, float Tw, float Ksol, float Kliq,
                                              float chi) {
@@ -403,8 +433,8 @@ struct Post {
 template <bool COLLIDE, bool MRT = false>
 __device__ __forceinline__ void collide_node(const Phys& ph, const Mom& m, const Stencil& S,
                                              float phi0, float cth, float lap_phi0, float Q_prev,
-                                             float jx_prev, float jy_prev, float ref_h, float* fv,
-                                             float* gv, float* hv, Post& o) {
+                                             float jx_prev, float jy_prev, float ref_h, float thold,
+                                             float* fv, float* gv, float* hv, Post& o) {
   // isotropic stencils (factor 1/c_s^2 = 3 for the gradient, 2/c_s^2 = 6 for
   // the Laplacian)
   float gphx = 0, gphy = 0, lphi = 0, lfs = 0, grx = 0, gry = 0, gpx = 0, gpy = 0;
@@ -516,7 +546,7 @@ __device__ __forceinline__ void collide_node(const Phys& ph, const Mom& m, const
   const float inv_tau_g = ph.inv_tau_g;
   const float pg = ph.pg;
   const float djx = jx - jx_prev, djy = jy - jy_prev;
-  const float pm = phi * mdot;
+  const float pm = phi * m.divu;
   if (!(MRT && ph.mrt && ph.s_g > 0.0f)) {
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
@@ -577,10 +607,10 @@ __device__ __forceinline__ void collide_node(const Phys& ph, const Mom& m, const
     hn[i] = hv[i] - (ha - ea) * inv_tau_a - (hs - es) * inv_tau_s + ps * wgt(i) * Q;
   }
   o.heat_src = 0.5f * Q_prev * inv_tau_s + ps * Q;
-  if (ph.subfix && phi0 >= 0.5f) {
-    // isothermal solid region: reset to the equilibrium at the held
-    // temperature (rest population relative to its reference)
-    const float Tw = ph.T_sub;
+  float Tw;
+  if (held_node(ph, phi0, thold, Tw)) {
+    // isothermal region: reset to the equilibrium at the held temperature
+    // (rest population relative to its reference)
     const float rH = enthalpy_at(ph, Tw, m.Ksol, m.Kliq, m.chi);
     const float EW = ph.Eref * Tw;
     float before = 0.0f, after = 0.0f;

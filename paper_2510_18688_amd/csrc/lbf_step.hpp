@@ -27,12 +27,34 @@ struct StepShared {
   double red[WX / 64][NRED];
 };
 
+
+
 // Everything a node's moments read from memory.
 struct NodeIn {
   float g[9], h[9];
   float flux, fsp, Qp, phi0, ghi, hhi, pprev;
+  float dlag;   // divergence of the previous step's velocity at the node
+                // (phase-field source from the flow's divergence)
 };
 
+// Isotropic divergence 3 sum_i w_i c_i . u(x + c_i) from the velocity
+// components at the eight neighbours (ux[i], uy[i] at x + c_i; the entries
+// off the component's axis are not read).  Every product is rounded on its
+// own and the grouping is fixed: a node's moments are formed in several
+// inlined places (strip rows, halo rows and columns, the batched kernel),
+// and a contraction chosen differently in one of them would make the state
+// depend on the launch shape.
+__device__ __forceinline__ float div9(const float* ux, const float* uy) {
+#pragma clang fp contract(off)
+  // axis neighbours (weight 1/9), then diagonals (1/36)
+  const float ax = (ux[1] - ux[3]) + (uy[2] - uy[4]);
+  const float dg = ((ux[5] + uy[5]) + (uy[6] - ux[6])) - ((ux[7] + uy[7]) + (uy[8] - ux[8]));
+  return 3.0f * ((1.0f / 9.0f) * ax + (1.0f / 36.0f) * dg);
+}
+
+// With the phase-field source from the flow's divergence, also gather the
+// previous step's velocity at the eight neighbours (periodic wrap or the
+// mirror ghost, as for every stencil) and form its divergence.
 __device__ __forceinline__ void node_load(const Geo& G, const Phys& ph, const Bufs& B, int xx,
                                           int yy, NodeIn& in) {
   in.flux = 0.0f;
@@ -44,6 +66,17 @@ __device__ __forceinline__ void node_load(const Geo& G, const Phys& ph, const Bu
   in.ghi = ldp(B.lin, LAG_GHI, G.P, k);
   in.hhi = ldp(B.lin, LAG_HHI, G.P, k);
   in.pprev = ldp(B.lin, LAG_P, G.P, k);
+  in.dlag = 0.0f;
+  if (ph.phi_src_flow) {
+    float ux[9], uy[9];
+#pragma unroll
+    for (int i = 1; i < 9; ++i) {
+      const int kk = map_axis(yy + cy(i), G.ny, G.py) * G.nx + map_axis(xx + cx(i), G.nx, G.px);
+      ux[i] = cx(i) ? ldp(B.lin, LAG_UX, G.P, kk) : 0.0f;
+      uy[i] = cy(i) ? ldp(B.lin, LAG_UY, G.P, kk) : 0.0f;
+    }
+    in.dlag = div9(ux, uy);
+  }
 }
 
 // Moments of a loaded node: liquid weight, enthalpy map, mass source, order
@@ -56,7 +89,7 @@ __device__ __forceinline__ void node_finish(const Phys& ph, const NodeIn& in, Mo
     sg += in.g[i];
     shh += in.h[i];
   }
-  moments(ph, in.ghi, sg, in.hhi, shh, in.fsp, in.Qp, in.phi0, m);
+  moments(ph, in.ghi, sg, in.hhi, shh, in.fsp, in.Qp, in.phi0, m, in.dlag);
   st[0] = m.phi;
   st[1] = m.fs;
   st[2] = m.rho;
@@ -66,19 +99,22 @@ __device__ __forceinline__ void node_finish(const Phys& ph, const NodeIn& in, Mo
 // Flow populations and node data the collision reads.
 struct FlowIn {
   float f[9];
-  float cth, lap0, jxp, jyp;
+  float cth, lap0, jxp, jyp, thold;
 };
 
 // LAP0 = false leaves lap0 to the caller (the step kernel takes it from its
 // stencil ring).
 template <bool LAP0 = true>
-__device__ __forceinline__ void flow_load(const Geo& G, const Bufs& B, int x, int y, FlowIn& in) {
+__device__ __forceinline__ void flow_load(const Geo& G, const Phys& ph, const Bufs& B, int x,
+                                          int y, FlowIn& in) {
   pull_f(G, B, x, y, in.f);
   const int k = y * G.nx + x;
   in.cth = ldp(B.stat, ST_CTH, G.P, k);
   in.lap0 = LAP0 ? ldp(B.stat, ST_LAP0, G.P, k) : 0.0f;
   in.jxp = ldp(B.lin, LAG_JX, G.P, k);
   in.jyp = ldp(B.lin, LAG_JY, G.P, k);
+  // the per-node held temperature is read only when that region is in use
+  in.thold = ph.subfix == 2 ? ldp(B.stat, ST_THOLD, G.P, k) : 0.0f;
 }
 
 // One strip (bx, by) of the lattice.  MODE_STEP writes the next state;
@@ -134,7 +170,7 @@ __device__ __forceinline__ void step_strip(const Geo& G, const Phys& ph, const B
     node_load(G, ph, B, x, map_axis(ys - dir, G.ny, G.py), bin);
     node_load(G, ph, B, x, ys, cin);
     node_load(G, ph, B, x, map_axis(ys + dir, G.ny, G.py), ain);
-    flow_load<false>(G, B, x, ys, fin);
+    flow_load<false>(G, ph, B, x, ys, fin);
     node_finish(ph, bin, m, st);
     st[4] = bin.phi0;
 #pragma unroll
@@ -180,7 +216,7 @@ __device__ __forceinline__ void step_strip(const Geo& G, const Phys& ph, const B
       next_c = ain;
       if (more) {
         node_load(G, ph, B, x, map_axis(ya + dir, G.ny, G.py), ain);
-        flow_load<false>(G, B, x, ya, fnx);   // before this row's collision
+        flow_load<false>(G, ph, B, x, ya, fnx);   // before this row's collision
       }
     }
     if (l == 0 || l == lastl) {
@@ -226,8 +262,8 @@ __device__ __forceinline__ void step_strip(const Geo& G, const Phys& ph, const B
       }
       Post o;
       if (MODE != MODE_FIELDS) {
-        collide_node<true, MRT>(ph, cm, S, phi0, fin.cth, lap0, cQp, fin.jxp, fin.jyp, crh, fv,
-                                cg, ch, o);
+        collide_node<true, MRT>(ph, cm, S, phi0, fin.cth, lap0, cQp, fin.jxp, fin.jyp, crh,
+                                fin.thold, fv, cg, ch, o);
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
           stp(B.fout, i, P, k, fv[i]);
@@ -241,19 +277,23 @@ __device__ __forceinline__ void step_strip(const Geo& G, const Phys& ph, const B
         stp(B.lout, LAG_P, P, k, o.p);
         stp(B.lout, LAG_GHI, P, k, o.ghi);
         stp(B.lout, LAG_HHI, P, k, o.hhi);
+        if (ph.phi_src_flow) {
+          stp(B.lout, LAG_UX, P, k, o.ux);
+          stp(B.lout, LAG_UY, P, k, o.uy);
+        }
         if (MODE == MODE_STEP_MOM) {
           stp(B.fields, 0, P, k, cm.phi);
           stp(B.fields, 1, P, k, cm.fs);
           stp(B.fields, 2, P, k, cm.rho);
         }
         if (RED) {
-          a_sphi += (double)cm.phi * (double)cm.mdot;
+          a_sphi += (double)cm.phi * (double)cm.divu;
           a_heat += o.heat_src;
           a_reset += o.reset;
         }
       } else {
         collide_node<false, MRT>(ph, cm, S, phi0, fin.cth, lap0, cQp, fin.jxp, fin.jyp, crh,
-                                 fv, cg, ch, o);
+                                 fin.thold, fv, cg, ch, o);
         stp(B.fields, 0, P, k, cm.phi);
         stp(B.fields, 1, P, k, cm.T);
         stp(B.fields, 2, P, k, 1.0f - cm.fs);

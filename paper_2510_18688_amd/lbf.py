@@ -22,7 +22,7 @@ FIELDS = ["phi", "T", "fl", "fs", "ux", "uy", "p", "rhoH", "mu", "C", "chi", "rh
 REDS = ["sum_g", "sum_h", "sum_fs", "sum_liq", "umax", "nonfinite", "src_phi", "src_heat",
         "wall_flux", "reset", "step"]
 EXPORTS = ["lbf_workspace_bytes", "lbf_create", "lbf_set_geometry", "lbf_set_wall_temperature",
-           "lbf_init_fields", "lbf_step", "lbf_read_field", "lbf_read_fields", "lbf_reduce",
+           "lbf_init_fields", "lbf_set_isothermal", "lbf_step", "lbf_read_field", "lbf_read_fields", "lbf_reduce",
            "lbf_set_poststream_state", "lbf_set_tile", "lbf_get_tile", "lbf_state_bytes", "lbf_save_state",
            "lbf_load_state", "lbf_set_timing", "lbf_last_step_kernel_ms", "lbf_last_error",
            "lbf_destroy", "lbf_batch_create", "lbf_batch_set_tile", "lbf_batch_step",
@@ -55,7 +55,8 @@ class Params(C.Structure):
             "rho_l", "rho_g", "rho_s", "mu_l", "mu_g", "mu_s", "lam_l", "lam_g", "lam_s",
             "cp_l", "cp_g", "cp_s", "latent", "T_m", "sigma", "eps", "mobility", "cos_psi",
             "rho_ref", "T_substrate", "pcm_floor")] + [
-        ("mrt", C.c_int32), ("check_every", C.c_int32), ("s_b", C.c_double), ("s_q", C.c_double),
+        ("mrt", C.c_int32), ("check_every", C.c_int32), ("phi_src_mdot", C.c_int32),
+        ("reserved3", C.c_int32), ("s_b", C.c_double), ("s_q", C.c_double),
         ("s_g", C.c_double), ("grav", C.c_double * 2), ("u_solid", C.c_double * 2)]
 
 
@@ -80,6 +81,7 @@ def load(path: str = LIB_PATH):
     L.lbf_create.argtypes = [C.POINTER(Params), vp, vp, C.c_size_t, C.POINTER(vp)]
     L.lbf_set_geometry.argtypes = [vp, vp, vp, i32]
     L.lbf_set_wall_temperature.argtypes = [vp, i32, vp, i32, i32]
+    L.lbf_set_isothermal.argtypes = [vp, vp, vp, i32]
     L.lbf_init_fields.argtypes = [vp, vp, vp, i32]
     L.lbf_set_poststream_state.argtypes = [vp, vp, vp, C.c_int64, i32]
     L.lbf_step.argtypes = [vp, i32]
@@ -141,6 +143,7 @@ def make_params(case) -> Params:
         setattr(p, k, float(getattr(m, k)))
     p.T_substrate = float(case.T_substrate)
     p.mrt = int(getattr(m, "mrt", 0))
+    p.phi_src_mdot = int(getattr(m, "phi_src_mdot", 0))
     p.s_b, p.s_q = float(getattr(m, "s_b", 0.0)), float(getattr(m, "s_q", 0.0))
     p.s_g = float(getattr(m, "s_g", 0.0))
     p.grav[0], p.grav[1] = float(m.g_x), float(m.g_y)
@@ -194,6 +197,8 @@ class Sim:
         self.set_geometry(case.phi0, case.cos_theta)
         for w in range(4):
             self.set_wall_temperature(w, case.wall_profile(w))
+        if getattr(case, "T_hold", None) is not None:
+            self.set_isothermal(np.isfinite(case.T_hold), np.nan_to_num(case.T_hold))
         self.init_fields(case.phi, case.T)
 
     def close(self) -> None:
@@ -228,6 +233,31 @@ class Sim:
             raise LbfError(-1, "phi0 and cos_theta must both be host or both device")
         check(_lib.lbf_set_geometry(self.h, a, b, d))
 
+    def set_isothermal(self, mask, T_hold) -> None:
+        """Hold the nodes where `mask` is true at the temperatures `T_hold`
+        ([ny, nx] host arrays or device tensors: uint8/bool mask, float32
+        temperatures); mask None removes the per-node region."""
+        if mask is None:
+            check(_lib.lbf_set_isothermal(self.h, None, None, 0))
+            return
+        import torch
+        if isinstance(mask, torch.Tensor):
+            if mask.device.type != "cuda" or mask.dtype not in (torch.uint8, torch.bool) \
+                    or not mask.is_contiguous() or mask.numel() != self.nx * self.ny:
+                raise LbfError(-1, "mask tensor: contiguous uint8/bool, nx * ny, on the device")
+            m, dm = C.c_void_p(mask.data_ptr()), 1
+            keep = mask
+        else:
+            keep = np.ascontiguousarray(np.asarray(mask).reshape(-1) != 0, dtype=np.uint8)
+            if keep.size != self.nx * self.ny:
+                raise LbfError(-1, "mask needs nx * ny values")
+            m, dm = C.c_void_p(keep.ctypes.data), 0
+        t, dt, k2 = self._ptr_in(T_hold)
+        if dm != dt:
+            raise LbfError(-1, "mask and T_hold must both be host or both device")
+        check(_lib.lbf_set_isothermal(self.h, m, t, dm))
+        del keep, k2
+
     def set_wall_temperature(self, wall: int, Tw) -> None:
         a, d, k = self._ptr_in(Tw)
         n = self.nx if wall in (0, 1) else self.ny
@@ -241,10 +271,11 @@ class Sim:
         check(_lib.lbf_init_fields(self.h, a, b, d))
 
     def set_poststream_state(self, f, g, h, lag, step: int = 0) -> None:
-        """Load post-streaming distributions (9 planes each) and lagged fields (5)."""
+        """Load post-streaming distributions (9 planes each) and lagged fields
+        (7: f_s, Q, (phi u)_x, (phi u)_y, p, u_x, u_y)."""
         dist = np.ascontiguousarray(np.concatenate([np.reshape(f, (9, -1)), np.reshape(g, (9, -1)),
                                                     np.reshape(h, (9, -1))]), dtype=np.float32)
-        lg = np.ascontiguousarray(np.reshape(lag, (5, -1)), dtype=np.float32)
+        lg = np.ascontiguousarray(np.reshape(lag, (7, -1)), dtype=np.float32)
         check(_lib.lbf_set_poststream_state(self.h, C.c_void_p(dist.ctypes.data),
                                             C.c_void_p(lg.ctypes.data), int(step), 0))
 

@@ -62,6 +62,9 @@ class Material:
     pcm_floor: float = 0.01
     latch_fs: int = 1
     h_src_tau_a: int = 0
+    # div u of the phase-field source and recovery: 0 the divergence of the
+    # previous step's velocity (the flow's own), 1 the model's mass source mdot
+    phi_src_mdot: int = 0
     # flow and phase-field collisions: 0 BGK (Sec. 3.1, 3.2), 1 MRT with the
     # bulk rate s_b (density, energy and energy-square moments of f), the
     # energy-flux rate s_q of f and the rate s_g of the moments of g above
@@ -102,6 +105,9 @@ class Case:
     substrate_fixed: bool = False    # nodes with phi0 >= 1/2 held at T_substrate
     T_substrate: float = 0.0
     steps: int = 0
+    # per-node isothermal region: held temperature of each node, NaN where
+    # the node is free (replaces the substrate_fixed rule when given)
+    T_hold: Optional[np.ndarray] = None
 
     @property
     def nodes(self) -> int:
@@ -312,6 +318,7 @@ def adjoint_case(n: int = 256, steps: int = 2000):
     90 deg + 15 deg s1(x) and -1 + 0.25 s2(x).
     """
     case = slab_drop(n, n, 77.0, 90.0, -1.0, steps=steps, name=f"adjoint_{n}x{n}")
+    case.mat.phi_src_mdot = 1   # the phase-field source the reverse sweep differentiates
     rng = np.random.default_rng(5)
     s1 = fourier_modes(n, rng)
     s2 = fourier_modes(n, rng)
@@ -325,6 +332,7 @@ def small_freezing_case(nx: int = 32, ny: int = 24, h_s: float = 3.0, radius: fl
     on both the wettability and the wall temperature.  Contact angles
     75 +- 10 degrees and wall temperatures T_wall +- 0.2, drawn per column."""
     case = slab_drop(nx, ny, radius, 75.0, T_wall, h_s=h_s, name=f"small_freezing_{nx}x{ny}")
+    case.mat.phi_src_mdot = 1   # the phase-field source the reverse sweep differentiates
     rng = np.random.default_rng(seed)
     th = 75.0 + 10.0 * rng.uniform(-1, 1, nx)
     case.cos_theta = np.broadcast_to(np.cos(np.radians(th))[None, :], (ny, nx)).copy()

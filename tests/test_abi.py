@@ -45,10 +45,11 @@ def test_exports_every_declared_symbol(L):
 def test_params_layout_matches_header(tmp_path):
     src = tmp_path / "sz.c"
     src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "lbf.h"\n'
-                   'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu\\n", sizeof(lbf_params),'
+                   'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(lbf_params),'
                    ' offsetof(lbf_params, rho_l), offsetof(lbf_params, T_substrate),'
                    ' offsetof(lbf_params, thermal_bc), offsetof(lbf_params, mrt),'
-                   ' offsetof(lbf_params, s_q), offsetof(lbf_params, check_every));return 0;}\n')
+                   ' offsetof(lbf_params, s_q), offsetof(lbf_params, check_every),'
+                   ' offsetof(lbf_params, phi_src_mdot));return 0;}\n')
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()
@@ -59,6 +60,7 @@ def test_params_layout_matches_header(tmp_path):
     assert int(out[3]) == P.thermal_bc.offset
     assert int(out[4]) == P.mrt.offset and int(out[5]) == P.s_q.offset
     assert int(out[6]) == P.check_every.offset
+    assert int(out[7]) == P.phi_src_mdot.offset
 
 
 def test_params3_layout_matches_header(tmp_path):
@@ -84,9 +86,10 @@ def test_workspace_bytes(L):
     assert L.lbf_tape_bytes(64, 48, 128, 100, 0) > L.lbf_tape_bytes(64, 48, 0, 100, 0)
     small = L.lbf_workspace_bytes(64, 48, 0)
     big = L.lbf_workspace_bytes(2048, 2048, 0)
-    assert small > 64 * 48 * 4 * (27 * 2 + 7 * 2 + 3)
-    # 71 resident state planes + 13 read-out planes + reduction scratch
-    assert 2048 * 2048 * 4 * 84 <= big <= 2048 * 2048 * 4 * 88
+    assert small > 64 * 48 * 4 * (27 * 2 + 9 * 2 + 4)
+    # 76 resident state planes (27 + 9 ping-pong, 4 static) + 13 read-out
+    # planes + reduction scratch
+    assert 2048 * 2048 * 4 * 89 <= big <= 2048 * 2048 * 4 * 92
 
 
 def _create_rc(L, case):
@@ -110,6 +113,7 @@ def _create_rc(L, case):
     (lambda c: (setattr(c.mat, "mrt", 1), setattr(c.mat, "s_g", 2.5)), "MRT rates"),
     (lambda c: setattr(c.mat, "g_x", float("nan")), "finite"),
     (lambda c: setattr(c, "check_every", -1), "check_every"),
+    (lambda c: setattr(c.mat, "phi_src_mdot", 2), "phi_src_mdot"),
 ])
 def test_invalid_params_rejected_on_host(L, mutate, needle):
     case = W.sessile_drop(nx=16, ny=8)

@@ -101,6 +101,7 @@ def check_gradients(label, g_gpu, g_orc, rng):
 
 
 def run_case(lbf, case, steps, loss, seed=0, segment=0):
+    case.mat.phi_src_mdot = 1   # the phase-field source form the reverse sweep supports
     Jg, gc, gw = gpu_grads(lbf, case, steps, loss, segment)
     Jo, oc, ow = oracle_grads(case, steps, loss)
     assert abs(Jg - Jo) <= 1e-3 * abs(Jo) + 1e-6, (case.name, Jg, Jo)

@@ -59,11 +59,13 @@ def test_benchmark_lattice_against_oracle(lbf_mod, oracle_mod, make):
     sim, orc, tile = run_pair(lbf_mod, oracle_mod, case, 20)
     print(case.name, "tile", tile, flush=True)
     compare(sim.fields(), orc.fields(), 2e-5, f"{case.name} step 20")
-    # global sums of the FP64 reductions
+    # global sums of the FP64 reductions; the ice sum gathers the mushy
+    # nodes along the cold wall (a few thousand, each within the 2e-5 field
+    # bar), so it is held to 1e-5 of itself
     r = sim.reduce()
     ro = orc.reduce()
-    for k in ("sum_g", "sum_h", "sum_fs"):
-        assert abs(r[k] - ro[k]) <= 1e-6 * max(abs(ro[k]), 1.0), (k, r[k], ro[k])
+    for k, rel in (("sum_g", 1e-6), ("sum_h", 1e-6), ("sum_fs", 1e-5)):
+        assert abs(r[k] - ro[k]) <= rel * max(abs(ro[k]), 1.0), (k, r[k], ro[k])
 
 
 @pytest.mark.parametrize("make, steps", [(W.curved_substrate, 600), (W.porous_medium, 200)],

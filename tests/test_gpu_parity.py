@@ -6,12 +6,11 @@ bar:
   density) agrees to 2e-6 absolute, the small dynamic fields (u, p, mu_phi,
   sums of O(1e-3) terms that cancel) to 1e-4 of their scale plus 1e-8;
 * after the 5000 steps of the sessile-drop workload phi, T and the liquid
-  fraction agree to 1e-4 (L-infinity; the target of the FP32 path), or to
-  three times the oracle's own divergence under FP32-sized perturbations
-  (its initial phi perturbed by one FP32 rounding, and its state rounded to
-  FP32 after every step) should that be larger.  Every field's error is
-  written to parity_report.json in the directory LBF_REPORT_DIR names, when
-  it is set.
+  fraction agree to 1e-4 (L-infinity; the target of the FP32 path).  The
+  oracle's own divergence under FP32-sized perturbations (its initial phi
+  perturbed by one FP32 rounding, and its state rounded to FP32 after every
+  step) is reported beside every field's error in parity_report.json, in
+  the directory LBF_REPORT_DIR names, when it is set.
 Tiling never changes a node's arithmetic, so every tile shape gives
 bit-identical states.
 """
@@ -128,8 +127,7 @@ def test_sessile_workload_5000_steps(lbf_mod, oracle_mod):
         np.savez_compressed(os.path.join(REPORT_DIR, "sessile_5000_fields.npz"),
                             **{"gpu_" + k: g[k] for k in FIELDS}, **{"orc_" + k: o[k] for k in FIELDS})
     for k in ("phi", "T", "fl"):
-        bound = max(1e-4, 3.0 * rep[k]["oracle_self_divergence"])
-        assert rep[k]["linf"] <= bound, (k, rep[k])
+        assert rep[k]["linf"] <= 1e-4, (k, rep[k])
     for k in ("ux", "uy", "p"):
         assert rep[k]["rel_l2"] < 1e-2, (k, rep[k])
 
@@ -228,7 +226,7 @@ def test_runs_are_deterministic(lbf_mod):
 
 def test_errors_from_device_path(lbf_mod):
     case = W.sessile_drop(nx=32, ny=16)
-    sim = lbf_mod.Sim(case)
+    sim = lbf_mod.Sim(case, check_every=0)
     with pytest.raises(lbf_mod.LbfError):
         sim.set_tile(96, 4)
     with pytest.raises(lbf_mod.LbfError):
@@ -261,7 +259,7 @@ def test_step_reports_instability(lbf_mod):
     z = np.zeros((9, case.ny, case.nx), dtype=np.float32)
     f = z.copy()
     f[0, 5, 5] = np.nan
-    sim.set_poststream_state(f, z, z, np.zeros((5, case.ny, case.nx), np.float32), step=5)
+    sim.set_poststream_state(f, z, z, np.zeros((7, case.ny, case.nx), np.float32), step=5)
     with pytest.raises(lbf_mod.LbfError, match="time level 6"):
         sim.step(5)
     assert sim.reduce(check_stable=False)["step"] == 7

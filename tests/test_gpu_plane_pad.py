@@ -121,7 +121,7 @@ def test_checkpoint_moves_between_pads(lbf_mod):
     from paper_2510_18688_amd import workloads3 as W3
     case = lambda: W.porous_medium(nx=131, ny=67, seed=5, rmin=6.0, rmax=10.0, porosity=0.8)
     a, b = lbf_mod.Sim(case()), lbf_mod.Sim(case(), plane_pad=4160)
-    assert a.state_bytes() == b.state_bytes() == (27 + 7) * 131 * 67 * 4 + 64
+    assert a.state_bytes() == b.state_bytes() == (27 + 9) * 131 * 67 * 4 + 64
     a.step(25)
     buf = torch.empty(a.state_bytes(), dtype=torch.uint8, device="cuda")
     a.save_state(buf)

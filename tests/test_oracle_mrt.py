@@ -114,6 +114,7 @@ def test_shear_wave_viscosity(oracle_mod, mat):
         L.orc_feq(0.0, mat.rho_l, float(ux[j, 0]), 0.0, _dp(out))
         f[:, j, :] = out[:, None]
     lag[2] = ux            # phi u of the previous step (phi = 1)
+    lag[5] = ux            # and the velocity of the previous step
     o.set_state(f, g, h, lag)
 
     def amp():

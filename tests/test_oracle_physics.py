@@ -369,3 +369,46 @@ def test_smaller_contact_angle_freezes_faster(oracle_mod):
         # (the first interval includes the time the cold front needs to
         # cross the slab)
         assert np.all(rate > 0) and np.all(np.diff(rate[1:]) < 0), rate
+
+
+def test_cylinder_closed_form_values():
+    """The drop-on-cylinder closed form (Sec. 4.4, eq. analy_contactangle
+    with the area conservation, exact lens areas) at R_0 = R_s = 50 and at
+    the 2048^2 workload's geometry."""
+    from test_gpu_long import cylinder_drop_height
+    for th, v in ((30, 1.7611), (60, 2.0000), (90, 2.2051), (120, 2.3792), (150, 2.5083)):
+        assert abs(cylinder_drop_height(50.0, 50.0, th) / 50.0 - v) < 1e-4
+    assert abs(cylinder_drop_height(400.0, 300.0, 60.0) - 682.35) < 0.01
+    # 90 degrees: the two circles cross at right angles
+    R_s = 50.0
+    H = cylinder_drop_height(R_s, R_s, 90.0)
+    # H = k + R, k^2 = R^2 + R_s^2: solve back for R and check the area
+    R = (H * H - R_s * R_s) / (2.0 * H)
+    k = H - R
+    assert abs(k * k - (R * R + R_s * R_s)) < 1e-9 * k * k
+
+
+@pytest.mark.parametrize("theta,steps", [(30.0, 40000), (90.0, 20000), (150.0, 20000)])
+def test_drop_on_cylinder_equilibrium(oracle_mod, theta, steps):
+    """Isothermal drop on a diffuse cylinder relaxes to the circle that
+    meets the cylinder at the prescribed angle and keeps the drop's area
+    (Sec. 4.4, at half the paper's size: R_0 = R_s = 25 on a lattice cropped
+    to the drop and the cylinder).  H_max above the cylinder centre within
+    2 %.  The shape is independent of sigma (0.03 here, for a short
+    relaxation)."""
+    from test_gpu_long import cylinder_drop_height
+    Rs = R0 = 25.0
+    nx, ny, yc = 84, 100, 30.0
+    mat = W.Material(sigma=0.03, latent=0.0)
+    y, x = np.mgrid[0:ny, 0:nx].astype(float)
+    phi0 = 0.5 + 0.5 * np.tanh(2 * (Rs - np.hypot(x - nx / 2, y - yc)) / mat.eps)
+    phi = (1 - phi0) * np.tanh(2 * (R0 - np.hypot(x - nx / 2, y - yc - Rs)) / mat.eps)
+    case = W.Case("cylinder", nx, ny, True, False, [0, 0, 0, 0], {}, phi0,
+                  np.full((ny, nx), math.cos(math.radians(theta))), phi, np.ones((ny, nx)), mat)
+    o = oracle_mod.Oracle(case)
+    o.step(steps)
+    col = o.fields()["phi"][:, nx // 2]
+    j = np.where(col > 0)[0].max()
+    top = j + col[j] / (col[j] - col[j + 1]) - yc
+    H = cylinder_drop_height(Rs, R0, theta)
+    assert abs(top - H) <= 0.02 * H, (theta, top, H)
