@@ -56,6 +56,31 @@ int lbf_ch_smooth(const lbf_ch_params* params, const uint8_t* solid, int32_t sol
                   float* phi0, int32_t phi0_on_device, int32_t iterations, void* stream,
                   void* workspace, size_t workspace_bytes);
 
+/* Largest image (nx * ny * nz nodes) that lbf_ch_smooth_noalloc accepts:
+ * 2^22 = 4 194 304 nodes (a 2048 x 2048 or 160^3 image). */
+size_t lbf_ch_noalloc_max_nodes(void);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * smoothing as lbf_ch_smooth, with the same kernels and bit-identical
+ * results, that calls no hipMalloc, hipFree or other allocating routine.
+ * Its two planes of c live in a library-held device array of
+ * 2 * lbf_ch_noalloc_max_nodes() floats (32 MiB), one per device, which each
+ * device that the library runs on holds until the process ends; the array
+ * of the current device (hipGetDevice) is used, so `stream` must belong to
+ * that device.  `solid_dev` (nx * ny * nz bytes) and `phi0_dev`
+ * (nx * ny * nz floats) are device memory owned by the caller.  Nothing in
+ * the array needs to start at zero (the first kernel writes every node the
+ * others read).  The call is ordered on `stream` (NULL: the default stream)
+ * and returns without waiting for it.  Every call on one device shares that
+ * device's array: calls that overlap on one device (on different streams, or
+ * from several threads without ordering) race and must be serialised by the
+ * caller.  LBF_EINVAL as for lbf_ch_smooth, for NULL buffers, and for images
+ * of more than lbf_ch_noalloc_max_nodes() nodes; LBF_EHIP when the array's
+ * device address cannot be obtained. */
+int lbf_ch_smooth_noalloc(const lbf_ch_params* params, const uint8_t* solid_dev, float* phi0_dev,
+                          int32_t iterations, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

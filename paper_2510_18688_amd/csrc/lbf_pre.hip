@@ -9,12 +9,22 @@
 
 #include <cmath>
 #include <cstdint>
+#include <mutex>
 
 #include "lbf_pre.h"
 #include "lbf_sim.hpp"
 #include "lbf_step.hpp"
 
 using lbfi::fail;
+
+// Scratch of the allocation-free entry point (lbf_ch_smooth_noalloc): the two
+// planes of c for images of up to kStaticNodesCH nodes.  Every device the
+// library runs on holds its own copy (32 MiB) from the module's load until
+// the process ends.  In host code the array's name is not a device address:
+// kernels and copies use the per-device address that hipGetSymbolAddress
+// returns.
+constexpr long long kStaticNodesCH = 1LL << 22;
+static __device__ __align__(256) float scratch[2 * kStaticNodesCH];
 
 namespace {
 
@@ -288,6 +298,92 @@ size_t plane_bytes(long long n) { return ((size_t)n * 4 + 255) / 256 * 256; }
 
 int ceil_div(int a, int b) { return (a + b - 1) / b; }
 
+// Checks shared by both entry points.
+int ch_validate(const lbf_ch_params* p, int32_t iterations) {
+  if (!p) return fail(LBF_EINVAL, "NULL argument");
+  if (p->nx < 1 || p->ny < 1 || p->nz < 1)
+    return fail(LBF_EINVAL, "image size %d x %d x %d", p->nx, p->ny, p->nz);
+  const long long n = (long long)p->nx * p->ny * p->nz;
+  if (n > kMaxNodesCH) return fail(LBF_EINVAL, "image of %lld nodes exceeds 2^31 - 1", n);
+  if (iterations < 0) return fail(LBF_EINVAL, "iterations %d", iterations);
+  if (!(p->A >= 0.0) || !(p->kappa >= 0.0) || !(p->mobility >= 0.0) || !(p->dt > 0.0) ||
+      !std::isfinite(p->A) || !std::isfinite(p->kappa) || !std::isfinite(p->mobility) ||
+      !std::isfinite(p->dt))
+    return fail(LBF_EINVAL, "A, kappa, mobility must be >= 0 and dt > 0, all finite");
+  const double lmax = 16.0 / 3.0;
+  const double amp = p->dt * p->mobility * lmax * (2.0 * p->A + p->kappa * lmax);
+  if (amp > 2.0)
+    return fail(LBF_EINVAL, "dt = %g is outside the explicit scheme's stability bound "
+                            "(dt M 16/3 (2 A + kappa 16/3) = %g > 2)", p->dt, amp);
+  return LBF_OK;
+}
+
+// The smoothing itself on two planes c0, c1 of at least plane_bytes(n) each
+// (c1 also stages a host image and, when phi0 is host memory, the result).
+// Stream-ordered; synchronises only when host memory is read or written.
+int ch_run(const lbf_ch_params* p, const uint8_t* solid, bool solid_on_device, float* phi0,
+           bool phi0_on_device, int32_t iterations, hipStream_t st, float* c0, float* c1) {
+  const int N = p->nx * p->ny * p->nz;
+  float* c[2] = {c0, c1};
+  const int nb = (N + 255) / 256;
+  const ChGeo G{{p->nx, p->ny, p->nz},
+                {p->periodic[0] ? 1 : 0, p->periodic[1] ? 1 : 0, p->periodic[2] ? 1 : 0}};
+  const bool is3d = p->nz > 1;
+  const int ntx = ceil_div(p->nx, is3d ? kTX3 : kTX2), nty = ceil_div(p->ny, is3d ? kTY3 : kTY2);
+  const int ntz = is3d ? ceil_div(p->nz, kTZ3) : 1;
+  const int ntiles = ntx * nty * ntz;
+  const float A = (float)p->A, kap = (float)p->kappa, dtM = (float)(p->dt * p->mobility);
+  const uint8_t* s = solid;
+  if (!solid_on_device) {
+    HIP_TRY(hipMemcpyAsync(c[1], solid, (size_t)N, hipMemcpyHostToDevice, st));
+    s = (const uint8_t*)c[1];
+  }
+  hipLaunchKernelGGL(k_ch_init, dim3(nb), dim3(256), 0, st, s, c[0], N);
+  HIP_TRY(hipGetLastError());
+  int cur = 0;
+  for (int it = 0; it < iterations; ++it) {
+    if (is3d)
+      hipLaunchKernelGGL((k_ch_step3<kTX3, kTY3, kTZ3>), dim3(ntiles), dim3(256), 0, st, G,
+                         c[cur], c[1 - cur], A, kap, dtM, ntx, nty, ntiles);
+    else
+      hipLaunchKernelGGL((k_ch_step2<kTX2, kTY2>), dim3(ntiles), dim3(256), 0, st, G, c[cur],
+                         c[1 - cur], A, kap, dtM, ntx, ntiles);
+    HIP_TRY(hipGetLastError());
+    cur = 1 - cur;
+  }
+  float* dst = phi0_on_device ? phi0 : c[1 - cur];
+  hipLaunchKernelGGL(k_ch_final, dim3(nb), dim3(256), 0, st, c[cur], dst, N);
+  HIP_TRY(hipGetLastError());
+  if (!phi0_on_device)
+    HIP_TRY(hipMemcpyAsync(phi0, dst, (size_t)N * 4, hipMemcpyDeviceToHost, st));
+  if (!phi0_on_device || !solid_on_device) HIP_TRY(hipStreamSynchronize(st));
+  return LBF_OK;
+}
+
+// Address of `scratch` per device, looked up once per device.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float* g_scratch[kMaxDevices];
+
+int scratch_on_current_device(float** out) {
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices)
+    return fail(LBF_EINVAL, "device %d: the scratch table holds devices 0..%d", dev,
+                kMaxDevices - 1);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(LBF_EHIP, "hipGetSymbolAddress(scratch) on device %d failed: %s", dev,
+                  hipGetErrorString(e));
+    g_scratch[dev] = (float*)p;
+  }
+  *out = g_scratch[dev];
+  return LBF_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -303,21 +399,10 @@ size_t lbf_ch_workspace_bytes(int32_t nx, int32_t ny, int32_t nz) {
 int lbf_ch_smooth(const lbf_ch_params* p, const uint8_t* solid, int32_t solid_on_device,
                   float* phi0, int32_t phi0_on_device, int32_t iterations, void* stream,
                   void* workspace, size_t workspace_bytes) {
-  if (!p || !solid || !phi0) return fail(LBF_EINVAL, "NULL argument");
-  if (p->nx < 1 || p->ny < 1 || p->nz < 1)
-    return fail(LBF_EINVAL, "image size %d x %d x %d", p->nx, p->ny, p->nz);
+  if (!solid || !phi0) return fail(LBF_EINVAL, "NULL argument");
+  int rc = ch_validate(p, iterations);
+  if (rc != LBF_OK) return rc;
   const long long n = (long long)p->nx * p->ny * p->nz;
-  if (n > kMaxNodesCH) return fail(LBF_EINVAL, "image of %lld nodes exceeds 2^31 - 1", n);
-  if (iterations < 0) return fail(LBF_EINVAL, "iterations %d", iterations);
-  if (!(p->A >= 0.0) || !(p->kappa >= 0.0) || !(p->mobility >= 0.0) || !(p->dt > 0.0) ||
-      !std::isfinite(p->A) || !std::isfinite(p->kappa) || !std::isfinite(p->mobility) ||
-      !std::isfinite(p->dt))
-    return fail(LBF_EINVAL, "A, kappa, mobility must be >= 0 and dt > 0, all finite");
-  const double lmax = 16.0 / 3.0;
-  const double amp = p->dt * p->mobility * lmax * (2.0 * p->A + p->kappa * lmax);
-  if (amp > 2.0)
-    return fail(LBF_EINVAL, "dt = %g is outside the explicit scheme's stability bound "
-                            "(dt M 16/3 (2 A + kappa 16/3) = %g > 2)", p->dt, amp);
   const size_t need = lbf_ch_workspace_bytes(p->nx, p->ny, p->nz);
   hipStream_t st = (hipStream_t)stream;
   char* ws = (char*)workspace;
@@ -329,50 +414,34 @@ int lbf_ch_smooth(const lbf_ch_params* p, const uint8_t* solid, int32_t solid_on
     if (hipMalloc((void**)&ws, need) != hipSuccess) return fail(LBF_ENOMEM, "hipMalloc failed");
     owns = true;
   }
-  const int N = (int)n;
   const size_t pb = plane_bytes(n);
-  float* c[2] = {(float*)ws, (float*)(ws + pb)};
-  const int nb = (N + 255) / 256;
-  const ChGeo G{{p->nx, p->ny, p->nz},
-                {p->periodic[0] ? 1 : 0, p->periodic[1] ? 1 : 0, p->periodic[2] ? 1 : 0}};
-  const bool is3d = p->nz > 1;
-  const int ntx = ceil_div(p->nx, is3d ? kTX3 : kTX2), nty = ceil_div(p->ny, is3d ? kTY3 : kTY2);
-  const int ntz = is3d ? ceil_div(p->nz, kTZ3) : 1;
-  const int ntiles = ntx * nty * ntz;
-  const float A = (float)p->A, kap = (float)p->kappa, dtM = (float)(p->dt * p->mobility);
-  auto run = [&]() -> int {
-    const uint8_t* s = solid;
-    if (!solid_on_device) {
-      HIP_TRY(hipMemcpyAsync(c[1], solid, (size_t)N, hipMemcpyHostToDevice, st));
-      s = (const uint8_t*)c[1];
-    }
-    hipLaunchKernelGGL(k_ch_init, dim3(nb), dim3(256), 0, st, s, c[0], N);
-    HIP_TRY(hipGetLastError());
-    int cur = 0;
-    for (int it = 0; it < iterations; ++it) {
-      if (is3d)
-        hipLaunchKernelGGL((k_ch_step3<kTX3, kTY3, kTZ3>), dim3(ntiles), dim3(256), 0, st, G,
-                           c[cur], c[1 - cur], A, kap, dtM, ntx, nty, ntiles);
-      else
-        hipLaunchKernelGGL((k_ch_step2<kTX2, kTY2>), dim3(ntiles), dim3(256), 0, st, G, c[cur],
-                           c[1 - cur], A, kap, dtM, ntx, ntiles);
-      HIP_TRY(hipGetLastError());
-      cur = 1 - cur;
-    }
-    float* dst = phi0_on_device ? phi0 : c[1 - cur];
-    hipLaunchKernelGGL(k_ch_final, dim3(nb), dim3(256), 0, st, c[cur], dst, N);
-    HIP_TRY(hipGetLastError());
-    if (!phi0_on_device)
-      HIP_TRY(hipMemcpyAsync(phi0, dst, (size_t)N * 4, hipMemcpyDeviceToHost, st));
-    if (!phi0_on_device || !solid_on_device || owns) HIP_TRY(hipStreamSynchronize(st));
-    return LBF_OK;
-  };
-  const int rc = run();
+  rc = ch_run(p, solid, solid_on_device != 0, phi0, phi0_on_device != 0, iterations, st,
+              (float*)ws, (float*)(ws + pb));
   if (owns) {
     (void)hipStreamSynchronize(st);
     (void)hipFree(ws);
   }
   return rc;
+}
+
+size_t lbf_ch_noalloc_max_nodes(void) { return (size_t)kStaticNodesCH; }
+
+int lbf_ch_smooth_noalloc(const lbf_ch_params* p, const uint8_t* solid_dev, float* phi0_dev,
+                          int32_t iterations, void* stream) {
+  if (!solid_dev || !phi0_dev) return fail(LBF_EINVAL, "NULL argument");
+  int rc = ch_validate(p, iterations);
+  if (rc != LBF_OK) return rc;
+  const long long n = (long long)p->nx * p->ny * p->nz;
+  if (n > kStaticNodesCH)
+    return fail(LBF_EINVAL, "image of %lld nodes exceeds the allocation-free limit of %lld "
+                            "nodes (use lbf_ch_smooth with a workspace)", n, kStaticNodesCH);
+  float* c = nullptr;
+  rc = scratch_on_current_device(&c);
+  if (rc != LBF_OK) return rc;
+  // every node of both planes that the smoothing reads is written first
+  // (k_ch_init fills c0 from the image), so nothing needs clearing
+  return ch_run(p, solid_dev, true, phi0_dev, true, iterations, (hipStream_t)stream, c,
+                c + plane_bytes(n) / sizeof(float));
 }
 
 }  // extern "C"

@@ -25,7 +25,8 @@ class ChParams(C.Structure):
                 ("mobility", C.c_double), ("dt", C.c_double)]
 
 
-EXPORTS = ["lbf_ch_workspace_bytes", "lbf_ch_smooth"]
+EXPORTS = ["lbf_ch_workspace_bytes", "lbf_ch_smooth", "lbf_ch_noalloc_max_nodes",
+           "lbf_ch_smooth_noalloc"]
 
 
 def _declare(L):
@@ -35,6 +36,9 @@ def _declare(L):
     L.lbf_ch_workspace_bytes.restype = C.c_size_t
     L.lbf_ch_workspace_bytes.argtypes = [i32, i32, i32]
     L.lbf_ch_smooth.argtypes = [C.POINTER(ChParams), vp, i32, vp, i32, i32, vp, vp, C.c_size_t]
+    L.lbf_ch_noalloc_max_nodes.restype = C.c_size_t
+    L.lbf_ch_noalloc_max_nodes.argtypes = []
+    L.lbf_ch_smooth_noalloc.argtypes = [C.POINTER(ChParams), vp, vp, i32, vp]
     L._ch_declared = True
 
 
@@ -86,6 +90,34 @@ def ch_smooth(solid, periodic: Sequence[bool], iterations: int, eps: float = 4.0
     lbf.check(L.lbf_ch_smooth(C.byref(p), src, int(on_dev), dst, int(on_dev), int(iterations),
                               C.c_void_p(stream.cuda_stream), C.c_void_p(workspace.data_ptr()),
                               workspace.numel()))
+    return out
+
+
+def ch_smooth_noalloc(solid, out, periodic: Sequence[bool], iterations: int, eps: float = 4.0,
+                      A: float = 1.0, mobility: float = 1.0, dt: float = 0.02, stream=None):
+    """`ch_smooth` through the allocation-free entry point: `solid` is a
+    contiguous uint8 device tensor, `out` a contiguous float32 device tensor
+    of the same shape that receives phi0; the library's per-device scratch
+    holds the working planes (images of up to lbf_ch_noalloc_max_nodes()
+    nodes).  Ordered on `stream` (default: torch's current stream); returns
+    `out`."""
+    torch = lbf._torch()
+    L = lbf.load()
+    _declare(L)
+    if not (hasattr(solid, "data_ptr") and hasattr(out, "data_ptr")):
+        raise ValueError("solid and out must be device tensors")
+    if solid.dtype != torch.uint8 or not solid.is_contiguous() or solid.device.type != "cuda":
+        raise ValueError("solid must be a contiguous uint8 device tensor")
+    if out.dtype != torch.float32 or not out.is_contiguous() or out.shape != solid.shape \
+            or out.device != solid.device:
+        raise ValueError("out must be a contiguous float32 tensor of the image's shape and device")
+    p = ch_params(tuple(solid.shape), periodic, eps, A, mobility, dt)
+    if stream is None:
+        stream = torch.cuda.current_stream(solid.device)
+    with torch.cuda.device(solid.device):
+        lbf.check(L.lbf_ch_smooth_noalloc(C.byref(p), C.c_void_p(solid.data_ptr()),
+                                          C.c_void_p(out.data_ptr()), int(iterations),
+                                          C.c_void_p(stream.cuda_stream)))
     return out
 
 

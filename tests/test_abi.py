@@ -253,3 +253,24 @@ def test_last_error_is_per_thread(L):
     t.join()
     assert other["rc"] == -1 and "pcm_floor" in other["msg"]
     assert "lattice size" in L.lbf_last_error().decode()
+
+
+def test_ch_noalloc_refuses_on_host(L):
+    """The allocation-free smoothing validates like lbf_ch_smooth and
+    refuses images above its stated maximum before any device call."""
+    from paper_2510_18688_amd import porous
+    porous._declare(L)
+    n_max = L.lbf_ch_noalloc_max_nodes()
+    assert n_max == 1 << 22
+    out = (C.c_float * 4)(3.0, 3.0, 3.0, 3.0)
+    buf = (C.c_uint8 * 4)()
+    p = porous.ch_params((2, 2, n_max // 4 + 1), (True, True, True))
+    rc = L.lbf_ch_smooth_noalloc(C.byref(p), buf, out, 1, None)
+    assert rc == -1 and "allocation-free limit" in L.lbf_last_error().decode()
+    p = porous.ch_params((8, 8), (False, False))
+    p.dt = 0.05
+    rc = L.lbf_ch_smooth_noalloc(C.byref(p), buf, out, 1, None)
+    assert rc == -1 and "stability bound" in L.lbf_last_error().decode()
+    assert L.lbf_ch_smooth_noalloc(C.byref(p), None, out, 1, None) == -1
+    assert L.lbf_ch_smooth_noalloc(None, buf, out, 1, None) == -1
+    assert list(out) == [3.0, 3.0, 3.0, 3.0]
