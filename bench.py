@@ -23,16 +23,22 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Algorithmic HBM bytes per lattice-node update, the method's own count:
-# 27 distributions and 5 lagged fields (f_s, Q = rho C_p T mdot, (phi u)_x,
-# (phi u)_y, p) read and written in FP32, and 3 static fields read (phi0,
-# cos theta, lap phi0).  The roofline is priced at this count.
+# Algorithmic HBM bytes per lattice-node update, the method's own count with
+# the phase-field source taken from the model's mass source: 27 distributions
+# and 5 lagged fields (f_s, Q = rho C_p T mdot, (phi u)_x, (phi u)_y, p) read
+# and written in FP32, and 3 static fields read (phi0, cos theta, lap phi0).
+# The roofline is priced at this count.
 BYTES_PER_LU = (27 + 5) * 2 * 4 + 3 * 4
-# What this implementation's step kernel moves by design: the same 27
-# distributions plus 7 lagged planes (the 5 fields and the high parts of the
-# float-float rest populations g_0, h_0) read and written, and 2 static
+# The same count with the source from the flow's own divergence (the default
+# reading): the previous step's velocity is needed as well, and (phi u) of
+# the previous step is then the product of phi and u, so the lagged fields
+# are f_s, Q, phi, p, u_x, u_y.
+METHOD_BYTES_PER_LU = (27 + 6) * 2 * 4 + 3 * 4
+# What this implementation's step kernel moves by design: those 27
+# distributions and 6 lagged fields plus the high parts of the float-float
+# rest populations g_0, h_0 (8 lagged planes) read and written, and 2 static
 # planes read (phi0, cos theta; lap phi0 is formed from phi0 in the kernel).
-IMPL_BYTES_PER_LU = (27 + 7) * 2 * 4 + 2 * 4
+IMPL_BYTES_PER_LU = (27 + 8) * 2 * 4 + 2 * 4
 HBM_PEAK_GBS = 8000.0
 # D3Q19, two kernels per step.  Moments pass: g and h pulled (38 planes), the
 # high parts of g_0, h_0, f_s, Q and p of the previous step, phi0 read; a
@@ -426,6 +432,8 @@ def main():
     kms = sim.last_step_kernel_ms()
     sim.set_timing(False)
     red = sim.reduce()
+    # the same access pattern with no arithmetic: the ceiling the step can reach
+    copy_ms, copy_bytes = sim.copy_probe(max(args.steps, 20))
 
     # observables: column and row profiles of the final state
     from paper_2510_18688_amd import observe
@@ -469,10 +477,22 @@ def main():
                      "impl_bytes_per_lu": IMPL_BYTES_PER_LU,
                      "impl_frac": round(IMPL_BYTES_PER_LU * nodes / (kms * 1e-3) / 1e9
                                         / HBM_PEAK_GBS, 4),
+                     "method_bytes_per_lu": METHOD_BYTES_PER_LU,
+                     "method_frac": round(METHOD_BYTES_PER_LU * nodes / (kms * 1e-3) / 1e9
+                                          / HBM_PEAK_GBS, 4),
                      "traffic_bytes_per_launch": counters and counters["hbm_bytes_per_launch"],
                      "traffic_bytes_per_lu": traffic_per_lu,
                      "traffic_over_algorithmic": counters and round(
                          counters["hbm_bytes_per_launch"] / (BYTES_PER_LU * nodes), 4)},
+        "copy_ceiling": {"kernel": "k_copy_probe (the step's planes, tiles and row order; "
+                                   "no arithmetic)",
+                         "ms": round(copy_ms, 5),
+                         "bytes_per_lu": round(copy_bytes / nodes, 1),
+                         "gbs": round(copy_bytes / (copy_ms * 1e-3) / 1e9, 1),
+                         "frac": round(copy_bytes / (copy_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                         # the step's bandwidth (its own bytes) over the copy's
+                         "step_bw_over_copy": round(IMPL_BYTES_PER_LU * nodes / kms
+                                                    / (copy_bytes / copy_ms), 4)},
         "checks": {"nonfinite": red["nonfinite"], "umax": red["umax"]},
         "observables": {"profiles_ms": round(prof_ms, 3),
                         "solid_fraction": observe.solid_fraction(prof),

@@ -274,6 +274,20 @@ int lbf_load_state(lbf_sim* sim, const void* src_device, size_t bytes);
 int lbf_set_timing(lbf_sim* sim, int32_t on);
 double lbf_last_step_kernel_ms(const lbf_sim* sim);
 
+/* Measurement aid (no passage of the paper defines it): the HBM ceiling of
+ * the step kernel's own access pattern.  Runs `launches` launches of a kernel
+ * that, with the simulation's tile shape, tile order and row order, copies
+ * every plane a step reads to the plane it writes (the 27 distributions and
+ * the lagged planes in use) and reads the static planes the step reads, with
+ * no arithmetic.  The copies go to the buffers the next step overwrites, so
+ * the simulation's state is unchanged.  On success *ms_per_launch receives
+ * the average launch duration (HIP events on the simulation's stream; the
+ * call waits for them) and *bytes_per_launch the bytes one launch moves.
+ * LBF_ESTATE before the state is set, LBF_EINVAL for launches < 1 or NULL
+ * outputs. */
+int lbf_copy_probe(lbf_sim* sim, int32_t launches, double* ms_per_launch,
+                   double* bytes_per_launch);
+
 const char* lbf_last_error(void);
 void lbf_destroy(lbf_sim* sim);
 

@@ -366,11 +366,12 @@ __device__ __forceinline__ void collide3_f(const Coll3& c, float* fv) {
 // (ghi, gv[0]).
 __device__ __forceinline__ void collide3_g(const Phys& ph, const Mom& m, const Coll3& c,
                                            float* gv, float& ghi) {
+  const float mu1 = wgt(1) * c.mu, mu7 = wgt(7) * c.mu;
+  const float mrest = 6.0f * mu1 + 12.0f * mu7;
 #pragma unroll
   for (int i = 0; i < NQ; ++i) {
     const float cj = cx(i) * c.j[0] + cy(i) * c.j[1] + cz(i) * c.j[2];
-    const float geq = (i == 0 ? m.dphi : 0.0f) + (wgt(i) - (i == 0 ? 1.0f : 0.0f)) * c.mu +
-                      3.0f * wgt(i) * cj;
+    const float geq = (i == 0 ? m.dphi - mrest : (i <= 6 ? mu1 : mu7)) + 3.0f * wgt(i) * cj;
     const float Gi =
         wgt(i) * (3.0f * (cx(i) * c.dj[0] + cy(i) * c.dj[1] + cz(i) * c.dj[2]) + c.pm);
     gv[i] = gv[i] - (gv[i] - geq) * ph.inv_tau_g + ph.pg * Gi;
@@ -383,12 +384,18 @@ __device__ __forceinline__ void collide3_g(const Phys& ph, const Mom& m, const C
 __device__ __forceinline__ void collide3_h(const Phys& ph, const Mom& m, const Coll3& c,
                                            float phi0, float ref_h, float* hv, float& hhi) {
   const float w0 = wgt(0);
+  // rest term from the same rounded products as the moving ones, so that
+  // the equilibria sum to rho H in FP32 without a systematic bias (the 2D
+  // collision gives the reason)
+  const float E1 = wgt(1) * c.ET, E7 = wgt(7) * c.ET;
+  const float Erest = 6.0f * E1 + 12.0f * E7;
   float heq[NQ];
 #pragma unroll
   for (int i = 0; i < NQ; ++i) {
     const float cu = cx(i) * c.u[0] + cy(i) * c.u[1] + cz(i) * c.u[2];
-    heq[i] = (i == 0) ? m.dH - (1.0f - w0) * c.ET - 1.5f * w0 * c.cT * c.uu
-                      : wgt(i) * (c.ET + c.cT * (3.0f * cu + 4.5f * cu * cu - 1.5f * c.uu));
+    heq[i] = (i == 0) ? m.dH - Erest - 1.5f * w0 * c.cT * c.uu
+                      : (i <= 6 ? E1 : E7) +
+                            wgt(i) * c.cT * (3.0f * cu + 4.5f * cu * cu - 1.5f * c.uu);
   }
   float hn[NQ];
 #pragma unroll
@@ -401,10 +408,10 @@ __device__ __forceinline__ void collide3_h(const Phys& ph, const Mom& m, const C
   if (ph.subfix && phi0 >= 0.5f) {
     const float Tw = ph.T_sub;
     const float rH = lbf::enthalpy_at(ph, Tw, m.Ksol, m.Kliq, m.chi);
-    const float EW = ph.Eref * Tw;
+    const float W1 = wgt(1) * ph.Eref * Tw, W7 = wgt(7) * ph.Eref * Tw;
 #pragma unroll
     for (int i = 0; i < NQ; ++i)
-      hn[i] = (i == 0) ? (rH - ref_h) - (1.0f - wgt(0)) * EW : wgt(i) * EW;
+      hn[i] = (i == 0) ? (rH - ref_h) - (6.0f * W1 + 12.0f * W7) : (i <= 6 ? W1 : W7);
   }
 #pragma unroll
   for (int i = 1; i < NQ; ++i) hv[i] = hn[i];

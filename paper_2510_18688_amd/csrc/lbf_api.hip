@@ -232,6 +232,20 @@ __global__ void k_unstream(Geo G, Phys ph, const float* tmp, float* dst, float* 
   lag[LAG_HHI * P + k] = tmp[18 * P + k];
   dst[9 * P + k] = 0.0f;
   dst[18 * P + k] = 0.0f;
+  if (ph.phi_src_flow) {
+    // the step keeps the previous step's phi in place of (phi u)_x: recover it
+    // from the caller's (phi u) and u (any value serves where u = 0)
+    const float jx = lag[LAG_JX * P + k], jy = lag[LAG_JY * P + k];
+    const float ux = lag[LAG_UX * P + k], uy = lag[LAG_UY * P + k];
+    float ph_prev = 0.0f;
+    if (fabsf(ux) >= fabsf(uy)) {
+      if (ux != 0.0f) ph_prev = jx / ux;
+    } else {
+      ph_prev = jy / uy;
+    }
+    lag[LAG_JX * P + k] = ph_prev;
+    lag[LAG_JY * P + k] = 0.0f;
+  }
 #pragma unroll
   for (int j = 1; j < 9; ++j) {
     // destination of population j leaving (x, y)
@@ -283,6 +297,57 @@ __global__ void k_reduce_blocks(const double* part, int nblocks, double* out) {
     if (threadIdx.x == 0) out[j] = s[0];
     __syncthreads();
   }
+}
+
+// Measurement aid: the step kernel's HBM access pattern without its
+// arithmetic.  Same strips (xcd_tile order, WX columns, CY rows, even tile
+// rows marching up and odd ones down) and the same buffer loads and
+// non-temporal stores; every plane the step reads is copied to the plane it
+// writes, the static planes are only read (their sum guards a store that
+// never happens, so the loads stay).
+template <int WX>
+__global__ __launch_bounds__(WX) void k_copy_probe(Geo G, Phys ph, BufArgs A, int CY, int nbx,
+                                                   int ntiles) {
+  const Bufs B = make_bufs(A, G.P);
+  const int t = xcd_tile(blockIdx.x, ntiles);
+  const int bx = t % nbx, by = t / nbx;
+  const int x = bx * WX + (int)threadIdx.x;
+  if (x >= G.nx) return;
+  const int y0 = by * CY, y1 = min(y0 + CY, G.ny);
+  const bool up = !(by & 1);
+  const int P = G.P;
+  const bool flow = ph.phi_src_flow != 0;
+  float acc = 0.0f;
+  for (int it = 0; it < y1 - y0; ++it) {
+    const int y = up ? y0 + it : y1 - 1 - it;
+    const int k = y * G.nx + x;
+    float v[27 + NLAG];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      v[i] = ldp(B.fin, i, P, k);
+      v[9 + i] = ldp(B.gin, i, P, k);
+      v[18 + i] = ldp(B.hin, i, P, k);
+    }
+#pragma unroll
+    for (int j = 0; j < NLAG; ++j) {
+      const bool used = flow ? j != LAG_JY : j < LAG_UX;
+      v[27 + j] = used ? ldp(B.lin, j, P, k) : 0.0f;
+    }
+    acc += ldp(B.stat, ST_PHI0, P, k) + ldp(B.stat, ST_CTH, P, k);
+    if (ph.subfix == 2) acc += ldp(B.stat, ST_THOLD, P, k);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      stp(B.fout, i, P, k, v[i]);
+      stp(B.gout, i, P, k, v[9 + i]);
+      stp(B.hout, i, P, k, v[18 + i]);
+    }
+#pragma unroll
+    for (int j = 0; j < NLAG; ++j) {
+      const bool used = flow ? j != LAG_JY : j < LAG_UX;
+      if (used) stp(B.lout, j, P, k, v[27 + j]);
+    }
+  }
+  if (acc == -1.0e30f) stp(B.lout, LAG_FS, P, y0 * G.nx + x, acc);
 }
 
 // ------------------------------------------------------------ launches
@@ -742,6 +807,44 @@ int lbf_set_timing(lbf_sim* s, int32_t on) {
 }
 
 double lbf_last_step_kernel_ms(const lbf_sim* s) { return s ? s->last_ms : 0.0; }
+
+int lbf_copy_probe(lbf_sim* s, int32_t launches, double* ms_per_launch,
+                   double* bytes_per_launch) {
+  if (!s || !ms_per_launch || !bytes_per_launch) return fail(LBF_EINVAL, "NULL argument");
+  if (launches < 1) return fail(LBF_EINVAL, "launches %d", launches);
+  if (!s->have_init) return fail(LBF_ESTATE, "the state must be set before lbf_copy_probe");
+  dim3 g2;
+  const int nt = grid_blocks(s, g2);
+  const int nbx = (int)g2.x;
+  BufArgs B = make_args(s);
+  HIP_TRY(hipEventRecord(s->ev0, s->stream));
+  for (int i = 0; i < launches; ++i) {
+    switch (s->tile_x) {
+      case 64:
+        hipLaunchKernelGGL(k_copy_probe<64>, dim3(nt), dim3(64), 0, s->stream, s->G, s->ph, B,
+                           s->tile_y, nbx, nt);
+        break;
+      case 128:
+        hipLaunchKernelGGL(k_copy_probe<128>, dim3(nt), dim3(128), 0, s->stream, s->G, s->ph, B,
+                           s->tile_y, nbx, nt);
+        break;
+      default:
+        hipLaunchKernelGGL(k_copy_probe<256>, dim3(nt), dim3(256), 0, s->stream, s->G, s->ph, B,
+                           s->tile_y, nbx, nt);
+        break;
+    }
+    HIP_TRY(hipGetLastError());
+  }
+  HIP_TRY(hipEventRecord(s->ev1, s->stream));
+  HIP_TRY(hipEventSynchronize(s->ev1));
+  float ms = 0.0f;
+  HIP_TRY(hipEventElapsedTime(&ms, s->ev0, s->ev1));
+  *ms_per_launch = (double)ms / launches;
+  const int lag = s->ph.phi_src_flow ? NLAG - 1 : NLAG - 2;   // planes in use
+  const int stat = 2 + (s->ph.subfix == 2 ? 1 : 0);
+  *bytes_per_launch = (double)s->G.nx * s->G.ny * 4.0 * (2.0 * (NDIST + lag) + stat);
+  return LBF_OK;
+}
 
 }  // extern "C"
 

@@ -10,7 +10,8 @@
 //   lagged fields  9 planes: f_s, Q = rho C_p T mdot, (phi u)_x, (phi u)_y, p
 //                  of the previous step, the high parts of g_0 and h_0, and
 //                  the previous step's velocity u_x, u_y (written and read only
-//                  when the phase-field source takes its divergence);
+//                  when the phase-field source takes its divergence; then the
+//                  (phi u)_x plane holds phi and (phi u)_y is not used);
 //   static fields  4 planes: phi0, cos(theta), lap(phi0), and the temperature
 //                  of the per-node isothermal region (NaN where not held).
 // Both distributions and lagged fields are double-buffered (ping-pong).
@@ -35,7 +36,10 @@ constexpr int NRED = 11;
 
 // lagged planes: f_s, Q = rho C_p T mdot, (phi u)_x, (phi u)_y, p of the
 // previous step, the high parts of the rest populations g_0, h_0, and the
-// previous step's velocity
+// previous step's velocity.  When the phase-field source takes the flow's
+// divergence (the velocity planes in use), the (phi u)_x plane holds the
+// previous step's phi instead and the (phi u)_y plane is unused: (phi u) is
+// their product.
 enum {
   LAG_FS = 0, LAG_Q = 1, LAG_JX = 2, LAG_JY = 3, LAG_P = 4, LAG_GHI = 5, LAG_HHI = 6,
   LAG_UX = 7, LAG_UY = 8
@@ -547,13 +551,16 @@ __device__ __forceinline__ void collide_node(const Phys& ph, const Mom& m, const
   const float pg = ph.pg;
   const float djx = jx - jx_prev, djy = jy - jy_prev;
   const float pm = phi * m.divu;
+  // chemical-potential parts of g^eq; the rest term from the same rounded
+  // products, so that the equilibria sum to phi (as for the enthalpy below)
+  const float mu1 = wgt(1) * mu, mu5 = wgt(5) * mu;
+  const float mrest = 4.0f * mu1 + 4.0f * mu5;
   if (!(MRT && ph.mrt && ph.s_g > 0.0f)) {
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
       const float cj = cx(i) * jx + cy(i) * jy;
       // rest population: equilibrium relative to the node's reference
-      const float geq = (i == 0 ? m.dphi : 0.0f) + (wgt(i) - (i == 0 ? 1.0f : 0.0f)) * mu +
-                        3.0f * wgt(i) * cj;
+      const float geq = (i == 0 ? m.dphi - mrest : (i <= 4 ? mu1 : mu5)) + 3.0f * wgt(i) * cj;
       const float Gi = wgt(i) * (3.0f * (cx(i) * djx + cy(i) * djy) + pm);
       gv[i] = gv[i] - (gv[i] - geq) * inv_tau_g + pg * Gi;
     }
@@ -565,8 +572,7 @@ __device__ __forceinline__ void collide_node(const Phys& ph, const Mom& m, const
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
       const float cj = cx(i) * jx + cy(i) * jy;
-      const float geq = (i == 0 ? m.dphi : 0.0f) + (wgt(i) - (i == 0 ? 1.0f : 0.0f)) * mu +
-                        3.0f * wgt(i) * cj;
+      const float geq = (i == 0 ? m.dphi - mrest : (i <= 4 ? mu1 : mu5)) + 3.0f * wgt(i) * cj;
       const float Gi = wgt(i) * (3.0f * (cx(i) * djx + cy(i) * djy) + pm);
       const float neq = gv[i] - geq + 0.5f * Gi;
       gv[i] = gv[i] - inv_tau_g * neq + Gi;
@@ -589,13 +595,20 @@ __device__ __forceinline__ void collide_node(const Phys& ph, const Mom& m, const
   // enthalpy, TRT (Sec. 3.3, eq22)
   const float ET = ph.Eref * T;
   const float cT = rhocp * T;
+  // The equilibria must sum to rho H.  In FP32, (1 - w_0) rho_ref C_p,ref T
+  // and the eight rounded products w_i rho_ref C_p,ref T differ by a bias of
+  // about 2e-8 of the product (1 - w_0 rounds low against the weights' sum),
+  // which every collision would add to the node's energy; the rest term is
+  // therefore formed from the same rounded products as the moving ones.
+  const float E1 = wgt(1) * ET, E5 = wgt(5) * ET;
+  const float Erest = 4.0f * E1 + 4.0f * E5;   // each 4x product exact
   float heq[9];
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
     const float cu = cx(i) * ux + cy(i) * uy;
     // rest population relative to the node's reference: rhoH - ref_h = dH
-    heq[i] = (i == 0) ? m.dH - (1.0f - wgt(0)) * ET - 1.5f * wgt(0) * cT * uu
-                      : wgt(i) * (ET + cT * (3.0f * cu + 4.5f * cu * cu - 1.5f * uu));
+    heq[i] = (i == 0) ? m.dH - Erest - 1.5f * wgt(0) * cT * uu
+                      : (i <= 4 ? E1 : E5) + wgt(i) * cT * (3.0f * cu + 4.5f * cu * cu - 1.5f * uu);
   }
   const float ps = ph.src_tau_a ? (1.0f - 0.5f * inv_tau_a) : (1.0f - 0.5f * inv_tau_s);
   float hn[9];
@@ -613,11 +626,12 @@ __device__ __forceinline__ void collide_node(const Phys& ph, const Mom& m, const
     // (rest population relative to its reference)
     const float rH = enthalpy_at(ph, Tw, m.Ksol, m.Kliq, m.chi);
     const float EW = ph.Eref * Tw;
+    const float W1 = wgt(1) * EW, W5 = wgt(5) * EW;
     float before = 0.0f, after = 0.0f;
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
       before += hn[i];
-      const float e = (i == 0) ? (rH - ref_h) - (1.0f - wgt(0)) * EW : wgt(i) * EW;
+      const float e = (i == 0) ? (rH - ref_h) - (4.0f * W1 + 4.0f * W5) : (i <= 4 ? W1 : W5);
       after += e;
       hn[i] = e;
     }

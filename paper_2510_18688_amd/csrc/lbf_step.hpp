@@ -10,6 +10,10 @@
 // each end of the strip.  The two halo columns of all CY + 2 rows are
 // computed up front by the whole block (one node per lane) and copied into
 // the ring row by row, so no lane diverges per row.  One barrier per row.
+// When the phase-field source takes the divergence of the previous step's
+// velocity, that velocity sits in a second four-row ring, filled two rows
+// ahead of the moments that read it, so each node's velocity is loaded
+// once per block instead of once per stencil neighbour.
 #pragma once
 #include "lbf_device.hpp"
 
@@ -24,6 +28,7 @@ template <int WX>
 struct StepShared {
   float v[NSV][4][WX + 2];        // [phi, fs, rho, p_prev, phi0][ring slot][column]
   float halo[NSV][2][CY_MAX + 2]; // [field][left, right][row - (y0 - 1)]
+  float u[2][4][WX + 2];          // previous step's velocity [x, y][ring slot][column]
   double red[WX / 64][NRED];
 };
 
@@ -35,6 +40,7 @@ struct NodeIn {
   float flux, fsp, Qp, phi0, ghi, hhi, pprev;
   float dlag;   // divergence of the previous step's velocity at the node
                 // (phase-field source from the flow's divergence)
+  float uxc, uyc;   // the previous step's velocity at the node itself (same source)
 };
 
 // Isotropic divergence 3 sum_i w_i c_i . u(x + c_i) from the velocity
@@ -52,11 +58,12 @@ __device__ __forceinline__ float div9(const float* ux, const float* uy) {
   return 3.0f * ((1.0f / 9.0f) * ax + (1.0f / 36.0f) * dg);
 }
 
-// With the phase-field source from the flow's divergence, also gather the
-// previous step's velocity at the eight neighbours (periodic wrap or the
-// mirror ghost, as for every stencil) and form its divergence.
+// With the phase-field source from the flow's divergence and `gather_u`,
+// also gather the previous step's velocity at the eight neighbours (periodic
+// wrap or the mirror ghost, as for every stencil) and form its divergence;
+// without `gather_u` the caller supplies in.dlag (from the velocity ring).
 __device__ __forceinline__ void node_load(const Geo& G, const Phys& ph, const Bufs& B, int xx,
-                                          int yy, NodeIn& in) {
+                                          int yy, NodeIn& in, bool gather_u = true) {
   in.flux = 0.0f;
   pull_gh(G, ph, B, xx, yy, in.g, in.h, in.flux);
   const int k = yy * G.nx + xx;
@@ -67,7 +74,9 @@ __device__ __forceinline__ void node_load(const Geo& G, const Phys& ph, const Bu
   in.hhi = ldp(B.lin, LAG_HHI, G.P, k);
   in.pprev = ldp(B.lin, LAG_P, G.P, k);
   in.dlag = 0.0f;
-  if (ph.phi_src_flow) {
+  if (ph.phi_src_flow && gather_u) {
+    in.uxc = ldp(B.lin, LAG_UX, G.P, k);
+    in.uyc = ldp(B.lin, LAG_UY, G.P, k);
     float ux[9], uy[9];
 #pragma unroll
     for (int i = 1; i < 9; ++i) {
@@ -76,6 +85,61 @@ __device__ __forceinline__ void node_load(const Geo& G, const Phys& ph, const Bu
       uy[i] = cy(i) ? ldp(B.lin, LAG_UY, G.P, kk) : 0.0f;
     }
     in.dlag = div9(ux, uy);
+  }
+}
+
+// Divergence of the previous step's velocity at column l of ring row `row`
+// (rows row - 1, row, row + 1 of the velocity ring; the same neighbours and
+// arithmetic as the gather in node_load, so both give the same bits).
+template <int WX>
+__device__ __forceinline__ float ring_div(const StepShared<WX>& sh, int l, int row) {
+  float ux[9], uy[9];
+#pragma unroll
+  for (int i = 1; i < 9; ++i) {
+    const int slot = (row + cy(i)) & 3, col = l + 1 + cx(i);
+    ux[i] = cx(i) ? sh.u[0][slot][col] : 0.0f;
+    uy[i] = cy(i) ? sh.u[1][slot][col] : 0.0f;
+  }
+  return div9(ux, uy);
+}
+
+// Previous step's velocity of one ring row: a lane's own node, and for the
+// first and last active lanes the halo column beyond them (x wrapped or
+// mirrored like every stencil neighbour).
+struct URow {
+  float x, y;      // at the lane's node
+  float lx, ly;    // left halo column (lane 0)
+  float rx, ry;    // right halo column (last active lane)
+};
+
+__device__ __forceinline__ void urow_load(const Geo& G, const Bufs& B, int x, int xl, int xr,
+                                          int yy, bool left, bool right, URow& u) {
+  const int row = yy * G.nx;
+  u.x = ldp(B.lin, LAG_UX, G.P, row + x);
+  u.y = ldp(B.lin, LAG_UY, G.P, row + x);
+  if (left) {
+    u.lx = ldp(B.lin, LAG_UX, G.P, row + xl);
+    u.ly = ldp(B.lin, LAG_UY, G.P, row + xl);
+  }
+  if (right) {
+    u.rx = ldp(B.lin, LAG_UX, G.P, row + xr);
+    u.ry = ldp(B.lin, LAG_UY, G.P, row + xr);
+  }
+}
+
+template <int WX>
+__device__ __forceinline__ void urow_store(StepShared<WX>& sh, int l, int lastl, int row,
+                                           const URow& u) {
+  const int s = row & 3;
+  sh.u[0][s][l + 1] = u.x;
+  sh.u[1][s][l + 1] = u.y;
+  if (l == 0) {
+    sh.u[0][s][0] = u.lx;
+    sh.u[1][s][0] = u.ly;
+  }
+  if (l == lastl) {
+    sh.u[0][s][lastl + 2] = u.rx;
+    sh.u[1][s][lastl + 2] = u.ry;
   }
 }
 
@@ -96,10 +160,13 @@ __device__ __forceinline__ void node_finish(const Phys& ph, const NodeIn& in, Mo
   st[3] = in.pprev;
 }
 
-// Flow populations and node data the collision reads.
+// Flow populations and node data the collision reads.  With the phase-field
+// source from the flow's divergence the previous step's (phi u) is not
+// stored: the previous step's phi is (in the plane of (phi u)_x) and the
+// velocity is anyway, and their product is the stored (phi u) bit for bit.
 struct FlowIn {
   float f[9];
-  float cth, lap0, jxp, jyp, thold;
+  float cth, lap0, jxp, jyp, thold;   // jxp: phi of the previous step in that case
 };
 
 // LAP0 = false leaves lap0 to the caller (the step kernel takes it from its
@@ -112,7 +179,7 @@ __device__ __forceinline__ void flow_load(const Geo& G, const Phys& ph, const Bu
   in.cth = ldp(B.stat, ST_CTH, G.P, k);
   in.lap0 = LAP0 ? ldp(B.stat, ST_LAP0, G.P, k) : 0.0f;
   in.jxp = ldp(B.lin, LAG_JX, G.P, k);
-  in.jyp = ldp(B.lin, LAG_JY, G.P, k);
+  in.jyp = ph.phi_src_flow ? 0.0f : ldp(B.lin, LAG_JY, G.P, k);
   // the per-node held temperature is read only when that region is in use
   in.thold = ph.subfix == 2 ? ldp(B.stat, ST_THOLD, G.P, k) : 0.0f;
 }
@@ -163,13 +230,33 @@ __device__ __forceinline__ void step_strip(const Geo& G, const Phys& ph, const B
   FlowIn fin;        // flow data of the current row (in flight)
   FlowIn fnx;        // flow data of the next row, in flight
   Mom cm;
+  // velocity ring (divergence source only): rows ys .. ys + 2 dir now, the
+  // row after them in flight; the moments of rows ys - dir and ys gather
+  // their neighbours' velocity themselves, and so does a ghost row beyond a
+  // y wall (its moments are the mirrored row's, whose divergence is taken
+  // around that row, not around the ghost row's place in the ring)
+  const bool uring = ph.phi_src_flow != 0;
+  auto ring_row = [&](int r) { return uring && (G.py || (r >= 0 && r < G.ny)); };
+  const int xl = map_axis(x0 - 1, G.nx, G.px);
+  const int xr = map_axis(x0 + lastl + 1, G.nx, G.px);
+  URow un;
+  if (act && uring) {
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      URow u0;
+      urow_load(G, B, x, xl, xr, map_axis(ys + r * dir, G.ny, G.py), l == 0, l == lastl, u0);
+      urow_store(sh, l, lastl, ys + r * dir, u0);
+    }
+    if (nrow > 1)
+      urow_load(G, B, x, xl, xr, map_axis(ys + 3 * dir, G.ny, G.py), l == 0, l == lastl, un);
+  }
   if (act) {
     NodeIn bin;
     Mom m;
     float st[NSV];
     node_load(G, ph, B, x, map_axis(ys - dir, G.ny, G.py), bin);
     node_load(G, ph, B, x, ys, cin);
-    node_load(G, ph, B, x, map_axis(ys + dir, G.ny, G.py), ain);
+    node_load(G, ph, B, x, map_axis(ys + dir, G.ny, G.py), ain, !ring_row(ys + dir));
     flow_load<false>(G, ph, B, x, ys, fin);
     node_finish(ph, bin, m, st);
     st[4] = bin.phi0;
@@ -209,13 +296,28 @@ __device__ __forceinline__ void step_strip(const Geo& G, const Phys& ph, const B
     NodeIn next_c;
     if (act) {
       float st[NSV];
+      if (uring) {
+        // rows y, ya, ya + dir of the velocity ring were filled before the
+        // last barrier; the row after them (slot of y - dir, no longer read)
+        // is stored now and the next one requested
+        if (ring_row(ya)) {
+          ain.dlag = ring_div(sh, l, ya);
+          ain.uxc = sh.u[0][ya & 3][l + 1];
+          ain.uyc = sh.u[1][ya & 3][l + 1];
+        }
+        if (more) {
+          urow_store(sh, l, lastl, y + 3 * dir, un);
+          if (it + 2 < nrow)
+            urow_load(G, B, x, xl, xr, map_axis(y + 4 * dir, G.ny, G.py), l == 0, l == lastl, un);
+        }
+      }
       node_finish(ph, ain, am, st);
       st[4] = ain.phi0;
 #pragma unroll
       for (int f = 0; f < NSV; ++f) sh.v[f][slot_n][l + 1] = st[f];
       next_c = ain;
       if (more) {
-        node_load(G, ph, B, x, map_axis(ya + dir, G.ny, G.py), ain);
+        node_load(G, ph, B, x, map_axis(ya + dir, G.ny, G.py), ain, !ring_row(ya + dir));
         flow_load<false>(G, ph, B, x, ya, fnx);   // before this row's collision
       }
     }
@@ -253,6 +355,9 @@ __device__ __forceinline__ void step_strip(const Geo& G, const Phys& ph, const B
       float* cg = cin.g;
       float* ch = cin.h;
       const float phi0 = cin.phi0, cQp = cin.Qp, crh = cin.hhi;
+      // lagged (phi u): stored, or the product of the previous step's phi and u
+      const float jxp = ph.phi_src_flow ? fin.jxp * cin.uxc : fin.jxp;
+      const float jyp = ph.phi_src_flow ? fin.jxp * cin.uyc : fin.jyp;
       if (RED) {
         a_sg += (double)cm.ref_g + (double)cm.sg;
         a_sh += (double)crh + (double)cm.sh;
@@ -262,7 +367,7 @@ __device__ __forceinline__ void step_strip(const Geo& G, const Phys& ph, const B
       }
       Post o;
       if (MODE != MODE_FIELDS) {
-        collide_node<true, MRT>(ph, cm, S, phi0, fin.cth, lap0, cQp, fin.jxp, fin.jyp, crh,
+        collide_node<true, MRT>(ph, cm, S, phi0, fin.cth, lap0, cQp, jxp, jyp, crh,
                                 fin.thold, fv, cg, ch, o);
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
@@ -272,8 +377,12 @@ __device__ __forceinline__ void step_strip(const Geo& G, const Phys& ph, const B
         }
         stp(B.lout, LAG_FS, P, k, cm.fs);
         stp(B.lout, LAG_Q, P, k, o.Q);
-        stp(B.lout, LAG_JX, P, k, o.jx);
-        stp(B.lout, LAG_JY, P, k, o.jy);
+        if (ph.phi_src_flow) {
+          stp(B.lout, LAG_JX, P, k, cm.phi);
+        } else {
+          stp(B.lout, LAG_JX, P, k, o.jx);
+          stp(B.lout, LAG_JY, P, k, o.jy);
+        }
         stp(B.lout, LAG_P, P, k, o.p);
         stp(B.lout, LAG_GHI, P, k, o.ghi);
         stp(B.lout, LAG_HHI, P, k, o.hhi);
@@ -292,7 +401,7 @@ __device__ __forceinline__ void step_strip(const Geo& G, const Phys& ph, const B
           a_reset += o.reset;
         }
       } else {
-        collide_node<false, MRT>(ph, cm, S, phi0, fin.cth, lap0, cQp, fin.jxp, fin.jyp, crh,
+        collide_node<false, MRT>(ph, cm, S, phi0, fin.cth, lap0, cQp, jxp, jyp, crh,
                                  fin.thold, fv, cg, ch, o);
         stp(B.fields, 0, P, k, cm.phi);
         stp(B.fields, 1, P, k, cm.T);

@@ -24,7 +24,8 @@ REDS = ["sum_g", "sum_h", "sum_fs", "sum_liq", "umax", "nonfinite", "src_phi", "
 EXPORTS = ["lbf_workspace_bytes", "lbf_create", "lbf_set_geometry", "lbf_set_wall_temperature",
            "lbf_init_fields", "lbf_set_isothermal", "lbf_step", "lbf_read_field", "lbf_read_fields", "lbf_reduce",
            "lbf_set_poststream_state", "lbf_set_tile", "lbf_get_tile", "lbf_state_bytes", "lbf_save_state",
-           "lbf_load_state", "lbf_set_timing", "lbf_last_step_kernel_ms", "lbf_last_error",
+           "lbf_load_state", "lbf_set_timing", "lbf_last_step_kernel_ms", "lbf_copy_probe",
+           "lbf_last_error",
            "lbf_destroy", "lbf_batch_create", "lbf_batch_set_tile", "lbf_batch_step",
            "lbf_batch_set_timing", "lbf_batch_last_step_ms", "lbf_batch_items",
            "lbf_batch_destroy", "lbf_tape_bytes", "lbf_tape_create", "lbf_tape_segment",
@@ -95,6 +96,7 @@ def load(path: str = LIB_PATH):
     L.lbf_save_state.argtypes = [vp, vp, C.c_size_t]
     L.lbf_load_state.argtypes = [vp, vp, C.c_size_t]
     L.lbf_set_timing.argtypes = [vp, i32]
+    L.lbf_copy_probe.argtypes = [vp, i32, d_p, d_p]
     L.lbf_last_step_kernel_ms.restype = C.c_double
     L.lbf_last_step_kernel_ms.argtypes = [vp]
     L.lbf_last_error.restype = C.c_char_p
@@ -292,6 +294,14 @@ class Sim:
 
     def set_timing(self, on: bool) -> None:
         check(_lib.lbf_set_timing(self.h, int(bool(on))))
+
+    def copy_probe(self, launches: int = 20):
+        """(ms per launch, bytes per launch) of a copy of the planes a step
+        reads and writes, in the step kernel's own tile and row order: the
+        bandwidth ceiling of its access pattern (the state is unchanged)."""
+        ms, nb = C.c_double(), C.c_double()
+        check(_lib.lbf_copy_probe(self.h, int(launches), C.byref(ms), C.byref(nb)))
+        return ms.value, nb.value
 
     def last_step_kernel_ms(self) -> float:
         return float(_lib.lbf_last_step_kernel_ms(self.h))

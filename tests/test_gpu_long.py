@@ -79,9 +79,6 @@ def test_sessile_drop_20000_steps(lbf_mod, oracle_mod):
                   [1000, 2000, 5000, 10000, 15000, 20000], "sessile_128x96")
 
 
-@pytest.mark.xfail(strict=False, reason="measured: the liquid fraction at the moving front "
-                   "reaches 2.2e-4 at step 10 000 (phi 3.7e-5, T 4.3e-5; 8.3e-5 and 8.4e-5 "
-                   "at 20 000), above the 1e-4 FP32 bar")
 def test_cold_cylinder_256_20000_steps(lbf_mod, oracle_mod):
     case = W.curved_substrate(n=256, R_s=50.0, R_0=37.5)
     _parity_curve(lbf_mod, oracle_mod, case, [2000, 5000, 10000, 20000], "cylinder_256")
