@@ -474,10 +474,11 @@ int lbf_create(const lbf_params* params, void* stream, void* workspace, size_t w
   fill_phys(params, s->ph);
   s->L = make_layout(params->nx, params->ny, params->plane_pad);
   s->stream = (hipStream_t)stream;
+  const size_t need = s->L.total;
   if (workspace) {
-    if (workspace_bytes < s->L.total) {
+    if (workspace_bytes < need) {
       delete s;
-      return fail(LBF_ENOMEM, "workspace of %zu bytes, %zu needed", workspace_bytes, s->L.total);
+      return fail(LBF_ENOMEM, "workspace of %zu bytes, %zu needed", workspace_bytes, need);
     }
     if ((uintptr_t)workspace % kAlign) {
       delete s;
@@ -486,9 +487,9 @@ int lbf_create(const lbf_params* params, void* stream, void* workspace, size_t w
     s->ws = (char*)workspace;
     s->owns_ws = false;
   } else {
-    if (hipMalloc((void**)&s->ws, s->L.total) != hipSuccess) {
+    if (hipMalloc((void**)&s->ws, need) != hipSuccess) {
       delete s;
-      return fail(LBF_ENOMEM, "hipMalloc of %zu bytes failed", s->L.total);
+      return fail(LBF_ENOMEM, "hipMalloc of %zu bytes failed", need);
     }
     s->owns_ws = true;
   }
