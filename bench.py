@@ -88,6 +88,9 @@ def parse():
                     help="steps of the 64-lattice batched workload (0 skips it)")
     ap.add_argument("--adjoint-steps", type=int, default=2000,
                     help="steps of the 256 x 256 gradient workload (0 skips it)")
+    ap.add_argument("--adjoint-hbm-steps", type=int, default=200,
+                    help="steps of the gradient workload at 2048 x 2048, where the state "
+                         "and the tape live in HBM (0 skips it)")
     ap.add_argument("--d3q19-steps", type=int, default=200,
                     help="steps of the D3Q19 workloads (0 skips them)")
     ap.add_argument("--small-steps", type=int, default=5000,
@@ -178,17 +181,19 @@ def batched(lbf, W, torch, steps):
             "nonfinite": sum(r["nonfinite"] for r in red)}
 
 
-def adjoint(lbf, W, torch, steps):
-    """Gradient workload: a drop on a slab over a cold wall, 256 x 256.  The
-    forward time of `steps` plain steps against the reverse sweep (segment
-    recomputation included) of the same run, for J = 1/2 sum (f_l - f_l*)^2
-    with respect to cos(theta) per node and the wall temperatures."""
-    case, th_t, tw_t = W.adjoint_case(steps=steps)
+def adjoint(lbf, W, torch, steps, n=256):
+    """Gradient workload: a drop on a slab over a cold wall, 256 x 256 (or
+    n x n with the drop scaled, for the HBM-resident form).  The forward time
+    of `steps` plain steps against the reverse sweep (segment recomputation
+    included) of the same run, for J = 1/2 sum (f_l - f_l*)^2 with respect to
+    cos(theta) per node and the wall temperatures."""
+    radius = 77.0 * n / 256
+    case, th_t, tw_t = W.adjoint_case(n=n, steps=steps, radius=radius)
     from paper_2510_18688_amd import autotune
     tile = autotune.lookup(case.nx, case.ny)
     # the target: final liquid fraction under the target controls (any
     # target gives the same work)
-    tcase, _, _ = W.adjoint_case(steps=steps)
+    tcase, _, _ = W.adjoint_case(n=n, steps=steps, radius=radius)
     tcase.cos_theta = np.broadcast_to(np.cos(np.radians(th_t))[None, :], (tcase.ny, tcase.nx)).copy()
     tcase.wall_T = {W.BOTTOM: np.asarray(tw_t, dtype=np.float64)}
     sim = lbf.Sim(tcase, tile=tile)
@@ -221,9 +226,11 @@ def adjoint(lbf, W, torch, steps):
     t_bwd = time.perf_counter() - t0
     seg = tape.segment
     tape.close()
-    return {"workload": f"{case.name}: drop R 77 on slab h_s 10 over a cold wall, "
+    sim.close()
+    torch.cuda.empty_cache()
+    return {"workload": f"{case.name}: drop R {radius:g} on slab h_s 10 over a cold wall, "
                         "J = 1/2 sum (f_l - f_l*)^2",
-            "steps": steps, "segment": seg, "J": J,
+            "nodes": case.nodes, "steps": steps, "segment": seg, "J": J,
             "grad_norm_cos_theta": float(gc.norm()), "grad_norm_wall_T": float(gw.norm()),
             "forward_ms": round(t_fwd * 1e3, 2), "tape_forward_ms": round(t_rec * 1e3, 2),
             "backward_ms": round(t_bwd * 1e3, 2),
@@ -503,6 +510,8 @@ def main():
         out["batched"] = batched(lbf, W, torch, args.batch_steps)
     if args.adjoint_steps > 0:
         out["adjoint"] = adjoint(lbf, W, torch, args.adjoint_steps)
+    if args.adjoint_hbm_steps > 0:
+        out["adjoint_hbm"] = adjoint(lbf, W, torch, args.adjoint_hbm_steps, n=2048)
     if args.mrt_steps > 0:
         out["mrt"] = mrt(lbf, W, torch, args.mrt_steps, tile, pad)
     if args.porous_steps > 0:

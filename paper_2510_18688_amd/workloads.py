@@ -311,13 +311,13 @@ def fourier_modes(n: int, rng: np.random.Generator, modes: int = 4) -> np.ndarra
     return s / np.max(np.abs(s))
 
 
-def adjoint_case(n: int = 256, steps: int = 2000):
+def adjoint_case(n: int = 256, steps: int = 2000, radius: float = 77.0):
     """Flat-wall drop for the gradient workload and its seeded target controls.
 
     Returns (case, theta_target_deg, Tw_target) where the target controls are
     90 deg + 15 deg s1(x) and -1 + 0.25 s2(x).
     """
-    case = slab_drop(n, n, 77.0, 90.0, -1.0, steps=steps, name=f"adjoint_{n}x{n}")
+    case = slab_drop(n, n, radius, 90.0, -1.0, steps=steps, name=f"adjoint_{n}x{n}")
     case.mat.phi_src_mdot = 1   # the phase-field source the reverse sweep differentiates
     rng = np.random.default_rng(5)
     s1 = fourier_modes(n, rng)
