@@ -35,10 +35,11 @@ BYTES_PER_LU = (27 + 5) * 2 * 4 + 3 * 4
 # are f_s, Q, phi, p, u_x, u_y.
 METHOD_BYTES_PER_LU = (27 + 6) * 2 * 4 + 3 * 4
 # What this implementation's step kernel moves by design: those 27
-# distributions and 6 lagged fields plus the high parts of the float-float
-# rest populations g_0, h_0 (8 lagged planes) read and written, and 2 static
-# planes read (phi0, cos theta; lap phi0 is formed from phi0 in the kernel).
-IMPL_BYTES_PER_LU = (27 + 8) * 2 * 4 + 2 * 4
+# distributions and 6 lagged fields plus one plane holding the 16-bit high
+# parts of the float-float rest populations g_0, h_0 (7 lagged planes) read
+# and written, and 2 static planes read (phi0, cos theta; lap phi0 is formed
+# from phi0 in the kernel).
+IMPL_BYTES_PER_LU = (27 + 7) * 2 * 4 + 2 * 4
 HBM_PEAK_GBS = 8000.0
 # D3Q19, two kernels per step.  Moments pass: g and h pulled (38 planes), the
 # high parts of g_0, h_0, f_s, Q and p of the previous step, phi0 read; a

@@ -130,10 +130,10 @@ typedef struct lbf_params {
    * discrete flow is not exactly divergence free: a drop freezing on a cold
    * wall, a drop dewetting a cylinder or a porous medium over thousands of
    * steps at a gas/liquid density ratio of 0.1 need it to stay stable; it
-   * stores the previous step's velocity (two more lagged planes, 16 more
-   * bytes per node update).  1: the model's mass source mdot of eq1 (sum phi
-   * changes by exactly sum phi mdot; stable only over shorter runs).  The
-   * adjoint (lbf_tape_*) supports 1 only. */
+   * stores the previous step's velocity and phi in place of (phi u) (one
+   * more lagged plane, 8 more bytes per node update).  1: the model's mass
+   * source mdot of eq1 (sum phi changes by exactly sum phi mdot; stable only
+   * over shorter runs).  The adjoint (lbf_tape_*) supports 1 only. */
   int32_t phi_src_mdot;
   int32_t reserved3;
   double s_b, s_q, s_g;
@@ -255,8 +255,8 @@ enum {
 };
 int lbf_profiles(lbf_sim* sim, double* col, double* row, int32_t dst_on_device);
 
-/* Launch shape of the step kernel: threads per block along x (64, 128, 256)
- * and rows per block along y (>= 1).  Defaults are chosen at creation. */
+/* Launch shape of the step kernel: threads per block along x (64, 128, 256,
+ * 512) and rows per block along y (>= 1).  Defaults are chosen at creation. */
 int lbf_set_tile(lbf_sim* sim, int32_t tile_x, int32_t tile_y);
 int lbf_get_tile(const lbf_sim* sim, int32_t* tile_x, int32_t* tile_y);
 

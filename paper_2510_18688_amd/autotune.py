@@ -19,7 +19,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 DB = os.path.join(HERE, "tiles.json")
 
 CANDIDATES: Tuple[Tuple[int, int], ...] = tuple(
-    (tx, ty) for tx in (64, 128, 256) for ty in (1, 2, 4, 8, 16, 32, 64, 128))
+    (tx, ty) for tx in (64, 128, 256, 512) for ty in (1, 2, 4, 8, 16, 32, 64, 128))
 
 
 def _load() -> dict:

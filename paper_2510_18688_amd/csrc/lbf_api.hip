@@ -228,10 +228,14 @@ __global__ void k_unstream(Geo G, Phys ph, const float* tmp, float* dst, float* 
   const long long P = G.P;
   const int k = y * G.nx + x;
   dst[k] = tmp[k];
-  lag[LAG_GHI * P + k] = tmp[9 * P + k];
-  lag[LAG_HHI * P + k] = tmp[18 * P + k];
-  dst[9 * P + k] = 0.0f;
-  dst[18 * P + k] = 0.0f;
+  // rest populations as float-float: 16-bit high parts (one plane), the
+  // exact remainders in the distribution planes
+  const float g0 = tmp[9 * P + k], h0 = tmp[18 * P + k];
+  const float gh = hi16(g0), hh = hi16(h0);
+  lag[LAG_GHI * P + k] = __builtin_bit_cast(float, pack_hi(gh, hh));
+  lag[LAG_HHI * P + k] = 0.0f;
+  dst[9 * P + k] = g0 - gh;
+  dst[18 * P + k] = h0 - hh;
   if (ph.phi_src_flow) {
     // the step keeps the previous step's phi in place of (phi u)_x: recover it
     // from the caller's (phi u) and u (any value serves where u = 0)
@@ -330,7 +334,7 @@ __global__ __launch_bounds__(WX) void k_copy_probe(Geo G, Phys ph, BufArgs A, in
     }
 #pragma unroll
     for (int j = 0; j < NLAG; ++j) {
-      const bool used = flow ? j != LAG_JY : j < LAG_UX;
+      const bool used = j != LAG_HHI && (flow ? j != LAG_JY : j < LAG_UX);
       v[27 + j] = used ? ldp(B.lin, j, P, k) : 0.0f;
     }
     acc += ldp(B.stat, ST_PHI0, P, k) + ldp(B.stat, ST_CTH, P, k);
@@ -343,7 +347,7 @@ __global__ __launch_bounds__(WX) void k_copy_probe(Geo G, Phys ph, BufArgs A, in
     }
 #pragma unroll
     for (int j = 0; j < NLAG; ++j) {
-      const bool used = flow ? j != LAG_JY : j < LAG_UX;
+      const bool used = j != LAG_HHI && (flow ? j != LAG_JY : j < LAG_UX);
       if (used) stp(B.lout, j, P, k, v[27 + j]);
     }
   }
@@ -404,6 +408,7 @@ int lbfi::launch_step_args(lbf_sim* s, int mode, bool red, BufArgs B, hipStream_
     case 64: return launch_wx<64>(s, mode, red, B, st);
     case 128: return launch_wx<128>(s, mode, red, B, st);
     case 256: return launch_wx<256>(s, mode, red, B, st);
+    case 512: return launch_wx<512>(s, mode, red, B, st);
     default: return fail(LBF_EINVAL, "tile_x %d", s->tile_x);
   }
 }
@@ -730,8 +735,8 @@ int lbf_reduce(lbf_sim* s, double* out) {
 
 int lbf_set_tile(lbf_sim* s, int32_t tile_x, int32_t tile_y) {
   if (!s) return fail(LBF_EINVAL, "sim is NULL");
-  if (tile_x != 64 && tile_x != 128 && tile_x != 256)
-    return fail(LBF_EINVAL, "tile_x must be 64, 128 or 256 (got %d)", tile_x);
+  if (tile_x != 64 && tile_x != 128 && tile_x != 256 && tile_x != 512)
+    return fail(LBF_EINVAL, "tile_x must be 64, 128, 256 or 512 (got %d)", tile_x);
   if (tile_y < 1 || tile_y > CY_MAX)
     return fail(LBF_EINVAL, "tile_y must be in [1, %d] (got %d)", CY_MAX, tile_y);
   s->tile_x = tile_x;
@@ -829,6 +834,10 @@ int lbf_copy_probe(lbf_sim* s, int32_t launches, double* ms_per_launch,
         hipLaunchKernelGGL(k_copy_probe<128>, dim3(nt), dim3(128), 0, s->stream, s->G, s->ph, B,
                            s->tile_y, nbx, nt);
         break;
+      case 512:
+        hipLaunchKernelGGL(k_copy_probe<512>, dim3(nt), dim3(512), 0, s->stream, s->G, s->ph, B,
+                           s->tile_y, nbx, nt);
+        break;
       default:
         hipLaunchKernelGGL(k_copy_probe<256>, dim3(nt), dim3(256), 0, s->stream, s->G, s->ph, B,
                            s->tile_y, nbx, nt);
@@ -841,7 +850,7 @@ int lbf_copy_probe(lbf_sim* s, int32_t launches, double* ms_per_launch,
   float ms = 0.0f;
   HIP_TRY(hipEventElapsedTime(&ms, s->ev0, s->ev1));
   *ms_per_launch = (double)ms / launches;
-  const int lag = s->ph.phi_src_flow ? NLAG - 1 : NLAG - 2;   // planes in use
+  const int lag = s->ph.phi_src_flow ? NLAG - 2 : NLAG - 3;   // planes in use
   const int stat = 2 + (s->ph.subfix == 2 ? 1 : 0);
   *bytes_per_launch = (double)s->G.nx * s->G.ny * 4.0 * (2.0 * (NDIST + lag) + stat);
   return LBF_OK;

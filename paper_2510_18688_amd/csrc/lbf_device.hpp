@@ -189,12 +189,37 @@ __device__ __forceinline__ void stp(Rsrc r, int plane, int P, int k, float v) {
 // division: the FP32 path's accuracy is set by its storage, not by this.
 __device__ __forceinline__ float rcp(float v) { return __builtin_amdgcn_rcpf(v); }
 
+// High parts of the float-float rest populations are kept to 16 bits (the
+// upper half of their FP32 pattern, i.e. truncated to a bfloat16 value), so
+// that the high parts of g_0 and h_0 share one 32-bit plane.
+__device__ __forceinline__ float hi16(float v) {
+  return __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, v) & 0xFFFF0000u);
+}
+__device__ __forceinline__ uint32_t pack_hi(float ghi, float hhi) {
+  return (__builtin_bit_cast(uint32_t, ghi) >> 16) | (__builtin_bit_cast(uint32_t, hhi) & 0xFFFF0000u);
+}
+__device__ __forceinline__ float unpack_ghi(uint32_t p) { return __builtin_bit_cast(float, p << 16); }
+__device__ __forceinline__ float unpack_hhi(uint32_t p) {
+  return __builtin_bit_cast(float, p & 0xFFFF0000u);
+}
+
 // Exact two-sum: hi + d = s + err with s = fl(hi + d) (no reassociation of
 // these additions is allowed, and none involves a product to contract).
 __device__ __forceinline__ void two_sum(float hi, float d, float& s, float& err) {
   s = hi + d;
   const float bb = s - hi;
   err = (hi - (s - bb)) + (d - bb);
+}
+
+// Renormalise a float-float pair (reference hi, deviation d) to a 16-bit high
+// part and an FP32 low part: hi' = hi16(fl(hi + d)), lo' the rest.  s - hi'
+// is exact (the two agree in sign and exponent), so the pair carries the sum
+// to within one rounding of lo' (|lo'| < 2^-8 |hi'|).
+__device__ __forceinline__ void renorm16(float hi, float d, float& hi_out, float& lo_out) {
+  float s, err;
+  two_sum(hi, d, s, err);
+  hi_out = hi16(s);
+  lo_out = (s - hi_out) + err;
 }
 
 __device__ __forceinline__ float clampf(float v, float lo, float hi) {
@@ -590,8 +615,8 @@ __device__ __forceinline__ void collide_node(const Phys& ph, const Mom& m, const
                      (1.0f / 12.0f) * (mrt_qx(i) * d[2] + mrt_qy(i) * d[3]) +
                      0.25f * (mrt_pxx(i) * d[4] + mrt_pxy(i) * d[5]));
   }
-  // renormalise g_0 = hi + lo: hi' = fl(hi + d), lo' = the exact residual
-  two_sum(m.ref_g, gv[0], o.ghi, gv[0]);
+  // renormalise g_0 = hi + lo (16-bit hi, FP32 lo)
+  renorm16(m.ref_g, gv[0], o.ghi, gv[0]);
   // enthalpy, TRT (Sec. 3.3, eq22)
   const float ET = ph.Eref * T;
   const float cT = rhocp * T;
@@ -639,8 +664,8 @@ __device__ __forceinline__ void collide_node(const Phys& ph, const Mom& m, const
   }
 #pragma unroll
   for (int i = 1; i < 9; ++i) hv[i] = hn[i];
-  // renormalise h_0 = hi + lo
-  two_sum(ref_h, hn[0], o.hhi, hv[0]);
+  // renormalise h_0 = hi + lo (16-bit hi, FP32 lo)
+  renorm16(ref_h, hn[0], o.hhi, hv[0]);
 }
 
 }  // namespace lbf

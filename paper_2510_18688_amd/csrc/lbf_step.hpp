@@ -70,8 +70,12 @@ __device__ __forceinline__ void node_load(const Geo& G, const Phys& ph, const Bu
   in.fsp = ldp(B.lin, LAG_FS, G.P, k);
   in.Qp = ldp(B.lin, LAG_Q, G.P, k);
   in.phi0 = ldp(B.stat, ST_PHI0, G.P, k);
-  in.ghi = ldp(B.lin, LAG_GHI, G.P, k);
-  in.hhi = ldp(B.lin, LAG_HHI, G.P, k);
+  {
+    // both high parts in one plane
+    const uint32_t hp = __builtin_bit_cast(uint32_t, ldp(B.lin, LAG_GHI, G.P, k));
+    in.ghi = unpack_ghi(hp);
+    in.hhi = unpack_hhi(hp);
+  }
   in.pprev = ldp(B.lin, LAG_P, G.P, k);
   in.dlag = 0.0f;
   if (ph.phi_src_flow && gather_u) {
@@ -384,8 +388,7 @@ __device__ __forceinline__ void step_strip(const Geo& G, const Phys& ph, const B
           stp(B.lout, LAG_JY, P, k, o.jy);
         }
         stp(B.lout, LAG_P, P, k, o.p);
-        stp(B.lout, LAG_GHI, P, k, o.ghi);
-        stp(B.lout, LAG_HHI, P, k, o.hhi);
+        stp(B.lout, LAG_GHI, P, k, __builtin_bit_cast(float, pack_hi(o.ghi, o.hhi)));
         if (ph.phi_src_flow) {
           stp(B.lout, LAG_UX, P, k, o.ux);
           stp(B.lout, LAG_UY, P, k, o.uy);

@@ -132,7 +132,8 @@ def test_sessile_workload_5000_steps(lbf_mod, oracle_mod):
         assert rep[k]["rel_l2"] < 1e-2, (k, rep[k])
 
 
-@pytest.mark.parametrize("tile", [(64, 1), (64, 7), (128, 32), (256, 5), (256, 200)])
+@pytest.mark.parametrize("tile", [(64, 1), (64, 7), (128, 32), (256, 5), (256, 200), (512, 3),
+                                  (512, 16)])
 def test_tiles_are_bit_identical(lbf_mod, tile):
     case = W.slab_drop(150, 70, 20.0, 75.0, -1.0)
     ref = lbf_mod.Sim(case, tile=(64, 32))
