@@ -20,6 +20,9 @@
 namespace lbf {
 
 constexpr int CY_MAX = 256;
+// strips of at least this many rows take the previous step's velocity from
+// the LDS ring, shorter ones gather it (the same values, the same bits)
+constexpr int kRingRows = 4;
 // values per node in the stencil ring: phi, f_s, rho, p of the previous step
 // and the static phi0 (whose Laplacian is taken from the ring, not stored)
 constexpr int NSV = 5;
@@ -239,7 +242,9 @@ __device__ __forceinline__ void step_strip(const Geo& G, const Phys& ph, const B
   // their neighbours' velocity themselves, and so does a ghost row beyond a
   // y wall (its moments are the mirrored row's, whose divergence is taken
   // around that row, not around the ghost row's place in the ring)
-  const bool uring = ph.phi_src_flow != 0;
+  // (a strip of a few rows gathers every row: the ring's fill and its
+  // barrier-ordered stores would cost more than they save)
+  const bool uring = ph.phi_src_flow != 0 && nrow >= kRingRows;
   auto ring_row = [&](int r) { return uring && (G.py || (r >= 0 && r < G.ny)); };
   const int xl = map_axis(x0 - 1, G.nx, G.px);
   const int xr = map_axis(x0 + lastl + 1, G.nx, G.px);
