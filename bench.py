@@ -41,15 +41,17 @@ METHOD_BYTES_PER_LU = (27 + 6) * 2 * 4 + 3 * 4
 # from phi0 in the kernel).
 IMPL_BYTES_PER_LU = (27 + 7) * 2 * 4 + 2 * 4
 HBM_PEAK_GBS = 8000.0
-# D3Q19, two kernels per step.  Moments pass: g and h pulled (38 planes), the
-# high parts of g_0, h_0, f_s, Q and p of the previous step, phi0 read; a
-# 16-byte record (phi, f_s, rho, p) written.  Step pass: 57 distributions,
-# the 7 other lagged planes, 3 static planes and the record read; 57
-# distributions and 8 lagged planes written.  The state itself (one pass, no
-# records) is 532 bytes per update.
-BYTES3_MOMENTS = (38 + 5 + 1) * 4 + 16
-BYTES3_STEP = (57 + 7 + 3) * 4 + 16 + (57 + 8) * 4
-BYTES3_STATE = (57 + 8) * 2 * 4 + 3 * 4
+# D3Q19, two kernels per step, with the phase-field source from the flow's
+# divergence.  Moments pass: g and h pulled (38 planes), the high parts of
+# g_0, h_0, f_s, Q and p of the previous step, phi0 and the previous step's
+# velocity (3 planes) read; a 16-byte record (phi, f_s, rho, p) and the
+# divergence (4 bytes) written.  Step pass: 57 distributions, the 7 other
+# lagged planes, 3 static planes, the record and the divergence read; 57
+# distributions and 11 lagged planes (8 and the velocity) written.  The state
+# itself (one pass, no records) is 556 bytes per update.
+BYTES3_MOMENTS = (38 + 5 + 1 + 3) * 4 + 16 + 4
+BYTES3_STEP = (57 + 7 + 3) * 4 + 16 + 4 + (57 + 11) * 4
+BYTES3_STATE = (57 + 11) * 2 * 4 + 3 * 4
 # Cahn-Hilliard smoothing, per node and Euler step (one fused pass): c read
 # once and the new c written once.
 BYTES_CH = 4 + 4

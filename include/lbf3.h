@@ -57,6 +57,13 @@ typedef struct lbf3_params {
   double wall_T[6];            /* temperature of each Dirichlet face */
   double grav[3];              /* body force G = rho * grav, as in lbf_params */
   double u_solid[3];           /* solid-phase velocity of the drag */
+  int32_t phi_src_mdot;        /* div u in the phase-field source and recovery, as
+                                  in lbf_params: 0 (default) the isotropic divergence
+                                  of the previous step's velocity (three more lagged
+                                  planes and one plane from the moments pass), which
+                                  the fracture set-up needs over its 20 000 steps;
+                                  1 the mass source mdot of eq1 */
+  int32_t reserved;
 } lbf3_params;
 
 typedef struct lbf3_sim lbf3_sim;

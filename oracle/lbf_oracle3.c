@@ -13,7 +13,8 @@
  *       collisions and the isothermal-region reset,
  *   (3) streaming with the wall rules.
  * State: post-streaming f_i, g_i, h_i (19 each) and the lagged f_s,
- * Q = rho C_p T mdot, phi u (3 components) and p of the previous step.
+ * Q = rho C_p T mdot, phi u (3 components), p and u (3 components, for the
+ * phase-field source of R54) of the previous step.
  * Node (x, y, z) is element (z ny + y) nx + x.  The readings of the
  * two-dimensional oracle apply unchanged; R49 and R50 are the 3D additions
  * (uniform temperature per Dirichlet face; wall precedence z, y, x).
@@ -59,6 +60,10 @@ typedef struct {
   double wall_T[6];           /* temperature of each Dirichlet face (R49) */
   double grav[3];             /* body force G = rho g (R32) */
   double u_solid[3];          /* solid-phase velocity u_s of the drag */
+  int32_t phi_src_mdot;       /* div u in the phase-field source and recovery: 0 the
+                                 isotropic divergence of the previous step's velocity
+                                 (R54), 1 the mass source mdot (R12) */
+  int32_t pad2_;
 } orc3_params;
 
 typedef struct {
@@ -71,6 +76,8 @@ typedef struct {
   double *phi0, *cth, *lap_phi0;
   double *phihat, *C, *chi, *rhoH, *T, *fs, *fstot, *mdot, *phi, *rho, *Ksol, *Kliq;
   double *ux, *uy, *uz, *pr, *mu;
+  double *ux_lag, *uy_lag, *uz_lag, *ux_new, *uy_new, *uz_new; /* velocity, previous step (R54) */
+  double *divu;                 /* div u of the phase-field source: R54 or R12 */
   double budget[4];
   long step;
 } orc3_sim;
@@ -224,7 +231,8 @@ static double* alloc0(size_t n) { return (double*)calloc(n, sizeof(double)); }
   &s->fs_prev, &s->Q_prev, &s->jx_prev, &s->jy_prev, &s->jz_prev, &s->p_prev, &s->fs_new,  \
       &s->Q_new, &s->jx_new, &s->jy_new, &s->jz_new, &s->p_new, &s->phi0, &s->cth,          \
       &s->lap_phi0, &s->phihat, &s->C, &s->chi, &s->rhoH, &s->T, &s->fs, &s->fstot,         \
-      &s->mdot, &s->phi, &s->rho, &s->Ksol, &s->Kliq, &s->ux, &s->uy, &s->uz, &s->pr, &s->mu
+      &s->mdot, &s->phi, &s->rho, &s->Ksol, &s->Kliq, &s->ux, &s->uy, &s->uz, &s->pr, &s->mu, \
+      &s->ux_lag, &s->uy_lag, &s->uz_lag, &s->ux_new, &s->uy_new, &s->uz_new, &s->divu
 
 orc3_sim* orc3_create(const orc3_params* p) {
   if (p->nx <= 0 || p->ny <= 0 || p->nz <= 0) return NULL;
@@ -293,9 +301,24 @@ static void pass1(orc3_sim* s) {
     double fs = chi * (1.0 - fl);
     double fstot = fmin(1.0, phi0 + fs);
     double mdot = (1.0 - p->rho_s / p->rho_l) * (fs - s->fs_prev[k]);
+    /* div u of the phase-field equation (Sec. 3.2): the model's mdot (R12), or
+     * the divergence of the flow's own velocity of the previous step with the
+     * isotropic stencil (R54) */
+    double divu = mdot;
+    if (!p->phi_src_mdot) {
+      int x = (int)(k % (size_t)s->n3[0]);
+      int y = (int)((k / (size_t)s->n3[0]) % (size_t)s->n3[1]);
+      int z = (int)(k / ((size_t)s->n3[0] * s->n3[1]));
+      double gx[3], gy[3], gz[3];
+      grad_lap(s, s->ux_lag, x, y, z, gx, NULL);
+      grad_lap(s, s->uy_lag, x, y, z, gy, NULL);
+      grad_lap(s, s->uz_lag, x, y, z, gz, NULL);
+      divu = gx[0] + gy[1] + gz[2];
+    }
+    s->divu[k] = divu;
     s->phihat[k] = sg; s->C[k] = C; s->chi[k] = chi; s->rhoH[k] = rhoH; s->T[k] = T;
     s->fs[k] = fs; s->fstot[k] = fstot; s->mdot[k] = mdot;
-    s->phi[k] = sg / (1.0 - 0.5 * mdot);
+    s->phi[k] = sg / (1.0 - 0.5 * divu);
     s->Ksol[k] = Ksol; s->Kliq[k] = Kliq;
     s->rho[k] = zeta(fstot, C, p->rho_s, p->rho_l, p->rho_g);
   }
@@ -369,7 +392,7 @@ static void pass2(orc3_sim* s, int collide) {
         orc3_geq(phi, mu, j, geq);
         for (int i = 0; i < Q; ++i) {
           double Gi = W[i] * (CX[i] * dj[0] + CY[i] * dj[1] + CZ[i] * dj[2]) / CS2 +
-                      W[i] * phi * mdot;
+                      W[i] * phi * s->divu[k];
           double gi = s->g[i * n + k];
           s->gc[i * n + k] = gi - (gi - geq[i]) / tau_g + (1.0 - 0.5 / tau_g) * Gi;
         }
@@ -390,7 +413,7 @@ static void pass2(orc3_sim* s, int collide) {
           hsum += v;
         }
         a_heat += 0.5 * s->Q_prev[k] / tau_s + (1.0 - 0.5 / tau_src) * Qs;
-        a_phi += phi * mdot;
+        a_phi += phi * s->divu[k];
         if (p->substrate_fixed && s->phi0[k] >= 0.5) {
           double Tw = p->T_substrate;
           double rH = enthalpy_at(p, Tw, s->Ksol[k], s->Kliq[k], s->chi[k]);
@@ -405,6 +428,7 @@ static void pass2(orc3_sim* s, int collide) {
         s->fs_new[k] = fs; s->Q_new[k] = Qs;
         s->jx_new[k] = j[0]; s->jy_new[k] = j[1]; s->jz_new[k] = j[2];
         s->p_new[k] = pr;
+        s->ux_new[k] = u[0]; s->uy_new[k] = u[1]; s->uz_new[k] = u[2];
       }
       size_t r = (size_t)z * ny + y;
       acc[3 * r] = a_heat; acc[3 * r + 1] = a_phi; acc[3 * r + 2] = a_reset;
@@ -481,6 +505,9 @@ static void swap_lagged(orc3_sim* s) {
   SWAP(s->jy_prev, s->jy_new);
   SWAP(s->jz_prev, s->jz_new);
   SWAP(s->p_prev, s->p_new);
+  SWAP(s->ux_lag, s->ux_new);
+  SWAP(s->uy_lag, s->uy_new);
+  SWAP(s->uz_lag, s->uz_new);
 #undef SWAP
 }
 
@@ -507,8 +534,9 @@ int orc3_init(orc3_sim* s, const double* phi0, const double* cth, const double* 
     for (int y = 0; y < ny; ++y)
       for (int x = 0; x < nx; ++x) grad_lap(s, s->phi0, x, y, z, NULL, &s->lap_phi0[idx(s, x, y, z)]);
   memset(s->f, 0, Q * n * sizeof(double));
-  double** lag[] = {&s->fs_prev, &s->Q_prev, &s->jx_prev, &s->jy_prev, &s->jz_prev, &s->p_prev};
-  for (int a = 0; a < 6; ++a) memset(*lag[a], 0, n * sizeof(double));
+  double** lag[] = {&s->fs_prev, &s->Q_prev, &s->jx_prev, &s->jy_prev, &s->jz_prev, &s->p_prev,
+                    &s->ux_lag, &s->uy_lag, &s->uz_lag};   /* u = 0 initially (R29) */
+  for (int a = 0; a < 9; ++a) memset(*lag[a], 0, n * sizeof(double));
   memcpy(s->phi, phi, n * sizeof(double));
   double zero[3] = {0, 0, 0};
   for (int z = 0; z < nz; ++z)

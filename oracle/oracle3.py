@@ -33,7 +33,8 @@ class Orc3Params(C.Structure):
             "rho_l", "rho_g", "rho_s", "mu_l", "mu_g", "mu_s", "lam_l", "lam_g", "lam_s",
             "cp_l", "cp_g", "cp_s", "latent", "T_m", "sigma", "eps", "mobility",
             "cos_psi", "rho_ref", "T_substrate", "pcm_floor")] + [
-        ("wall_T", C.c_double * 6), ("grav", C.c_double * 3), ("u_solid", C.c_double * 3)]
+        ("wall_T", C.c_double * 6), ("grav", C.c_double * 3), ("u_solid", C.c_double * 3),
+        ("phi_src_mdot", C.c_int32), ("pad2_", C.c_int32)]
 
 
 def build(force: bool = False) -> str:
@@ -103,6 +104,7 @@ def make_params(case) -> Orc3Params:
     for a, k in enumerate("xyz"):
         p.grav[a] = float(getattr(m, "g_" + k))
         p.u_solid[a] = float(getattr(m, "us_" + k))
+    p.phi_src_mdot = int(getattr(m, "phi_src_mdot", 0))
     return p
 
 

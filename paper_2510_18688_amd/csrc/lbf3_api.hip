@@ -1,6 +1,8 @@
 // C ABI of the three-dimensional (D3Q19) coupled step (contracts in
 // include/lbf3.h).  Two kernels per step, one node per lane: the moments pass
-// pulls g and h and stores phi, f_s and rho for the stencils; the step pass
+// pulls g and h and stores phi, f_s and rho for the stencils (and, with the
+// flow-divergence phase-field source, the divergence of the previous step's
+// velocity from its eighteen neighbours); the step pass
 // pulls f, g and h, accumulates the 3D stencils from those planes, collides
 // and stores the next state.  Workgroups are dealt to the XCDs in contiguous
 // bands of nodes so that the y and z neighbours a band reads stay in one L2.
@@ -50,7 +52,7 @@ Layout3 make_layout3(int nx, int ny, int nz, int pad) {
   L.lag[0] = take(NLAG * pb);
   L.lag[1] = take(NLAG * pb);
   L.stat = take(NSTAT * pb);
-  L.mom = take(4 * pb);   // 16-byte records
+  L.mom = take(5 * pb);   // 16-byte records, then the div u plane
   L.fields = take(NFIELD * pb);
   L.red = take((size_t)L.nblocks * kRed3 * sizeof(double));
   L.redfinal = take(kRed3 * sizeof(double));
@@ -193,8 +195,15 @@ __global__ __launch_bounds__(256) void k3_moments(Geo3 G, Phys ph, BufArgs3 A, i
   pull19(G, x, y, z, n);
   float gv[NQ], hv[NQ];
   pull_gh3(G, ph, B, n, gv, hv);
+  // the flow-divergence phase-field source: div u of the previous step, kept
+  // for the step pass (which reads it instead of gathering the velocity again)
+  float dl = 0.0f;
+  if (ph.phi_src_flow) {
+    dl = div3(G, B, n);
+    lbf::stp(B.mom, MOM_DIVU, G.P, k, dl);
+  }
   Mom m;
-  node_moments3(G, ph, B, (uint32_t)k, gv, hv, lbf::ldp(B.stat, ST_PHI0, G.P, k), m);
+  node_moments3(G, ph, B, (uint32_t)k, gv, hv, lbf::ldp(B.stat, ST_PHI0, G.P, k), m, dl);
   st_rec(B.mom, (uint32_t)k * 16u, m.phi, m.fs, m.rho, lbf::ldp(B.lin, LAG_P, G.P, k));
 }
 
@@ -217,8 +226,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
     float gv[NQ], hv[NQ], fv[NQ];
     pull_gh3(G, ph, B, n, gv, hv);
     const float phi0 = lbf::ldp(B.stat, ST_PHI0, G.P, k);
+    const float dl = ph.phi_src_flow ? lbf::ldp(B.mom, MOM_DIVU, G.P, k) : 0.0f;
     Mom m;
-    node_moments3(G, ph, B, (uint32_t)k, gv, hv, phi0, m);
+    node_moments3(G, ph, B, (uint32_t)k, gv, hv, phi0, m, dl);
     Stencil3 S;
     stencils3(G, B, n, m.phi, m.fs, S);
     pull_f3(G, B, n, fv);
@@ -243,6 +253,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
       lbf::stp(B.lout, LAG_P, G.P, k, o.p);
       lbf::stp(B.lout, LAG_GHI, G.P, k, o.ghi);
       lbf::stp(B.lout, LAG_HHI, G.P, k, o.hhi);
+      if (ph.phi_src_flow) {
+        lbf::stp(B.lout, LAG_UX, G.P, k, o.u[0]);
+        lbf::stp(B.lout, LAG_UY, G.P, k, o.u[1]);
+        lbf::stp(B.lout, LAG_UZ, G.P, k, o.u[2]);
+      }
     } else {
       const float mu = lbf::chem_pot(ph, m.phi, S.lphi, phi0, lbf::ldp(B.stat, ST_CTH, G.P, k),
                                      lbf::ldp(B.stat, ST_LAP0, G.P, k), m.fs, S.lfs);
@@ -328,6 +343,8 @@ int validate3(const lbf3_params* p) {
   for (int a = 0; a < 3; ++a)
     if (!std::isfinite(p->grav[a]) || !std::isfinite(p->u_solid[a]))
       return fail(LBF_EINVAL, "grav and u_solid must be finite");
+  if (p->phi_src_mdot != 0 && p->phi_src_mdot != 1)
+    return fail(LBF_EINVAL, "phi_src_mdot = %d", p->phi_src_mdot);
   const double cpref = 2.0 * p->cp_s * p->cp_l / (p->cp_s + p->cp_l);
   const double kmin = std::min({p->rho_l, p->rho_g, p->rho_s}) *
                       std::min({p->cp_l, p->cp_g, p->cp_s});
@@ -360,7 +377,7 @@ void fill_phys3(const lbf3_params* p, Phys& ph) {
   ph.latch = p->latch_fs ? 1 : 0;
   ph.src_tau_a = p->h_src_tau_a ? 1 : 0;
   ph.subfix = p->substrate_fixed ? 1 : 0;
-  ph.phi_src_flow = 0;   // the D3Q19 step takes div u = mdot (no lagged velocity planes)
+  ph.phi_src_flow = p->phi_src_mdot ? 0 : 1;
   for (int a = 0; a < 3; ++a) {
     ph.grav[a] = (float)p->grav[a];
     ph.vsol[a] = (float)p->u_solid[a];

@@ -6,9 +6,13 @@
 //                 stored at the node that wrote them (pull scheme); the rest
 //                 populations g_0, h_0 hold the low parts of float-float
 //                 values whose high parts are lagged planes;
-//   lagged        8 planes: f_s, Q = rho C_p T mdot, (phi u)_x, _y, _z, p of
-//                 the previous step, high parts of g_0 and h_0;
-//   static        3 planes: phi0, cos(theta), lap(phi0).
+//   lagged       11 planes: f_s, Q = rho C_p T mdot, (phi u)_x, _y, _z, p of
+//                 the previous step, high parts of g_0 and h_0, and the
+//                 previous step's velocity (read and written only when the
+//                 phase-field source takes its divergence);
+//   static        3 planes: phi0, cos(theta), lap(phi0);
+//   moments       per node a 16-byte record (phi, f_s, rho, lagged p) and one
+//                 plane of div u, written by the moments pass.
 // The node-local moments, the chemical potential and the mixing rule are the
 // dimension-free functions of the two-dimensional step (lbf_device.hpp).
 #pragma once
@@ -22,10 +26,12 @@ using lbf::Rsrc;
 
 constexpr int NQ = 19;
 constexpr int NDIST = 3 * NQ;
-constexpr int NLAG = 8;
+constexpr int NLAG = 11;
 constexpr int NSTAT = 3;
 constexpr int NFIELD = 14;
-enum { LAG_FS = 0, LAG_Q, LAG_JX, LAG_JY, LAG_JZ, LAG_P, LAG_GHI, LAG_HHI };
+enum { LAG_FS = 0, LAG_Q, LAG_JX, LAG_JY, LAG_JZ, LAG_P, LAG_GHI, LAG_HHI, LAG_UX, LAG_UY, LAG_UZ };
+// plane of div u behind the records in the moments buffer (in units of P floats)
+constexpr int MOM_DIVU = 4;
 enum { ST_PHI0 = 0, ST_CTH = 1, ST_LAP0 = 2 };
 
 // D3Q19 (Sec. 3.1): rest, six axis directions, twelve face diagonals, in the
@@ -67,7 +73,8 @@ struct BufArgs3 {
   float* lout;
   const float* stat;
   float* mom;        // per node a 16-byte record (phi, f_s, rho of the state read,
-                     // p of the step before), written by the moments pass
+                     // p of the step before), then a plane of div u (MOM_DIVU),
+                     // written by the moments pass
 };
 
 __device__ __forceinline__ Bufs3 make_bufs3(const BufArgs3& a, int P) {
@@ -82,7 +89,7 @@ __device__ __forceinline__ Bufs3 make_bufs3(const BufArgs3& a, int P) {
   B.lin = lbf::make_rsrc(a.lin, NLAG * pb);
   B.lout = lbf::make_rsrc(a.lout, a.lout ? NLAG * pb : 0u);
   B.stat = lbf::make_rsrc(a.stat, NSTAT * pb);
-  B.mom = lbf::make_rsrc(a.mom, 4 * pb);
+  B.mom = lbf::make_rsrc(a.mom, 5 * pb);
   return B;
 }
 
@@ -188,10 +195,12 @@ __device__ __forceinline__ void pull_f3(const Geo3& G, const Bufs3& B, const Pul
   }
 }
 
-// Node moments from the pulled g, h and the lagged fields.
+// Node moments from the pulled g, h and the lagged fields; dlag is the
+// divergence of the previous step's velocity (used with the flow-divergence
+// phase-field source).
 __device__ __forceinline__ void node_moments3(const Geo3& G, const Phys& ph, const Bufs3& B,
                                               uint32_t k, const float* gv, const float* hv,
-                                              float phi0, Mom& m) {
+                                              float phi0, Mom& m, float dlag = 0.0f) {
   float sg = gv[0], sh = hv[0];
 #pragma unroll
   for (int i = 1; i < NQ; ++i) {
@@ -202,14 +211,43 @@ __device__ __forceinline__ void node_moments3(const Geo3& G, const Phys& ph, con
   const float hhi = lbf::ldp(B.lin, LAG_HHI, G.P, (int)k);
   const float fsp = lbf::ldp(B.lin, LAG_FS, G.P, (int)k);
   const float Qp = lbf::ldp(B.lin, LAG_Q, G.P, (int)k);
-  lbf::moments(ph, ghi, sg, hhi, sh, fsp, Qp, phi0, m);
+  lbf::moments(ph, ghi, sg, hhi, sh, fsp, Qp, phi0, m, dlag);
 }
+
+
 
 // Neighbour index for the stencils: wrap, or the mirror ghost at a wall.
 __device__ __forceinline__ int nb3(int v, int n, int periodic) {
   if (v < 0) return periodic ? v + n : 0;
   if (v >= n) return periodic ? v - n : n - 1;
   return v;
+}
+
+// Isotropic divergence 3 sum_i w_i c_i . u(x + c_i) of the previous step's
+// velocity at one node, over the same neighbours as the stencils (the pull
+// offsets, the mirror ghost for a link that crosses a wall).  Fixed grouping
+// and no contraction: axis neighbours (weight 1/18), then face diagonals
+// (1/36).
+__device__ __forceinline__ float div3(const Geo3& G, const Bufs3& B, const Pull19& n) {
+#pragma clang fp contract(off)
+  float ax = 0.0f, dg = 0.0f;
+#pragma unroll
+  for (int i = 1; i < NQ; ++i) {
+    uint32_t o = n.off[opp(i)];
+    if ((n.wmask >> opp(i)) & 1u) {
+      const int xx = nb3(n.x + cx(i), G.n[0], G.per[0]);
+      const int yy = nb3(n.y + cy(i), G.n[1], G.per[1]);
+      const int zz = nb3(n.z + cz(i), G.n[2], G.per[2]);
+      o = (((uint32_t)zz * G.n[1] + yy) * G.n[0] + xx) * 4u;
+    }
+    float c = 0.0f;
+    if (cx(i)) c = c + (float)cx(i) * lbf::ldo(B.lin, o, LAG_UX, G.P);
+    if (cy(i)) c = c + (float)cy(i) * lbf::ldo(B.lin, o, LAG_UY, G.P);
+    if (cz(i)) c = c + (float)cz(i) * lbf::ldo(B.lin, o, LAG_UZ, G.P);
+    if (i <= 6) ax = ax + c;
+    else dg = dg + c;
+  }
+  return 3.0f * ((1.0f / 18.0f) * ax + (1.0f / 36.0f) * dg);
 }
 
 // The moments pass's record of a node: phi, f_s, rho and the lagged p.
@@ -340,7 +378,7 @@ __device__ __forceinline__ void collide3_prepare(const Phys& ph, const Mom& m, c
     c.j[a] = phi * c.u[a];
     c.dj[a] = c.j[a] - jprev[a];
   }
-  c.pm = phi * mdot;
+  c.pm = phi * m.divu;
   const float rhocp = rho * cp;
   c.Q = rhocp * T * mdot;
   c.ET = ph.Eref * T;

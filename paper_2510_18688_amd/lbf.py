@@ -550,7 +550,8 @@ class Params3(C.Structure):
             "rho_l", "rho_g", "rho_s", "mu_l", "mu_g", "mu_s", "lam_l", "lam_g", "lam_s",
             "cp_l", "cp_g", "cp_s", "latent", "T_m", "sigma", "eps", "mobility", "cos_psi",
             "rho_ref", "T_substrate", "pcm_floor")] + [
-        ("wall_T", C.c_double * 6), ("grav", C.c_double * 3), ("u_solid", C.c_double * 3)]
+        ("wall_T", C.c_double * 6), ("grav", C.c_double * 3), ("u_solid", C.c_double * 3),
+        ("phi_src_mdot", C.c_int32), ("reserved", C.c_int32)]
 
 
 def _declare3(L):
@@ -596,6 +597,7 @@ def make_params3(case) -> Params3:
     for a, k in enumerate("xyz"):
         p.grav[a] = float(getattr(m, "g_" + k))
         p.u_solid[a] = float(getattr(m, "us_" + k))
+    p.phi_src_mdot = int(getattr(m, "phi_src_mdot", 0))
     return p
 
 

@@ -66,15 +66,16 @@ def test_params_layout_matches_header(tmp_path):
 def test_params3_layout_matches_header(tmp_path):
     src = tmp_path / "sz3.c"
     src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "lbf3.h"\n'
-                   'int main(void){printf("%zu %zu %zu %zu\\n", sizeof(lbf3_params),'
+                   'int main(void){printf("%zu %zu %zu %zu %zu\\n", sizeof(lbf3_params),'
                    ' offsetof(lbf3_params, rho_l), offsetof(lbf3_params, pcm_floor),'
-                   ' offsetof(lbf3_params, wall_T));return 0;}\n')
+                   ' offsetof(lbf3_params, wall_T), offsetof(lbf3_params, phi_src_mdot));'
+                   'return 0;}\n')
     exe = tmp_path / "sz3"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()
     P = lbf.Params3
     assert [int(v) for v in out] == [C.sizeof(P), P.rho_l.offset, P.pcm_floor.offset,
-                                     P.wall_T.offset]
+                                     P.wall_T.offset, P.phi_src_mdot.offset]
 
 
 def test_workspace_bytes(L):

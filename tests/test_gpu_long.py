@@ -18,7 +18,8 @@ a drop on a cylinder, and the D3Q19 step at its benchmarked size.
   cos(theta) and R from the conservation of the drop's area, within 2 % at
   30, 60, 90, 120 and 150 degrees.  The shape does not depend on sigma, so
   sigma = 0.01 shortens the relaxation.
-* The D3Q19 drop in a 256^3 box against the 3D oracle after 5 steps.
+* The D3Q19 drop in a 256^3 box against the 3D oracle after 5 steps, and
+  the D3Q19 fracture over its 20 000 steps.
 """
 
 import json
@@ -152,6 +153,29 @@ def test_drop_on_cylinder_equilibrium(lbf_mod, theta):
     print("cylinder", theta, "H_max", round(top, 2), "closed form", round(H, 2), flush=True)
     report(f"cylinder_theta{int(theta)}", {"H_max": top, "closed_form": H})
     assert abs(top - H) <= 0.02 * H, (theta, top, H)
+
+
+def test_d3q19_fracture_at_stated_length(lbf_mod):
+    """The D3Q19 fracture set-up over its 20 000 steps in the benchmark's
+    configuration: every 2 500 steps no non-finite node and max |u| < 0.3,
+    and the ice keeps growing.  (With the model's mass source as div u the
+    same run goes non-finite between steps 10 000 and 12 500.)"""
+    import torch
+    from paper_2510_18688_amd import autotune, workloads3 as W3
+    case = W3.fracture()
+    sim = lbf_mod.Sim3(case, plane_pad=autotune.lookup_pad(case.nx, case.ny, case.nz))
+    done, hist = 0, []
+    while done < case.steps:
+        sim.step(2500)
+        done += 2500
+        r = sim.reduce(check_stable=False)
+        hist.append([done, r["umax"], r["nonfinite"], r["sum_fs"]])
+        assert r["nonfinite"] == 0 and r["umax"] < 0.3, hist[-1]
+    print("fracture steps", done, "last", hist[-1], flush=True)
+    report("fracture_256x128x30_20000", hist)
+    assert all(b[3] > a[3] for a, b in zip(hist, hist[1:]))
+    sim.close()
+    torch.cuda.empty_cache()
 
 
 def test_d3q19_cube256_against_oracle(lbf_mod):

@@ -213,6 +213,30 @@ def test_save_load_continues_bitwise(lbf_mod):
         assert np.array_equal(ref[k], got[k]), k
 
 
+@pytest.mark.parametrize("mdot", [0, 1])
+def test_copy_probe_leaves_the_state_unchanged(lbf_mod, mdot):
+    """lbf_copy_probe (the bandwidth ceiling of the step's access pattern)
+    writes only the buffers the next step overwrites: a run with probes in
+    the middle continues bit for bit, and the probe counts the step's bytes
+    (27 distributions and the lagged planes in use, read and written, two
+    static planes read)."""
+    case = W.slab_drop(150, 70, 20.0, 75.0, -1.0)
+    case.mat.phi_src_mdot = mdot
+    a = lbf_mod.Sim(case, tile=(128, 8))
+    a.step(30)
+    ref = a.fields()
+    b = lbf_mod.Sim(case, tile=(128, 8))
+    b.step(13)
+    ms, nbytes = b.copy_probe(3)
+    b.step(17)
+    got = b.fields()
+    for k in FIELDS:
+        assert np.array_equal(ref[k], got[k]), k
+    assert ms > 0.0
+    lag = 7 if mdot == 0 else 6
+    assert nbytes == case.nx * case.ny * 4 * (2 * (27 + lag) + 2)
+
+
 def test_runs_are_deterministic(lbf_mod):
     case = W.sessile_drop(nx=64, ny=48, radius=15.0)
     outs = []

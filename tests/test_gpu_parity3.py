@@ -88,6 +88,24 @@ def test_one_step_and_few_steps(lbf_mod, O3, name):
         assert abs(r[k] - ro[k]) <= 1e-6 * max(abs(ro[k]), 1.0), (name, k, r[k], ro[k])
 
 
+@pytest.mark.parametrize("name", ["boxed_21x19x17", "fracture_small"])
+def test_mass_source_reading(lbf_mod, O3, name):
+    """The phase-field source with the model's mass source as div u (R12,
+    phi_src_mdot = 1: no velocity planes) against the oracle with the same
+    reading."""
+    case = cases()[name]
+    case.mat.phi_src_mdot = 1
+    sim = lbf_mod.Sim3(case)
+    orc = O3.Oracle3(case)
+    sim.step(1)
+    orc.step(1)
+    compare(sim.fields(), orc.fields(), 2e-6, name + " R12 step 1")
+    sim.step(29)
+    orc.step(29)
+    compare(sim.fields(), orc.fields(), 2e-5, name + " R12 step 30",
+            ["phi", "T", "fl", "fs", "rhoH", "C", "chi"])
+
+
 def test_fracture_full_size(lbf_mod, O3):
     """The full fracture in the benchmark's configuration (its tuned plane
     padding) after 5 steps, and the freezing fields after 300."""
