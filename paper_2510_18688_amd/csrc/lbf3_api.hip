@@ -185,9 +185,12 @@ __global__ __launch_bounds__(256) void k3_unstream(Geo3 G, Phys ph, const float*
 }
 
 // Moments pass: phi, f_s, rho of the state read, for the stencils.
+// With the flow-divergence source it walks the step pass's strip order: the
+// divergence reads the z neighbours' velocity, which is then still in L2.
 __global__ __launch_bounds__(256) void k3_moments(Geo3 G, Phys ph, BufArgs3 A, int N, int nblocks) {
-  const int k = node_of_block(nblocks);
-  if (k >= N) return;
+  const int q = node_of_block(nblocks);
+  if (q >= N) return;
+  const int k = ph.phi_src_flow ? node_in_strips(G, q) : q;
   int x, y, z;
   coords(G, k, x, y, z);
   const Bufs3 B = make_bufs3(A, G.P);
