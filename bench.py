@@ -85,6 +85,8 @@ def parse():
     ap.add_argument("--tile", type=str, default="", help="TXxTY, e.g. 128x32")
     ap.add_argument("--plane-pad", type=int, default=-1,
                     help="floats of padding between workspace planes (-1: the tuned value)")
+    ap.add_argument("--row-block", type=int, default=-1,
+                    help="rows per block of the state layout, 0 plane-major (-1: the tuned value)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--batch-steps", type=int, default=320,
@@ -199,12 +201,12 @@ def adjoint(lbf, W, torch, steps, n=256):
     tcase, _, _ = W.adjoint_case(n=n, steps=steps, radius=radius)
     tcase.cos_theta = np.broadcast_to(np.cos(np.radians(th_t))[None, :], (tcase.ny, tcase.nx)).copy()
     tcase.wall_T = {W.BOTTOM: np.asarray(tw_t, dtype=np.float64)}
-    sim = lbf.Sim(tcase, tile=tile)
+    sim = lbf.Sim(tcase, tile=tile, row_block=0)
     sim.step(steps)
     fl_star = torch.as_tensor(sim.field("fl"), device="cuda")
     sim.close()
-    # forward: plain steps from the initial state
-    sim = lbf.Sim(case, tile=tile)
+    # forward: plain steps from the initial state (the tape's plane-major layout)
+    sim = lbf.Sim(case, tile=tile, row_block=0)
     sim.step(8)
     sim.init_fields(case.phi, case.T)
     torch.cuda.synchronize()
@@ -286,13 +288,13 @@ def d3q19(lbf, torch, steps):
     return out
 
 
-def mrt(lbf, W, torch, steps, tile, pad):
+def mrt(lbf, W, torch, steps, tile, pad, rb):
     """The headline workload with MRT flow and phase-field collisions (bulk
     rate 1.5, energy-flux rate 1.2, phase-field rate 1.4): the same state and
     bytes per update as BGK."""
     case = W.curved_substrate()
     case.mat.mrt, case.mat.s_b, case.mat.s_q, case.mat.s_g = 1, 1.5, 1.2, 1.4
-    sim = lbf.Sim(case, tile=tile, plane_pad=pad)
+    sim = lbf.Sim(case, tile=tile, plane_pad=pad, row_block=rb)
     sim.step(50)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -341,8 +343,8 @@ def porous(lbf, W, torch, steps):
     from paper_2510_18688_amd import autotune
     case = W.porous_medium()
     tile = autotune.lookup(case.nx, case.ny)
-    pad = autotune.lookup_pad(case.nx, case.ny)
-    sim = lbf.Sim(case, tile=tile, plane_pad=pad)
+    rb, pad = autotune.lookup_layout(case.nx, case.ny)
+    sim = lbf.Sim(case, tile=tile, plane_pad=pad, row_block=rb)
     sim.step(50)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -356,7 +358,7 @@ def porous(lbf, W, torch, steps):
     sim.close()
     gbs = BYTES_PER_LU * case.nodes / (kms * 1e-3) / 1e9
     return {"workload": case.name, "nodes": case.nodes, "steps": steps,
-            "tile": f"{tile[0]}x{tile[1]}", "plane_pad": pad,
+            "tile": f"{tile[0]}x{tile[1]}", "plane_pad": pad, "row_block": rb,
             "mlups": round(case.nodes * steps / wall / 1e6, 1),
             "kernel_ms": round(kms, 5), "achieved_gbs": round(gbs, 1),
             "frac": round(gbs / HBM_PEAK_GBS, 4), "nonfinite": red["nonfinite"],
@@ -417,8 +419,12 @@ def main():
 
     case = W.curved_substrate()
     from paper_2510_18688_amd import autotune
-    pad = args.plane_pad if args.plane_pad >= 0 else autotune.lookup_pad(case.nx, case.ny)
-    sim = lbf.Sim(case, plane_pad=pad)
+    rb, pad = autotune.lookup_layout(case.nx, case.ny)
+    if args.plane_pad >= 0:
+        pad = args.plane_pad
+    if args.row_block >= 0:
+        rb = args.row_block
+    sim = lbf.Sim(case, plane_pad=pad, row_block=rb)
     if args.tile:
         tx, ty = (int(v) for v in args.tile.lower().split("x"))
         sim.set_tile(tx, ty)
@@ -477,7 +483,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": case.name, "nx": case.nx, "ny": case.ny, "nodes": nodes,
-                   "tile": f"{tile[0]}x{tile[1]}", "plane_pad": pad,
+                   "tile": f"{tile[0]}x{tile[1]}", "plane_pad": pad, "row_block": rb,
                    "steps_per_run": case.steps},
         "pct_hbm": round(100.0 * mlups * 1e6 * BYTES_PER_LU / (HBM_PEAK_GBS * 1e9), 2),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
@@ -516,7 +522,7 @@ def main():
     if args.adjoint_hbm_steps > 0:
         out["adjoint_hbm"] = adjoint(lbf, W, torch, args.adjoint_hbm_steps, n=2048)
     if args.mrt_steps > 0:
-        out["mrt"] = mrt(lbf, W, torch, args.mrt_steps, tile, pad)
+        out["mrt"] = mrt(lbf, W, torch, args.mrt_steps, tile, pad, rb)
     if args.porous_steps > 0:
         out["porous"] = porous(lbf, W, torch, args.porous_steps)
     if args.small_steps > 0:

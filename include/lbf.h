@@ -135,7 +135,14 @@ typedef struct lbf_params {
    * source mdot of eq1 (sum phi changes by exactly sum phi mdot; stable only
    * over shorter runs).  The adjoint (lbf_tape_*) supports 1 only. */
   int32_t phi_src_mdot;
-  int32_t reserved3;
+  /* Memory layout of the state (a tuning knob; results do not depend on it).
+   * 0: plane-major, each plane's nx * ny nodes back to back.  1, 2, 4, 8, 16
+   * or 32: row blocks of that many rows, each block holding its rows of every
+   * distribution and lagged plane (and of every static plane) back to back,
+   * so the planes one step touches at a time lie close together in HBM;
+   * plane_pad then pads each block's planes.  The adjoint (lbf_tape_*)
+   * supports 0 only.  Row blocks cap a lattice at about 29.8 M nodes. */
+  int32_t row_block;
   double s_b, s_q, s_g;
   /* Body force G = rho * grav (a uniform acceleration acting on the local
    * density) and the solid-phase velocity u_s of the drag f_s (u_s - u*)
@@ -148,13 +155,14 @@ typedef struct lbf_params {
 typedef struct lbf_sim lbf_sim;
 
 /* Bytes of device workspace one simulation needs (distributions, lagged
- * fields, static fields, reduction scratch) for lattice nx x ny and
- * lbf_params.plane_pad, or 0 for invalid sizes or pads. */
-size_t lbf_workspace_bytes(int32_t nx, int32_t ny, int32_t plane_pad);
+ * fields, static fields, reduction scratch) for lattice nx x ny,
+ * lbf_params.plane_pad and lbf_params.row_block, or 0 for invalid sizes,
+ * pads or row blocks. */
+size_t lbf_workspace_bytes(int32_t nx, int32_t ny, int32_t plane_pad, int32_t row_block);
 
 /* Create a simulation on HIP stream `stream` (a hipStream_t, NULL for the
  * default stream).  `workspace` is caller-owned device memory of at least
- * lbf_workspace_bytes(nx, ny, plane_pad) bytes, 256-byte aligned, that must outlive the
+ * lbf_workspace_bytes(nx, ny, plane_pad, row_block) bytes, 256-byte aligned, that must outlive the
  * simulation; with workspace == NULL the library allocates it with hipMalloc
  * and frees it in lbf_destroy.  Rejects with LBF_EINVAL: non-positive sizes,
  * non-positive densities, specific heats, viscosities or conductivities,

@@ -4,9 +4,12 @@ For a lattice size it times every candidate launch shape (threads per block
 along x, rows per block along y) with HIP events on the simulation's stream
 and persists the fastest in tiles.json next to this file, keyed by "NXxNY".
 `tune_pad` does the same for the padding between the workspace's planes
-(lbf_params.plane_pad), which decides how the 34 planes that one step
-streams spread over the HBM channels; its effect depends on the exact size,
-so `lookup_pad` answers for measured sizes only.
+(lbf_params.plane_pad) of the plane-major layout (and of the 3D lattice),
+which decides how the 34 planes that one step streams spread over the HBM
+channels; `tune_layout` picks the 2D state layout (rows per block,
+lbf_params.row_block) together with its pad.  Their effect depends on the
+exact size, so `lookup_pad` and `lookup_layout` answer for measured sizes
+only.
 """
 
 from __future__ import annotations
@@ -93,7 +96,8 @@ def tune_pad(case, tile: Optional[Sequence[int]] = None, steps: int = 100, repea
     three = hasattr(case, "nz")
     times = {}
     for pad in candidates:
-        sim = lbf.Sim3(case, plane_pad=pad) if three else lbf.Sim(case, tile=tile, plane_pad=pad)
+        sim = (lbf.Sim3(case, plane_pad=pad) if three
+               else lbf.Sim(case, tile=tile, plane_pad=pad, row_block=0))
         sim.step(10)
         sim.set_timing(True)
         runs = []
@@ -114,6 +118,55 @@ def tune_pad(case, tile: Optional[Sequence[int]] = None, steps: int = 100, repea
         with open(DB, "w") as f:
             json.dump(db, f, indent=1, sort_keys=True)
     return best, times
+
+
+# (rows per block, plane pad) of the 2D state layout; row_block 0 is plane-major
+LAYOUT_CANDIDATES: Tuple[Tuple[int, int], ...] = tuple(
+    (rb, pad) for rb in (0, 2, 4, 8) for pad in (0, 64, 128, 576, 2112, 4160))
+
+
+def lookup_layout(nx: int, ny: int) -> Tuple[int, int]:
+    """Tuned (row_block, plane_pad) of a 2D lattice size; (4, 0) if that size
+    was not measured."""
+    v = _load().get(_key(nx, ny))
+    if v and "layout" in v:
+        rb, pad = v["layout"]
+        return int(rb), int(pad)
+    return 4, 0
+
+
+def tune_layout(case, tile: Optional[Sequence[int]] = None, steps: int = 100, repeats: int = 3,
+                candidates: Iterable[Sequence[int]] = LAYOUT_CANDIDATES, save: bool = True
+                ) -> Tuple[Tuple[int, int], dict]:
+    """Time the 2D step of `case` with launch shape `tile` in each state
+    layout (a fresh simulation each, median of `repeats` runs of `steps`
+    steps) and keep the best."""
+    import statistics
+    from . import lbf
+    times = {}
+    for rb, pad in candidates:
+        sim = lbf.Sim(case, tile=tile, plane_pad=pad, row_block=rb)
+        sim.step(10)
+        sim.set_timing(True)
+        runs = []
+        for _ in range(repeats):
+            sim.step(steps)
+            runs.append(sim.last_step_kernel_ms())
+        times[f"{rb}/{pad}"] = statistics.median(runs)
+        sim.close()
+        del sim
+    best = min(times, key=times.get)
+    layout = tuple(int(v) for v in best.split("/"))
+    if save:
+        db = _load()
+        key = _key(case.nx, case.ny)
+        entry = db.get(key, {"tile": list(tile)})
+        entry["layout"], entry["layout_ms"] = list(layout), times[best]
+        entry["layout_all"] = times
+        db[key] = entry
+        with open(DB, "w") as f:
+            json.dump(db, f, indent=1, sort_keys=True)
+    return layout, times
 
 
 BATCH_CANDIDATES: Tuple[Tuple[int, int], ...] = tuple(

@@ -161,7 +161,7 @@ size_t lbf_tape_bytes(int32_t nx, int32_t ny, int32_t plane_pad, int32_t nsteps,
     return 0;
   const int seg = segment > 0 ? segment : default_segment(nsteps);
   size_t offs[kTapeParts];
-  return tape_layout(nx, ny, plane_stride(nx, ny, plane_pad), nsteps, seg, offs);
+  return tape_layout(nx, ny, plane_stride(nx, ny, plane_pad, 0), nsteps, seg, offs);
 }
 
 int lbf_tape_create(lbf_sim* sim, int32_t nsteps, int32_t segment, lbf_tape** out) {
@@ -178,6 +178,8 @@ int lbf_tape_create(lbf_sim* sim, int32_t nsteps, int32_t segment, lbf_tape** ou
   if (sim->ph.phi_src_flow)
     return fail(LBF_EINVAL, "the adjoint supports phi_src_mdot = 1 only (the phase-field "
                             "source from the mass source)");
+  if (sim->prm.row_block != 0)
+    return fail(LBF_EINVAL, "the adjoint supports row_block = 0 (the plane-major layout) only");
   if (nsteps < 0) return fail(LBF_EINVAL, "nsteps %d", nsteps);
   if (segment < 0) return fail(LBF_EINVAL, "segment %d", segment);
   lbf_tape* t = new (std::nothrow) lbf_tape();

@@ -504,7 +504,7 @@ __global__ __launch_bounds__(256) void k_adj_collide(AdjStepArgs a) {
   if (x >= a.G.nx) return;
   const Geo& G = a.G;
   const Phys& ph = a.ph;
-  const Bufs B = make_bufs(a.F, G.P);
+  const Bufs B = make_bufs(a.F, G);
   const size_t P = (size_t)G.P;
   const int k = y * G.nx + x;
   // forward recompute of the node
@@ -668,7 +668,7 @@ __global__ __launch_bounds__(256) void k_adj_seed(AdjSeedArgs a) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
   if (x >= a.G.nx) return;
   const Geo& G = a.G;
-  const Bufs B = make_bufs(a.F, G.P);
+  const Bufs B = make_bufs(a.F, G);
   const size_t P = (size_t)G.P;
   const int k = y * G.nx + x;
   NodeIn in;
@@ -710,7 +710,7 @@ __global__ __launch_bounds__(256) void k_adj_init(AdjInitArgs a) {
   if (x >= a.G.nx) return;
   const Geo& G = a.G;
   const Phys& ph = a.ph;
-  const Bufs B = make_bufs(a.F, G.P);
+  const Bufs B = make_bufs(a.F, G);
   const size_t P = (size_t)G.P;
   const int k = y * G.nx + x;
   NodeIn in;

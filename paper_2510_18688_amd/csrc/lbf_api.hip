@@ -28,26 +28,35 @@ int fail(int code, const char* fmt, ...) {
   return code;
 }
 
-Layout make_layout(int nx, int ny, int pad) {
+static_assert(NDIST + NLAG == kStateSlots, "a state array holds the distributions and lags");
+
+// Each parity's state is one array of row blocks (the 27 distribution planes,
+// then the 9 lagged ones); the static planes use the same block structure, so
+// a node has one index in all of them.  The read-out planes stay plane-major.
+Layout make_layout(int nx, int ny, int pad, int rb) {
   Layout L{};
-  const size_t P = (size_t)plane_stride(nx, ny, pad) * sizeof(float);
+  const long long P = plane_stride(nx, ny, pad, rb);
+  const int nblk = num_blocks(ny, rb);
+  const long long gs = kStateSlots * P;
+  const size_t PF = round_up((size_t)nx * ny, 64) * sizeof(float);
   size_t off = 0;
   auto take = [&](size_t bytes) {
     size_t o = off;
     off = round_up(off + bytes, kAlign);
     return o;
   };
-  L.dist[0] = take(NDIST * P);
-  L.dist[1] = take(NDIST * P);
-  L.lag[0] = take(NLAG * P);
-  L.lag[1] = take(NLAG * P);
-  L.stat = take(NSTAT * P);
-  L.fields = take(NFIELD * P);
+  const size_t sb = (size_t)array_floats(nblk, gs, P, kStateSlots) * sizeof(float);
+  for (int c = 0; c < 2; ++c) {
+    L.dist[c] = take(sb);
+    L.lag[c] = L.dist[c] + (size_t)NDIST * P * sizeof(float);
+  }
+  L.stat = take((size_t)array_floats(nblk, gs, P, NSTAT) * sizeof(float));
+  L.fields = take(NFIELD * PF);
   L.wstride = (int)round_up((size_t)std::max(nx, ny), 64);
   L.wall = take(4 * (size_t)L.wstride * sizeof(float));
-  const size_t rb = max_blocks(nx, ny) * NRED * sizeof(double);
-  L.red[0] = take(rb);
-  L.red[1] = take(rb);
+  const size_t redb = max_blocks(nx, ny) * NRED * sizeof(double);
+  L.red[0] = take(redb);
+  L.red[1] = take(redb);
   L.redfinal = take(2 * NRED * sizeof(double));
   // column-profile partials (4 per column and chunk of rows), then the
   // column and row profiles
@@ -84,9 +93,12 @@ int validate(const lbf_params* p) {
   if (p->plane_pad < 0 || p->plane_pad > kMaxPlanePad || p->plane_pad % 64)
     return fail(LBF_EINVAL, "plane_pad %d (a multiple of 64 in [0, %d])", p->plane_pad,
                 kMaxPlanePad);
-  if (plane_stride(p->nx, p->ny, p->plane_pad) > kMaxPlane)
-    return fail(LBF_EINVAL, "lattice of %d x %d nodes exceeds the %lld-node limit", p->nx, p->ny,
-                kMaxPlane);
+  if (!valid_row_block(p->row_block))
+    return fail(LBF_EINVAL, "row_block %d (0, 1, 2, 4, 8, 16 or 32)", p->row_block);
+  if (!fits_offsets(p->nx, p->ny, p->plane_pad, p->row_block))
+    return fail(LBF_EINVAL,
+                "lattice of %d x %d nodes exceeds the 32-bit offset limit of its layout "
+                "(row_block %d)", p->nx, p->ny, p->row_block);
   const double pos[] = {p->rho_l, p->rho_g, p->rho_s, p->mu_l, p->mu_g, p->mu_s, p->lam_l,
                         p->lam_g, p->lam_s, p->cp_l, p->cp_g, p->cp_s, p->eps, p->mobility,
                         p->rho_ref};
@@ -163,35 +175,38 @@ __global__ void k_lap_static(Geo G, float* stat) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
   if (x >= G.nx || y >= G.ny) return;
   const float* phi0 = stat + ST_PHI0 * G.P;
-  const float c = phi0[y * G.nx + x];
+  const float c = phi0[nidx(G, x, y)];
   float lap = 0.0f;
 #pragma unroll
   for (int i = 1; i < 9; ++i) {
     const int xx = map_axis(x + cx(i), G.nx, G.px), yy = map_axis(y + cy(i), G.ny, G.py);
-    lap += wgt(i) * (phi0[yy * G.nx + xx] - c);
+    lap += wgt(i) * (phi0[nidx(G, xx, yy)] - c);
   }
-  stat[ST_LAP0 * G.P + y * G.nx + x] = 6.0f * lap;
+  stat[ST_LAP0 * G.P + nidx(G, x, y)] = 6.0f * lap;
 }
 
 // Held temperature per node from a byte mask and a temperature field (both
-// staged in device memory): T where the mask is set, NaN elsewhere.
+// staged in device memory, plane-major): T where the mask is set, NaN
+// elsewhere.
 __global__ void k_set_thold(Geo G, const uint8_t* mask, const float* T, float* stat) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
   if (x >= G.nx || y >= G.ny) return;
   const int k = y * G.nx + x;
-  stat[ST_THOLD * G.P + k] = mask[k] ? T[k] : __builtin_nanf("");
+  stat[ST_THOLD * G.P + nidx(G, x, y)] = mask[k] ? T[k] : __builtin_nanf("");
 }
 
 // Equilibrium populations of the initial state, in post-stream form, into
-// `tmp` (NDIST planes); `in` holds phi (plane 0) and T (plane 1).
+// `tmp` (NDIST planes of a state array); `in` holds phi (plane 0) and T
+// (plane 1), plane-major, PF apart.
 __global__ void k_init_eq(Geo G, Phys ph, const float* stat, const float* in, float* tmp) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
   if (x >= G.nx || y >= G.ny) return;
   const long long P = G.P;
-  const int k = y * G.nx + x;
+  const int kf = y * G.nx + x;
+  const int k = nidx(G, x, y);
   const float* phi = in;
-  const float* T0 = in + P;
-  const float pc = phi[k];
+  const float* T0 = in + G.PF;
+  const float pc = phi[kf];
   float lap = 0.0f;
 #pragma unroll
   for (int i = 1; i < 9; ++i) {
@@ -207,7 +222,7 @@ __global__ void k_init_eq(Geo G, Phys ph, const float* stat, const float* in, fl
   const float chi = clampf(Cp, 0.0f, 1.0f - phi0);
   const float Kliq = zeta(phi0, C, ph.rho_s, ph.rho_l, ph.rho_g) *
                      zeta(phi0, C, ph.cp_s, ph.cp_l, ph.cp_g);
-  const float Tk = T0[k];
+  const float Tk = T0[kf];
   const float rhoH = Kliq * (Tk - ph.T_m) + Kliq * ph.T_m + chi * ph.rho_l * ph.latent;
   const float ET = ph.Eref * Tk;
 #pragma unroll
@@ -226,7 +241,7 @@ __global__ void k_unstream(Geo G, Phys ph, const float* tmp, float* dst, float* 
   const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
   if (x >= G.nx || y >= G.ny) return;
   const long long P = G.P;
-  const int k = y * G.nx + x;
+  const int k = nidx(G, x, y);
   dst[k] = tmp[k];
   // rest populations as float-float: 16-bit high parts (one plane), the
   // exact remainders in the distribution planes
@@ -263,7 +278,7 @@ __global__ void k_unstream(Geo G, Phys ph, const float* tmp, float* dst, float* 
       else wall = dx < 0 ? 2 : 3;
     }
     if (wall < 0) {
-      const int d = dy * G.nx + dx;
+      const int d = nidx(G, dx, dy);
       dst[j * P + k] = tmp[j * P + d];
       dst[(9 + j) * P + k] = tmp[(9 + j) * P + d];
       dst[(18 + j) * P + k] = tmp[(18 + j) * P + d];
@@ -312,7 +327,7 @@ __global__ void k_reduce_blocks(const double* part, int nblocks, double* out) {
 template <int WX>
 __global__ __launch_bounds__(WX) void k_copy_probe(Geo G, Phys ph, BufArgs A, int CY, int nbx,
                                                    int ntiles) {
-  const Bufs B = make_bufs(A, G.P);
+  const Bufs B = make_bufs(A, G);
   const int t = xcd_tile(blockIdx.x, ntiles);
   const int bx = t % nbx, by = t / nbx;
   const int x = bx * WX + (int)threadIdx.x;
@@ -324,7 +339,7 @@ __global__ __launch_bounds__(WX) void k_copy_probe(Geo G, Phys ph, BufArgs A, in
   float acc = 0.0f;
   for (int it = 0; it < y1 - y0; ++it) {
     const int y = up ? y0 + it : y1 - 1 - it;
-    const int k = y * G.nx + x;
+    const int k = nidx(G, x, y);
     float v[27 + NLAG];
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
@@ -351,7 +366,7 @@ __global__ __launch_bounds__(WX) void k_copy_probe(Geo G, Phys ph, BufArgs A, in
       if (used) stp(B.lout, j, P, k, v[27 + j]);
     }
   }
-  if (acc == -1.0e30f) stp(B.lout, LAG_FS, P, y0 * G.nx + x, acc);
+  if (acc == -1.0e30f) stp(B.lout, LAG_FS, P, nidx(G, x, y0), acc);
 }
 
 // ------------------------------------------------------------ launches
@@ -424,6 +439,49 @@ int copy_in(lbf_sim* s, void* dst, const void* src, size_t bytes, int on_device)
   return LBF_OK;
 }
 
+// Copy one plane between a plain array of nx * ny values (`flat`) and the
+// plane that starts at `plane` in a state or static array (row blocks, or
+// plane-major), on the simulation's stream.  `to_plane` gives the direction.
+int plane_copy(lbf_sim* s, float* plane, float* flat, bool to_plane, hipMemcpyKind kind) {
+  const Geo& G = s->G;
+  const size_t n = (size_t)G.nx * G.ny;
+  if (G.nblk == 1) {
+    HIP_TRY(hipMemcpyAsync(to_plane ? plane : flat, to_plane ? flat : plane, n * sizeof(float),
+                           kind, s->stream));
+    return LBF_OK;
+  }
+  const size_t rb = (size_t)G.rmask + 1, full = (size_t)G.ny / rb, rem = (size_t)G.ny - full * rb;
+  const size_t w = rb * G.nx * sizeof(float), pitch = (size_t)G.GS * sizeof(float);
+  if (full)
+    HIP_TRY(hipMemcpy2DAsync(to_plane ? plane : flat, to_plane ? pitch : w,
+                             to_plane ? flat : plane, to_plane ? w : pitch, w, full, kind,
+                             s->stream));
+  if (rem) {
+    float* pb = plane + full * G.GS;
+    float* fb = flat + full * rb * G.nx;
+    HIP_TRY(hipMemcpyAsync(to_plane ? pb : fb, to_plane ? fb : pb, rem * G.nx * sizeof(float),
+                           kind, s->stream));
+  }
+  return LBF_OK;
+}
+
+// Zero the lagged planes of state buffer c (every block).
+int zero_lags(lbf_sim* s, int c) {
+  HIP_TRY(hipMemset2DAsync(fptr(s, s->L.lag[c]), (size_t)s->G.GS * sizeof(float), 0,
+                           NLAG * (size_t)s->G.P * sizeof(float), (size_t)s->G.nblk, s->stream));
+  return LBF_OK;
+}
+
+// Plane copy from caller memory (host or device) into a state or static
+// plane; a host source is released when this returns.
+int plane_in(lbf_sim* s, float* plane, const float* src, int on_device) {
+  int rc = plane_copy(s, plane, const_cast<float*>(src), true,
+                      on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice);
+  if (rc) return rc;
+  if (!on_device) HIP_TRY(hipStreamSynchronize(s->stream));
+  return LBF_OK;
+}
+
 // Stability check of lbf_step: fixed-order sum of the partials a step wrote
 // for the state it read (time level `level`), then non-finite count and
 // max |u| on the host.
@@ -451,10 +509,10 @@ extern "C" {
 
 const char* lbf_last_error(void) { return g_err; }
 
-size_t lbf_workspace_bytes(int32_t nx, int32_t ny, int32_t plane_pad) {
+size_t lbf_workspace_bytes(int32_t nx, int32_t ny, int32_t plane_pad, int32_t row_block) {
   if (nx < 1 || ny < 1 || plane_pad < 0 || plane_pad > kMaxPlanePad || plane_pad % 64) return 0;
-  if (plane_stride(nx, ny, plane_pad) > kMaxPlane) return 0;
-  return make_layout(nx, ny, plane_pad).total;
+  if (!valid_row_block(row_block) || !fits_offsets(nx, ny, plane_pad, row_block)) return 0;
+  return make_layout(nx, ny, plane_pad, row_block).total;
 }
 
 int lbf_create(const lbf_params* params, void* stream, void* workspace, size_t workspace_bytes,
@@ -475,9 +533,18 @@ int lbf_create(const lbf_params* params, void* stream, void* workspace, size_t w
     s->G.tbc[w] = params->thermal_bc[w];
     if (params->thermal_bc[w] == LBF_DIRICHLET) s->G.tmask |= 1 << w;
   }
-  s->G.P = (int)plane_stride(params->nx, params->ny, params->plane_pad);
+  const int rb = params->row_block;
+  s->G.P = (int)plane_stride(params->nx, params->ny, params->plane_pad, rb);
+  s->G.GS = kStateSlots * s->G.P;
+  s->G.nblk = num_blocks(params->ny, rb);
+  s->G.rbs = 31;
+  if (rb)
+    for (s->G.rbs = 0; (1 << s->G.rbs) < rb; ++s->G.rbs) {
+    }
+  s->G.rmask = rb ? rb - 1 : 0x7fffffff;
+  s->G.PF = (int)round_up((size_t)params->nx * params->ny, 64);
   fill_phys(params, s->ph);
-  s->L = make_layout(params->nx, params->ny, params->plane_pad);
+  s->L = make_layout(params->nx, params->ny, params->plane_pad, rb);
   s->stream = (hipStream_t)stream;
   const size_t need = s->L.total;
   if (workspace) {
@@ -529,11 +596,10 @@ void lbf_destroy(lbf_sim* s) {
 
 int lbf_set_geometry(lbf_sim* s, const float* phi0, const float* cos_theta, int32_t on_device) {
   if (!s || !phi0 || !cos_theta) return fail(LBF_EINVAL, "NULL argument");
-  const size_t n = (size_t)s->G.nx * s->G.ny;
   float* stat = fptr(s, s->L.stat);
-  int rc = copy_in(s, stat + ST_PHI0 * s->G.P, phi0, n * sizeof(float), on_device);
+  int rc = plane_in(s, stat + ST_PHI0 * (size_t)s->G.P, phi0, on_device);
   if (rc) return rc;
-  rc = copy_in(s, stat + ST_CTH * s->G.P, cos_theta, n * sizeof(float), on_device);
+  rc = plane_in(s, stat + ST_CTH * (size_t)s->G.P, cos_theta, on_device);
   if (rc) return rc;
   hipLaunchKernelGGL(k_lap_static, node_grid(s), dim3(256), 0, s->stream, s->G, stat);
   HIP_TRY(hipGetLastError());
@@ -552,7 +618,7 @@ int lbf_set_isothermal(lbf_sim* s, const uint8_t* mask, const float* T_hold, int
   const size_t n = (size_t)s->G.nx * s->G.ny;
   // stage both arrays in the read-out planes (free between calls)
   float* stage = fptr(s, s->L.fields);
-  uint8_t* mstage = reinterpret_cast<uint8_t*>(stage + s->G.P);
+  uint8_t* mstage = reinterpret_cast<uint8_t*>(stage + s->G.PF);
   int rc = copy_in(s, stage, T_hold, n * sizeof(float), on_device);
   if (rc) return rc;
   rc = copy_in(s, mstage, mask, n, on_device);
@@ -581,15 +647,21 @@ int lbf_init_fields(lbf_sim* s, const float* phi, const float* T, int32_t on_dev
   float* stage = fptr(s, s->L.fields);
   int rc = copy_in(s, stage, phi, n * sizeof(float), on_device);
   if (rc) return rc;
-  rc = copy_in(s, stage + s->G.P, T, n * sizeof(float), on_device);
+  rc = copy_in(s, stage + s->G.PF, T, n * sizeof(float), on_device);
   if (rc) return rc;
   s->cur = 0;
   float* tmp = fptr(s, s->L.dist[1]);
   hipLaunchKernelGGL(k_init_eq, node_grid(s), dim3(256), 0, s->stream, s->G, s->ph,
                      (const float*)fptr(s, s->L.stat), (const float*)stage, tmp);
   HIP_TRY(hipGetLastError());
-  HIP_TRY(hipMemsetAsync(fptr(s, s->L.lag[0]), 0, NLAG * (size_t)s->G.P * sizeof(float),
-                         s->stream));
+  // the lagged planes of every block, in both buffers: planes a step does
+  // not write (the high part of h_0, which shares g_0's plane, and (phi u)_y
+  // under the flow-divergence source) then stay zero, and a saved state does
+  // not depend on what the workspace held
+  for (int c = 0; c < 2; ++c) {
+    int rc = zero_lags(s, c);
+    if (rc) return rc;
+  }
   hipLaunchKernelGGL(k_unstream, node_grid(s), dim3(256), 0, s->stream, s->G, s->ph,
                      (const float*)tmp, fptr(s, s->L.dist[0]), fptr(s, s->L.stat),
                      fptr(s, s->L.lag[0]), (const float*)fptr(s, s->L.wall), s->L.wstride);
@@ -606,9 +678,11 @@ int lbf_set_poststream_state(lbf_sim* s, const float* dist, const float* lag, in
   if (!s || !dist || !lag) return fail(LBF_EINVAL, "NULL argument");
   if (!s->have_geo) return fail(LBF_ESTATE, "lbf_set_geometry must precede the state");
   const size_t n = (size_t)s->G.nx * s->G.ny;
+  int rc0 = zero_lags(s, 1 - s->cur);
+  if (rc0) return rc0;
   float* tmp = fptr(s, s->L.dist[1 - s->cur]);
   for (int pl = 0; pl < NDIST; ++pl) {
-    int rc = copy_in(s, tmp + (size_t)pl * s->G.P, dist + pl * n, n * sizeof(float), on_device);
+    int rc = plane_in(s, tmp + (size_t)pl * s->G.P, dist + pl * n, on_device);
     if (rc) return rc;
   }
   float* lg = fptr(s, s->L.lag[s->cur]);
@@ -616,8 +690,7 @@ int lbf_set_poststream_state(lbf_sim* s, const float* dist, const float* lag, in
   // the rest populations come from dist
   const int dst_plane[7] = {LAG_FS, LAG_Q, LAG_JX, LAG_JY, LAG_P, LAG_UX, LAG_UY};
   for (int pl = 0; pl < 7; ++pl) {
-    int rc = copy_in(s, lg + (size_t)dst_plane[pl] * s->G.P, lag + pl * n, n * sizeof(float),
-                     on_device);
+    int rc = plane_in(s, lg + (size_t)dst_plane[pl] * s->G.P, lag + pl * n, on_device);
     if (rc) return rc;
   }
   hipLaunchKernelGGL(k_unstream, node_grid(s), dim3(256), 0, s->stream, s->G, s->ph,
@@ -679,7 +752,7 @@ int lbf_read_fields(lbf_sim* s, float* dst, int32_t dst_on_device) {
   const size_t n = (size_t)s->G.nx * s->G.ny;
   const float* F = fptr(s, s->L.fields);
   for (int f = 0; f < LBF_NFIELDS; ++f)
-    HIP_TRY(hipMemcpyAsync(dst + f * n, F + f * s->G.P, n * sizeof(float),
+    HIP_TRY(hipMemcpyAsync(dst + f * n, F + f * (size_t)s->G.PF, n * sizeof(float),
                            dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
                            s->stream));
   HIP_TRY(hipStreamSynchronize(s->stream));
@@ -693,7 +766,7 @@ int lbf_read_field(lbf_sim* s, int32_t field_id, float* dst, int32_t dst_on_devi
   int rc = launch_step(s, MODE_FIELDS, false, nullptr);
   if (rc) return rc;
   const size_t n = (size_t)s->G.nx * s->G.ny;
-  HIP_TRY(hipMemcpyAsync(dst, fptr(s, s->L.fields) + field_id * s->G.P, n * sizeof(float),
+  HIP_TRY(hipMemcpyAsync(dst, fptr(s, s->L.fields) + field_id * (size_t)s->G.PF, n * sizeof(float),
                          dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
                          s->stream));
   HIP_TRY(hipStreamSynchronize(s->stream));
@@ -767,12 +840,14 @@ int lbf_save_state(lbf_sim* s, void* dst, size_t cap) {
   const size_t need = lbf_state_bytes(s);
   if (cap < need) return fail(LBF_ENOMEM, "state needs %zu bytes", need);
   char* d = (char*)dst;
-  const size_t nb = (size_t)s->G.nx * s->G.ny * sizeof(float);
-  const size_t pb = (size_t)s->G.P * sizeof(float);
-  HIP_TRY(hipMemcpy2DAsync(d, nb, s->ws + s->L.dist[s->cur], pb, nb, NDIST,
-                           hipMemcpyDeviceToDevice, s->stream));
-  HIP_TRY(hipMemcpy2DAsync(d + NDIST * nb, nb, s->ws + s->L.lag[s->cur], pb, nb, NLAG,
-                           hipMemcpyDeviceToDevice, s->stream));
+  const size_t n = (size_t)s->G.nx * s->G.ny, nb = n * sizeof(float);
+  // the distributions, then the lagged planes: the state array's planes in order
+  float* st = fptr(s, s->L.dist[s->cur]);
+  for (int pl = 0; pl < kStateSlots; ++pl) {
+    int rc = plane_copy(s, st + (size_t)pl * s->G.P, (float*)d + pl * n, false,
+                        hipMemcpyDeviceToDevice);
+    if (rc) return rc;
+  }
   const size_t db = NDIST * nb, lb = NLAG * nb;
   long long hdr[8] = {kStateMagic, s->step, s->G.nx, s->G.ny, 0, 0, 0, 0};
   HIP_TRY(hipMemcpyAsync(d + db + lb, hdr, sizeof hdr, hipMemcpyHostToDevice, s->stream));
@@ -785,8 +860,7 @@ int lbf_load_state(lbf_sim* s, const void* src, size_t bytes) {
   const size_t need = lbf_state_bytes(s);
   if (bytes < need) return fail(LBF_EINVAL, "state of %zu bytes, %zu needed", bytes, need);
   const char* d = (const char*)src;
-  const size_t nb = (size_t)s->G.nx * s->G.ny * sizeof(float);
-  const size_t pb = (size_t)s->G.P * sizeof(float);
+  const size_t n = (size_t)s->G.nx * s->G.ny, nb = n * sizeof(float);
   const size_t db = NDIST * nb, lb = NLAG * nb;
   long long hdr[8];
   HIP_TRY(hipMemcpyAsync(hdr, d + db + lb, sizeof hdr, hipMemcpyDeviceToHost, s->stream));
@@ -794,10 +868,12 @@ int lbf_load_state(lbf_sim* s, const void* src, size_t bytes) {
   if (hdr[0] != kStateMagic || hdr[2] != s->G.nx || hdr[3] != s->G.ny)
     return fail(LBF_EINVAL, "state buffer does not match this lattice");
   if (!s->have_geo) return fail(LBF_ESTATE, "lbf_set_geometry must precede lbf_load_state");
-  HIP_TRY(hipMemcpy2DAsync(s->ws + s->L.dist[s->cur], pb, d, nb, nb, NDIST,
-                           hipMemcpyDeviceToDevice, s->stream));
-  HIP_TRY(hipMemcpy2DAsync(s->ws + s->L.lag[s->cur], pb, d + db, nb, nb, NLAG,
-                           hipMemcpyDeviceToDevice, s->stream));
+  float* st = fptr(s, s->L.dist[s->cur]);
+  for (int pl = 0; pl < kStateSlots; ++pl) {
+    int rc = plane_copy(s, st + (size_t)pl * s->G.P, (float*)d + pl * n, true,
+                        hipMemcpyDeviceToDevice);
+    if (rc) return rc;
+  }
   HIP_TRY(hipStreamSynchronize(s->stream));
   s->step = hdr[1];
   s->have_init = true;

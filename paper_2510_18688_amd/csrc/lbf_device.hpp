@@ -83,7 +83,22 @@ struct Geo {
   int tbc[4];        // per wall: 0 adiabatic, 1 Dirichlet (bottom, top, left, right)
   int tmask;         // bit w set when wall w is Dirichlet
   int P;             // plane stride in floats (every byte offset fits 32 bits)
+  // Row blocks: rows rb i .. rb i + rb - 1 of every plane of a state array
+  // (27 distributions, then 9 lagged planes) lie in block i, GS floats after
+  // block i - 1; inside a block each plane's rows are back to back, P floats
+  // after the previous plane's.  rbs = log2 rb, rmask = rb - 1; the plain
+  // plane-major layout is one block (rbs 31, rmask 0x7fffffff).
+  int GS;            // block stride in floats
+  int rbs, rmask;
+  int nblk;          // number of blocks
+  int PF;            // plane stride of the read-out planes (plane-major)
 };
+
+// Index of node (x, y) in every plane of a state array, and in the static
+// planes (same block structure).
+__host__ __device__ __forceinline__ int nidx(const Geo& G, int x, int y) {
+  return (y >> G.rbs) * G.GS + (y & G.rmask) * G.nx + x;
+}
 
 // Physical constants in the form the kernels use them.
 struct Phys {
@@ -150,19 +165,29 @@ struct BufArgs {
   double* red;
 };
 
-__device__ __forceinline__ Bufs make_bufs(const BufArgs& a, int P) {
-  const uint32_t pb = (uint32_t)P * 4u;
+// Bytes from a resource's base to the end of its array: the base holds
+// `planes` planes of the last block (all earlier blocks lie before them).
+__device__ __forceinline__ uint32_t block_extent(const Geo& G, int planes) {
+  return (uint32_t)(((size_t)(G.nblk - 1) * G.GS + (size_t)planes * G.P) * 4u);
+}
+
+__device__ __forceinline__ Bufs make_bufs(const BufArgs& a, const Geo& G) {
+  const size_t P = (size_t)G.P;
+  const uint32_t e9 = block_extent(G, 9);
   Bufs B;
-  B.fin = make_rsrc(a.din, 9 * pb);
-  B.gin = make_rsrc(a.din + 9 * (size_t)P, 9 * pb);
-  B.hin = make_rsrc(a.din + 18 * (size_t)P, 9 * pb);
-  B.fout = make_rsrc(a.dout, 9 * pb);
-  B.gout = make_rsrc(a.dout + 9 * (size_t)P, 9 * pb);
-  B.hout = make_rsrc(a.dout + 18 * (size_t)P, 9 * pb);
-  B.lin = make_rsrc(a.lin, NLAG * pb);
-  B.lout = make_rsrc(a.lout, NLAG * pb);
-  B.stat = make_rsrc(a.stat, NSTAT * pb);
-  B.fields = make_rsrc(a.fields, a.fields ? NFIELD * pb : 0u);
+  B.fin = make_rsrc(a.din, e9);
+  B.gin = make_rsrc(a.din + 9 * P, e9);
+  B.hin = make_rsrc(a.din + 18 * P, e9);
+  B.fout = make_rsrc(a.dout, e9);
+  B.gout = make_rsrc(a.dout + 9 * P, e9);
+  B.hout = make_rsrc(a.dout + 18 * P, e9);
+  B.lin = make_rsrc(a.lin, block_extent(G, NLAG));
+  B.lout = make_rsrc(a.lout, block_extent(G, NLAG));
+  B.stat = make_rsrc(a.stat, block_extent(G, NSTAT));
+  // read-out planes (plane-major, PF apart), or the 3 moment planes of a
+  // recomputed step (state indexing, P apart)
+  const size_t fe = (NFIELD * (size_t)G.PF > 3 * P ? NFIELD * (size_t)G.PF : 3 * P) * 4u;
+  B.fields = make_rsrc(a.fields, a.fields ? (uint32_t)fe : 0u);
   B.wallT = a.wallT;
   B.wstride = a.wstride;
   B.red = a.red;
@@ -261,7 +286,7 @@ struct Pull9 {
 __device__ __forceinline__ void pull9(const Geo& G, int x, int y, Pull9& p) {
   const int sx[3] = {pull_axis(x, -1, G.nx, G.px), x, pull_axis(x, 1, G.nx, G.px)};
   const int sy[3] = {pull_axis(y, -1, G.ny, G.py), y, pull_axis(y, 1, G.ny, G.py)};
-  const int k = y * G.nx + x;
+  const int k = nidx(G, x, y);
   p.k4 = (uint32_t)k * 4u;
   p.wmask = 0u;
   p.ymask = 0u;
@@ -269,7 +294,7 @@ __device__ __forceinline__ void pull9(const Geo& G, int x, int y, Pull9& p) {
   for (int i = 0; i < 9; ++i) {
     const int xs = sx[cx(i) + 1], ys = sy[cy(i) + 1];
     const bool wy = ys < 0, w = wy || xs < 0;
-    p.off[i] = w ? p.k4 : (uint32_t)(ys * G.nx + xs) * 4u;
+    p.off[i] = w ? p.k4 : (uint32_t)nidx(G, xs, ys) * 4u;
     p.wmask |= (uint32_t)w << i;
     p.ymask |= (uint32_t)wy << i;
   }

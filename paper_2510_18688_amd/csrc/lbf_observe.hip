@@ -33,7 +33,7 @@ __global__ __launch_bounds__(256) void k_col_partial(Geo G, const float* __restr
                                                      double* __restrict__ part) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x, ch = blockIdx.y;
   if (x >= G.nx) return;
-  const size_t P = (size_t)G.P;
+  const size_t P = (size_t)G.PF;   // read-out planes are plane-major
   const float* fs = fields + (size_t)LBF_FIELD_FS * P;
   const float* chi = fields + (size_t)LBF_FIELD_CHI * P;
   const int y0 = ch * kProfileChunk, y1 = min(y0 + kProfileChunk, G.ny);
@@ -82,7 +82,7 @@ __global__ __launch_bounds__(256) void k_row_profiles(Geo G, const float* __rest
                                                       double* __restrict__ row) {
   __shared__ double s[6][256];
   const int y = blockIdx.x, l = threadIdx.x;
-  const size_t P = (size_t)G.P;
+  const size_t P = (size_t)G.PF;   // read-out planes are plane-major
   const float* fs = fields + (size_t)LBF_FIELD_FS * P + (size_t)y * G.nx;
   const float* chi = fields + (size_t)LBF_FIELD_CHI * P + (size_t)y * G.nx;
   const double none_left = 1e300, none_right = -1e300;

@@ -25,19 +25,45 @@ constexpr size_t kAlign = 256;
 
 inline size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
-// Plane stride: nx * ny rounded up to 64 floats (256 bytes).
-// Floats between consecutive planes: the node count rounded up to 64, plus
-// `pad` (a multiple of 64).  Which HBM channels the 34 planes of a step hit
-// at one time depends on this stride; the autotuner picks the pad per size.
-inline long long plane_stride(int nx, int ny, int pad) {
-  return (long long)round_up((size_t)nx * ny, 64) + pad;
+// Plane stride in floats.  Plane-major (rb = 0): the node count rounded up
+// to 64, plus `pad`.  Row blocks of rb rows: rb rows of nx rounded up to 64,
+// plus `pad`.  Which HBM channels the 34 planes of a step hit at one time
+// depends on this stride; the autotuner picks the pad per size and layout.
+inline long long plane_stride(int nx, int ny, int pad, int rb) {
+  return (long long)round_up((size_t)nx * (size_t)(rb ? rb : ny), 64) + pad;
+}
+
+// Planes of one state array: the 27 distributions, then the 9 lagged planes.
+constexpr int kStateSlots = 27 + 9;
+
+inline int num_blocks(int ny, int rb) { return rb ? (ny + rb - 1) / rb : 1; }
+
+// Floats from an array's base to its end when its last block holds `planes`
+// planes (block stride gs).
+inline long long array_floats(int nblk, long long gs, long long P, int planes) {
+  return (long long)(nblk - 1) * gs + (long long)planes * P;
 }
 
 constexpr int kMaxPlanePad = 65536;
 
-// Kernels address each block of planes with 32-bit byte offsets: the 27
-// distribution planes must span less than 4 GiB.
+// Kernels address each block of planes with 32-bit byte offsets.
+// Plane-major: the 27 distribution planes must span less than 4 GiB.
 constexpr long long kMaxPlane = (0xFFFFFFFFLL / (4LL * 27)) / 64 * 64;
+// Row blocks: a whole state array must.
+constexpr long long kMaxStateFloats = 0xFFFFFFFFLL / 4;
+
+inline bool valid_row_block(int rb) {
+  return rb == 0 || rb == 1 || rb == 2 || rb == 4 || rb == 8 || rb == 16 || rb == 32;
+}
+
+// Every byte offset the kernels form fits 32 bits (and every node index an
+// int): plane-major, the 27 distribution planes; row blocks, a whole state
+// array.
+inline bool fits_offsets(int nx, int ny, int pad, int rb) {
+  const long long P = plane_stride(nx, ny, pad, rb);
+  if (!rb) return P <= kMaxPlane;
+  return array_floats(num_blocks(ny, rb), kStateSlots * P, P, kStateSlots) <= kMaxStateFloats;
+}
 
 // Worst-case number of per-block partial sums: 64-wide strips, 1 row each.
 inline size_t max_blocks(int nx, int ny) { return ((size_t)(nx + 63) / 64) * (size_t)ny; }
@@ -50,7 +76,7 @@ struct Layout {
   int wstride;
 };
 
-Layout make_layout(int nx, int ny);
+Layout make_layout(int nx, int ny, int pad, int rb);
 
 }  // namespace lbfi
 

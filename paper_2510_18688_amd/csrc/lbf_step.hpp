@@ -69,7 +69,7 @@ __device__ __forceinline__ void node_load(const Geo& G, const Phys& ph, const Bu
                                           int yy, NodeIn& in, bool gather_u = true) {
   in.flux = 0.0f;
   pull_gh(G, ph, B, xx, yy, in.g, in.h, in.flux);
-  const int k = yy * G.nx + xx;
+  const int k = nidx(G, xx, yy);
   in.fsp = ldp(B.lin, LAG_FS, G.P, k);
   in.Qp = ldp(B.lin, LAG_Q, G.P, k);
   in.phi0 = ldp(B.stat, ST_PHI0, G.P, k);
@@ -87,7 +87,7 @@ __device__ __forceinline__ void node_load(const Geo& G, const Phys& ph, const Bu
     float ux[9], uy[9];
 #pragma unroll
     for (int i = 1; i < 9; ++i) {
-      const int kk = map_axis(yy + cy(i), G.ny, G.py) * G.nx + map_axis(xx + cx(i), G.nx, G.px);
+      const int kk = nidx(G, map_axis(xx + cx(i), G.nx, G.px), map_axis(yy + cy(i), G.ny, G.py));
       ux[i] = cx(i) ? ldp(B.lin, LAG_UX, G.P, kk) : 0.0f;
       uy[i] = cy(i) ? ldp(B.lin, LAG_UY, G.P, kk) : 0.0f;
     }
@@ -121,7 +121,7 @@ struct URow {
 
 __device__ __forceinline__ void urow_load(const Geo& G, const Bufs& B, int x, int xl, int xr,
                                           int yy, bool left, bool right, URow& u) {
-  const int row = yy * G.nx;
+  const int row = nidx(G, 0, yy);
   u.x = ldp(B.lin, LAG_UX, G.P, row + x);
   u.y = ldp(B.lin, LAG_UY, G.P, row + x);
   if (left) {
@@ -182,7 +182,7 @@ template <bool LAP0 = true>
 __device__ __forceinline__ void flow_load(const Geo& G, const Phys& ph, const Bufs& B, int x,
                                           int y, FlowIn& in) {
   pull_f(G, B, x, y, in.f);
-  const int k = y * G.nx + x;
+  const int k = nidx(G, x, y);
   in.cth = ldp(B.stat, ST_CTH, G.P, k);
   in.lap0 = LAP0 ? ldp(B.stat, ST_LAP0, G.P, k) : 0.0f;
   in.jxp = ldp(B.lin, LAG_JX, G.P, k);
@@ -340,7 +340,7 @@ __device__ __forceinline__ void step_strip(const Geo& G, const Phys& ph, const B
     }
     __syncthreads();
     if (act) {
-      const int k = y * G.nx + x;
+      const int k = nidx(G, x, y);
       Stencil S;
       const int sm1 = (y - 1) & 3, s0 = y & 3, sp1 = (y + 1) & 3;
 #pragma unroll
@@ -411,19 +411,21 @@ __device__ __forceinline__ void step_strip(const Geo& G, const Phys& ph, const B
       } else {
         collide_node<false, MRT>(ph, cm, S, phi0, fin.cth, lap0, cQp, jxp, jyp, crh,
                                  fin.thold, fv, cg, ch, o);
-        stp(B.fields, 0, P, k, cm.phi);
-        stp(B.fields, 1, P, k, cm.T);
-        stp(B.fields, 2, P, k, 1.0f - cm.fs);
-        stp(B.fields, 3, P, k, cm.fs);
-        stp(B.fields, 4, P, k, o.ux);
-        stp(B.fields, 5, P, k, o.uy);
-        stp(B.fields, 6, P, k, o.p);
-        stp(B.fields, 7, P, k, cm.rhoH);
-        stp(B.fields, 8, P, k, o.mu);
-        stp(B.fields, 9, P, k, cm.C);
-        stp(B.fields, 10, P, k, cm.chi);
-        stp(B.fields, 11, P, k, cm.rho);
-        stp(B.fields, 12, P, k, cm.ref_g + cm.sg);
+        // read-out planes are plane-major whatever the state's layout
+        const int kf = y * G.nx + x, PF = G.PF;
+        stp(B.fields, 0, PF, kf, cm.phi);
+        stp(B.fields, 1, PF, kf, cm.T);
+        stp(B.fields, 2, PF, kf, 1.0f - cm.fs);
+        stp(B.fields, 3, PF, kf, cm.fs);
+        stp(B.fields, 4, PF, kf, o.ux);
+        stp(B.fields, 5, PF, kf, o.uy);
+        stp(B.fields, 6, PF, kf, o.p);
+        stp(B.fields, 7, PF, kf, cm.rhoH);
+        stp(B.fields, 8, PF, kf, o.mu);
+        stp(B.fields, 9, PF, kf, cm.C);
+        stp(B.fields, 10, PF, kf, cm.chi);
+        stp(B.fields, 11, PF, kf, cm.rho);
+        stp(B.fields, 12, PF, kf, cm.ref_g + cm.sg);
       }
       if (RED) {
         const float um = sqrtf(o.ux * o.ux + o.uy * o.uy);
@@ -482,7 +484,7 @@ template <int WX, int MODE, bool RED, bool MRT = false>
 __global__ __launch_bounds__(WX) __attribute__((amdgpu_waves_per_eu(kWaves, 8))) void
 step_kernel(Geo G, Phys ph, BufArgs A, int CY, int nbx, int ntiles) {
   __shared__ StepShared<WX> sh;
-  const Bufs B = make_bufs(A, G.P);
+  const Bufs B = make_bufs(A, G);
   const int t = xcd_tile(blockIdx.x, ntiles);
   const int bx = t % nbx, by = t / nbx;
   double* red = RED ? A.red + (size_t)t * NRED : nullptr;
@@ -521,7 +523,7 @@ batch_step_kernel(const InstDesc* __restrict__ D, const int2* __restrict__ items
     const Phys ph = D[item.x].ph;
     const BufArgs args = D[item.x].A[parity];
     const int CY = D[item.x].CY, nbx = D[item.x].nbx;
-    const Bufs B = make_bufs(args, geo.P);
+    const Bufs B = make_bufs(args, geo);
     const int bx = item.y % nbx, by = item.y / nbx;
     __syncthreads();   // the LDS ring of the previous item is free
     step_strip<WX, MODE_STEP, false, MRT>(geo, ph, B, bx, by, CY, (by & 1) ? -1 : 1, nullptr,

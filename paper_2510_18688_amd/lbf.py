@@ -57,7 +57,7 @@ class Params(C.Structure):
             "cp_l", "cp_g", "cp_s", "latent", "T_m", "sigma", "eps", "mobility", "cos_psi",
             "rho_ref", "T_substrate", "pcm_floor")] + [
         ("mrt", C.c_int32), ("check_every", C.c_int32), ("phi_src_mdot", C.c_int32),
-        ("reserved3", C.c_int32), ("s_b", C.c_double), ("s_q", C.c_double),
+        ("row_block", C.c_int32), ("s_b", C.c_double), ("s_q", C.c_double),
         ("s_g", C.c_double), ("grav", C.c_double * 2), ("u_solid", C.c_double * 2)]
 
 
@@ -78,7 +78,7 @@ def load(path: str = LIB_PATH):
     L = C.CDLL(path)
     vp, i32, f_p, d_p = C.c_void_p, C.c_int32, C.POINTER(C.c_float), C.POINTER(C.c_double)
     L.lbf_workspace_bytes.restype = C.c_size_t
-    L.lbf_workspace_bytes.argtypes = [i32, i32, i32]
+    L.lbf_workspace_bytes.argtypes = [i32, i32, i32, i32]
     L.lbf_create.argtypes = [C.POINTER(Params), vp, vp, C.c_size_t, C.POINTER(vp)]
     L.lbf_set_geometry.argtypes = [vp, vp, vp, i32]
     L.lbf_set_wall_temperature.argtypes = [vp, i32, vp, i32, i32]
@@ -167,28 +167,34 @@ def _f32_host(a) -> np.ndarray:
 class Sim:
     """One lattice on the current HIP device; workspace owned by a torch tensor.
 
-    `tile` is the launch shape (threads along x, rows per block) and
-    `plane_pad` the padding between workspace planes in floats (a multiple
-    of 64); both change speed only, and `autotune.lookup` /
-    `autotune.lookup_pad` return the tuned values for a lattice size.
+    `tile` is the launch shape (threads along x, rows per block),
+    `row_block` the state's memory layout (0 plane-major; 1 .. 32 rows per
+    block of all planes, lbf_params.row_block) and `plane_pad` the padding
+    between its planes in floats (a multiple of 64); they change speed only,
+    and `autotune.lookup` / `autotune.lookup_layout` return the tuned values
+    for a lattice size.  The adjoint (`Tape`) needs row_block 0.
     `check_every`: `step` raises LbfError(LBF_EUNSTABLE) after a step that
     starts at a time level divisible by it found a non-finite or too fast
     state (0: no checks)."""
 
     def __init__(self, case, tile: Optional[Sequence[int]] = None, device: str = "cuda",
-                 stream=None, plane_pad: int = 0, check_every: int = 1000):
+                 stream=None, plane_pad: int = 0, check_every: int = 1000,
+                 row_block: int = 4):
         torch = _torch()
         L = load()
         self.case = case
         self.nx, self.ny = case.nx, case.ny
         self.params = make_params(case)
         self.params.plane_pad = int(plane_pad)
+        self.params.row_block = int(row_block)
         self.params.check_every = int(check_every)
         self.device = torch.device(device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
-        nbytes = L.lbf_workspace_bytes(self.nx, self.ny, self.params.plane_pad)
+        nbytes = L.lbf_workspace_bytes(self.nx, self.ny, self.params.plane_pad,
+                                       self.params.row_block)
         if nbytes == 0:
-            raise LbfError(-1, f"bad lattice size {self.nx} x {self.ny} or plane_pad {plane_pad}")
+            raise LbfError(-1, f"bad lattice size {self.nx} x {self.ny}, plane_pad {plane_pad} "
+                               f"or row_block {row_block}")
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         h = C.c_void_p()
         check(L.lbf_create(C.byref(self.params), C.c_void_p(self.stream.cuda_stream),
@@ -491,7 +497,7 @@ def _freeze_function():
 
         @staticmethod
         def forward(ctx, cos_theta, wall_T, case, steps, segment, tile):
-            sim = Sim(case, tile=tile)
+            sim = Sim(case, tile=tile, row_block=0)
             dev = sim.device
             sim.set_geometry(torch.as_tensor(np.ascontiguousarray(case.phi0, dtype=np.float32),
                                              device=dev),

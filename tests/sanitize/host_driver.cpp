@@ -31,9 +31,11 @@ static lbf_params base() {
 
 int main() {
   // sizes
-  EXPECT(lbf_workspace_bytes(0, 5, 0) == 0);
-  EXPECT(lbf_workspace_bytes(24, 16, 0) > 0);
-  EXPECT(lbf_workspace_bytes(24, 16, 7) == 0);
+  EXPECT(lbf_workspace_bytes(0, 5, 0, 0) == 0);
+  EXPECT(lbf_workspace_bytes(24, 16, 0, 0) > 0);
+  EXPECT(lbf_workspace_bytes(24, 16, 0, 4) > 0);
+  EXPECT(lbf_workspace_bytes(24, 16, 7, 0) == 0);
+  EXPECT(lbf_workspace_bytes(24, 16, 0, 3) == 0);
   EXPECT(lbf_ch_workspace_bytes(10, 10, 1) == 2 * 512);
   EXPECT(lbf_ch_noalloc_max_nodes() == (size_t)1 << 22);
   // invalid parameter sets are refused before any device call
@@ -48,6 +50,7 @@ int main() {
     {"plane_pad", [](lbf_params& p) { p.plane_pad = 65; }},
     {"mrt rate", [](lbf_params& p) { p.mrt = 1; p.s_b = 2.5; }},
     {"phi_src_mdot", [](lbf_params& p) { p.phi_src_mdot = 3; }},
+    {"row_block", [](lbf_params& p) { p.row_block = 6; }},
     {"thermal_bc", [](lbf_params& p) { p.thermal_bc[2] = 5; }},
     {"grav", [](lbf_params& p) { p.grav[0] = 1.0 / 0.0; }},
   };

@@ -78,19 +78,36 @@ def test_params3_layout_matches_header(tmp_path):
                                      P.wall_T.offset, P.phi_src_mdot.offset]
 
 
-def test_workspace_bytes(L):
-    assert L.lbf_workspace_bytes(0, 5, 0) == 0
+@pytest.mark.parametrize("rb", [0, 1, 2, 4, 8, 16, 32])
+def test_workspace_bytes(L, rb):
+    assert L.lbf_workspace_bytes(0, 5, 0, rb) == 0
     for bad in (-64, 32, 65536 + 64):
-        assert L.lbf_workspace_bytes(64, 48, bad) == 0
-    assert L.lbf_workspace_bytes(64, 48, 64) > L.lbf_workspace_bytes(64, 48, 0)
+        assert L.lbf_workspace_bytes(64, 48, bad, rb) == 0
+    assert L.lbf_workspace_bytes(64, 48, 64, rb) > L.lbf_workspace_bytes(64, 48, 0, rb)
     assert L.lbf_tape_bytes(64, 48, 32, 100, 0) == 0
     assert L.lbf_tape_bytes(64, 48, 128, 100, 0) > L.lbf_tape_bytes(64, 48, 0, 100, 0)
-    small = L.lbf_workspace_bytes(64, 48, 0)
-    big = L.lbf_workspace_bytes(2048, 2048, 0)
+    small = L.lbf_workspace_bytes(64, 48, 0, rb)
+    big = L.lbf_workspace_bytes(2048, 2048, 0, rb)
     assert small > 64 * 48 * 4 * (27 * 2 + 9 * 2 + 4)
-    # 76 resident state planes (27 + 9 ping-pong, 4 static) + 13 read-out
-    # planes + reduction scratch
-    assert 2048 * 2048 * 4 * 89 <= big <= 2048 * 2048 * 4 * 92
+    # 76 resident state planes (27 + 9 ping-pong, 4 static; in row blocks
+    # the static array spans the blocks' stride, 36 plane slots) + 13
+    # read-out planes + reduction scratch
+    lo, hi = (89, 92) if rb == 0 else (2 * 36 + 36 + 13 - 32 + 1, 2 * 36 + 36 + 13 + 3)
+    assert 2048 * 2048 * 4 * lo <= big <= 2048 * 2048 * 4 * hi, big / (2048 * 2048 * 4)
+
+
+def test_row_block_validation(L):
+    for bad in (-1, 3, 5, 64):
+        assert L.lbf_workspace_bytes(64, 48, 0, bad) == 0
+        p = lbf.make_params(W.sessile_drop(nx=16, ny=8))
+        p.row_block = bad
+        h = C.c_void_p()
+        assert L.lbf_create(C.byref(p), None, None, 0, C.byref(h)) == -1
+        assert "row_block" in L.lbf_last_error().decode()
+    # row blocks: a whole state array within 32-bit offsets (about 29.8 M nodes)
+    assert L.lbf_workspace_bytes(4096, 4096, 0, 4) > 0
+    assert L.lbf_workspace_bytes(8192, 4096, 0, 4) == 0
+    assert L.lbf_workspace_bytes(8192, 4096, 0, 0) > 0        # plane-major: 27 planes
 
 
 def _create_rc(L, case):

@@ -34,4 +34,9 @@ def test_tuning_table_is_well_formed():
     # untuned sizes: no padding, and the nearest 2D size for the tile
     assert autotune.lookup_pad(123, 45) == 0
     assert autotune.lookup_pad(7, 8, 9) == 0
+    # state layout (rows per block, pad): tuned, else 4-row blocks without pad
+    for size in ((2048, 2048), (4096, 2048)):
+        rb, pad = autotune.lookup_layout(*size)
+        assert rb in (0, 1, 2, 4, 8, 16, 32) and pad % 64 == 0
+    assert autotune.lookup_layout(123, 45) == (4, 0)
     assert autotune.lookup(2000, 2000) == autotune.lookup(2048, 2048)

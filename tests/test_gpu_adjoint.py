@@ -169,7 +169,7 @@ def test_checkpoint_interval_does_not_change_the_gradient(lbf_mod):
 def test_tape_call_order(lbf_mod):
     lbf = lbf_mod
     case = W.small_freezing_case()
-    sim = lbf.Sim(case)
+    sim = lbf.Sim(case, row_block=0)
     tape = lbf.Tape(sim, 5, 2)
     assert tape.segment == 2
     with pytest.raises(lbf.LbfError, match="LBF_ESTATE"):

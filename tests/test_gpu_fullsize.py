@@ -45,7 +45,8 @@ def compare(gpu, orc, tol, label):
 def run_pair(lbf, oracle_mod, case, steps):
     from paper_2510_18688_amd import autotune
     tile = autotune.lookup(case.nx, case.ny)
-    sim = lbf.Sim(case, tile=tile, plane_pad=autotune.lookup_pad(case.nx, case.ny))
+    rb, pad = autotune.lookup_layout(case.nx, case.ny)
+    sim = lbf.Sim(case, tile=tile, plane_pad=pad, row_block=rb)
     orc = oracle_mod.Oracle(case)
     sim.step(steps)
     orc.step(steps)

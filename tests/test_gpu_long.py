@@ -91,8 +91,9 @@ def test_benchmark_workload_at_stated_length(lbf_mod, make):
     import torch
     from paper_2510_18688_amd import autotune
     case = make()
-    sim = lbf_mod.Sim(case, tile=autotune.lookup(case.nx, case.ny),
-                      plane_pad=autotune.lookup_pad(case.nx, case.ny), check_every=1000)
+    rb, pad = autotune.lookup_layout(case.nx, case.ny)
+    sim = lbf_mod.Sim(case, tile=autotune.lookup(case.nx, case.ny), plane_pad=pad, row_block=rb,
+                      check_every=1000)
     done, hist = 0, []
     while done < case.steps:
         n = min(2500, case.steps - done)

@@ -83,8 +83,8 @@ def test_mrt_full_size(lbf_mod, O):
     from paper_2510_18688_amd import autotune
     case = W.curved_substrate()
     case.mat.mrt, case.mat.s_b, case.mat.s_q, case.mat.s_g = 1, 1.5, 1.2, 1.4
-    sim = lbf_mod.Sim(case, tile=autotune.lookup(case.nx, case.ny),
-                      plane_pad=autotune.lookup_pad(case.nx, case.ny))
+    rb, pad = autotune.lookup_layout(case.nx, case.ny)
+    sim = lbf_mod.Sim(case, tile=autotune.lookup(case.nx, case.ny), plane_pad=pad, row_block=rb)
     orc = O.Oracle(case)
     sim.step(20)
     orc.step(20)
