@@ -63,14 +63,23 @@ typedef struct lbf3_params {
                                   planes and one plane from the moments pass), which
                                   the fracture set-up needs over its 20 000 steps;
                                   1 the mass source mdot of eq1 */
-  int32_t reserved;
+  int32_t row_block;           /* memory layout of the state (a tuning knob; results
+                                  do not depend on it): 0 plane-major; 1, 2, 4, 8,
+                                  16, 32 or 64 rows of nx nodes (row z ny + y) per
+                                  block, each block holding its rows of every plane
+                                  of the f, g, h, lagged and static arrays, so the
+                                  planes one pass streams lie close together in HBM;
+                                  plane_pad then pads each block's planes.  Row
+                                  blocks cap a lattice at about 33 M nodes */
 } lbf3_params;
 
 typedef struct lbf3_sim lbf3_sim;
 
-/* Device bytes of one simulation's workspace with lbf3_params.plane_pad,
- * 0 for invalid sizes or pads and for lattices above the addressing limit. */
-size_t lbf3_workspace_bytes(int32_t nx, int32_t ny, int32_t nz, int32_t plane_pad);
+/* Device bytes of one simulation's workspace with lbf3_params.plane_pad and
+ * lbf3_params.row_block, 0 for invalid sizes, pads or row blocks and for
+ * lattices above the addressing limit of their layout. */
+size_t lbf3_workspace_bytes(int32_t nx, int32_t ny, int32_t nz, int32_t plane_pad,
+                            int32_t row_block);
 
 /* Create on HIP stream `stream` (NULL: default stream); workspace as in
  * lbf_create (caller-owned, 256-byte aligned, or NULL for a library

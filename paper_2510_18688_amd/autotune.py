@@ -96,7 +96,7 @@ def tune_pad(case, tile: Optional[Sequence[int]] = None, steps: int = 100, repea
     three = hasattr(case, "nz")
     times = {}
     for pad in candidates:
-        sim = (lbf.Sim3(case, plane_pad=pad) if three
+        sim = (lbf.Sim3(case, plane_pad=pad, row_block=0) if three
                else lbf.Sim(case, tile=tile, plane_pad=pad, row_block=0))
         sim.step(10)
         sim.set_timing(True)
@@ -133,6 +133,16 @@ def lookup_layout(nx: int, ny: int) -> Tuple[int, int]:
         rb, pad = v["layout"]
         return int(rb), int(pad)
     return 4, 0
+
+
+def lookup_layout3(nx: int, ny: int, nz: int) -> Tuple[int, int]:
+    """Tuned (row_block, plane_pad) of a D3Q19 lattice size; (32, 0) if that
+    size was not measured."""
+    v = _load().get(_key(nx, ny, nz))
+    if v and "layout" in v:
+        rb, pad = v["layout"]
+        return int(rb), int(pad)
+    return 32, 0
 
 
 def tune_layout(case, tile: Optional[Sequence[int]] = None, steps: int = 100, repeats: int = 3,

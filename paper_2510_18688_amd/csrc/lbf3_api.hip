@@ -31,15 +31,37 @@ constexpr int kRed3 = 6;   // sum g, sum h, sum f_s, liquid PCM, max |u|, non-fi
 
 struct Layout3 {
   size_t dist[2], lag[2], stat, mom, fields, red, redfinal, total;
-  size_t P;
-  int nblocks;
+  size_t P;       // plane stride inside a block
+  size_t GS;      // block stride (one block: unused)
+  size_t AS;      // floats of one of the f, g, h arrays
+  size_t PL;      // plane stride of the linear arrays
+  int nblk;       // row blocks
+  int nblocks;    // workgroups of a pass
 };
 
-Layout3 make_layout3(int nx, int ny, int nz, int pad) {
+bool valid_row_block3(int rb) {
+  return rb == 0 || rb == 1 || rb == 2 || rb == 4 || rb == 8 || rb == 16 || rb == 32 || rb == 64;
+}
+
+// Row blocks: rb rows of nx nodes per block, the block stride the power of
+// two at or above the 19 planes of the f, g and h arrays; rb = 0: one block
+// (plane-major, plane stride the node count rounded up to 64 plus the pad).
+Layout3 make_layout3(int nx, int ny, int nz, int pad, int rb) {
   Layout3 L{};
-  const size_t n = (size_t)nx * ny * nz;
-  L.P = up3(n, 64) + pad;
-  const size_t pb = L.P * sizeof(float);
+  const size_t n = (size_t)nx * ny * nz, rows = (size_t)ny * nz;
+  L.PL = up3(n, 64);
+  if (rb) {
+    L.P = up3((size_t)rb * nx, 64) + pad;
+    L.nblk = (int)((rows + rb - 1) / rb);
+    L.GS = 1;
+    while (L.GS < NQ * L.P) L.GS <<= 1;
+  } else {
+    L.P = up3(n, 64) + pad;
+    L.nblk = 1;
+    L.GS = NQ * L.P;
+  }
+  const size_t base = (size_t)(L.nblk - 1) * L.GS;
+  L.AS = base + NQ * L.P;
   L.nblocks = (int)((n + 255) / 256);
   size_t off = 0;
   auto take = [&](size_t b) {
@@ -47,13 +69,13 @@ Layout3 make_layout3(int nx, int ny, int nz, int pad) {
     off = up3(off + b, kAlign3);
     return o;
   };
-  L.dist[0] = take(NDIST * pb);
-  L.dist[1] = take(NDIST * pb);
-  L.lag[0] = take(NLAG * pb);
-  L.lag[1] = take(NLAG * pb);
-  L.stat = take(NSTAT * pb);
-  L.mom = take(5 * pb);   // 16-byte records, then the div u plane
-  L.fields = take(NFIELD * pb);
+  L.dist[0] = take(3 * L.AS * sizeof(float));
+  L.dist[1] = take(3 * L.AS * sizeof(float));
+  L.lag[0] = take((base + NLAG * L.P) * sizeof(float));
+  L.lag[1] = take((base + NLAG * L.P) * sizeof(float));
+  L.stat = take((base + NSTAT * L.P) * sizeof(float));
+  L.mom = take(5 * L.PL * sizeof(float));   // 16-byte records, then the div u plane
+  L.fields = take(NFIELD * L.PL * sizeof(float));
   L.red = take((size_t)L.nblocks * kRed3 * sizeof(double));
   L.redfinal = take(kRed3 * sizeof(double));
   L.total = off;
@@ -95,27 +117,29 @@ __global__ __launch_bounds__(256) void k3_lap_static(Geo3 G, float* stat, int N)
   if (k >= N) return;
   int x, y, z;
   coords(G, k, x, y, z);
+  const uint32_t s = sidx3(G, x, y, z);
   const float* phi0 = stat + ST_PHI0 * (size_t)G.P;
-  const float c = phi0[k];
+  const float c = phi0[s];
   float lap = 0.0f;
 #pragma unroll
   for (int i = 1; i < NQ; ++i) {
     const int xx = nb3(x + cx(i), G.n[0], G.per[0]), yy = nb3(y + cy(i), G.n[1], G.per[1]);
     const int zz = nb3(z + cz(i), G.n[2], G.per[2]);
-    lap += wgt(i) * (phi0[((size_t)zz * G.n[1] + yy) * G.n[0] + xx] - c);
+    lap += wgt(i) * (phi0[sidx3(G, xx, yy, zz)] - c);
   }
-  stat[ST_LAP0 * (size_t)G.P + k] = 6.0f * lap;
+  stat[ST_LAP0 * (size_t)G.P + s] = 6.0f * lap;
 }
 
-// Equilibria of the initial state in post-stream form (tmp: 57 planes);
-// `in` holds phi (plane 0) and T (plane 1).
+// Equilibria of the initial state in post-stream form (tmp: the f, g, h
+// arrays); `in` holds phi (plane 0) and T (plane 1), linear, PL apart.
 __global__ __launch_bounds__(256) void k3_init_eq(Geo3 G, Phys ph, const float* stat,
                                                   const float* in, float* tmp, int N) {
   const int k = blockIdx.x * 256 + threadIdx.x;
   if (k >= N) return;
   int x, y, z;
   coords(G, k, x, y, z);
-  const size_t P = G.P;
+  const size_t P = G.P, AS = G.AS;
+  const uint32_t s = sidx3(G, x, y, z);
   const float pc = in[k];
   float lap = 0.0f;
 #pragma unroll
@@ -125,22 +149,22 @@ __global__ __launch_bounds__(256) void k3_init_eq(Geo3 G, Phys ph, const float* 
     lap += wgt(i) * (in[((size_t)zz * G.n[1] + yy) * G.n[0] + xx] - pc);
   }
   lap *= 6.0f;
-  const float phi0 = stat[ST_PHI0 * P + k];
-  const float mu = lbf::chem_pot(ph, pc, lap, phi0, stat[ST_CTH * P + k], stat[ST_LAP0 * P + k],
+  const float phi0 = stat[ST_PHI0 * P + s];
+  const float mu = lbf::chem_pot(ph, pc, lap, phi0, stat[ST_CTH * P + s], stat[ST_LAP0 * P + s],
                                  0.0f, 0.0f);
   const float C = lbf::clampf(0.5f * (1.0f - phi0 + pc), 0.0f, 1.0f);
   const float Cp = lbf::clampf((C - ph.pcm_floor) * ph.inv_pcm_span, 0.0f, 1.0f);
   const float chi = lbf::clampf(Cp, 0.0f, 1.0f - phi0);
   const float Kliq = lbf::zeta(phi0, C, ph.rho_s, ph.rho_l, ph.rho_g) *
                      lbf::zeta(phi0, C, ph.cp_s, ph.cp_l, ph.cp_g);
-  const float Tk = in[P + k];
+  const float Tk = in[(size_t)G.PL + k];
   const float rhoH = Kliq * (Tk - ph.T_m) + Kliq * ph.T_m + chi * ph.rho_l * ph.latent;
   const float ET = ph.Eref * Tk;
 #pragma unroll
   for (int i = 0; i < NQ; ++i) {
-    tmp[i * P + k] = 0.0f;
-    tmp[(NQ + i) * P + k] = (i == 0 ? pc : 0.0f) + (wgt(i) - (i == 0 ? 1.0f : 0.0f)) * mu;
-    tmp[(2 * NQ + i) * P + k] = (i == 0) ? rhoH - ET + wgt(0) * ET : wgt(i) * ET;
+    tmp[i * P + s] = 0.0f;
+    tmp[AS + i * P + s] = (i == 0 ? pc : 0.0f) + (wgt(i) - (i == 0 ? 1.0f : 0.0f)) * mu;
+    tmp[2 * AS + i * P + s] = (i == 0) ? rhoH - ET + wgt(0) * ET : wgt(i) * ET;
   }
 }
 
@@ -152,12 +176,13 @@ __global__ __launch_bounds__(256) void k3_unstream(Geo3 G, Phys ph, const float*
   if (k >= N) return;
   int x, y, z;
   coords(G, k, x, y, z);
-  const size_t P = G.P;
-  dst[k] = tmp[k];
-  lag[LAG_GHI * P + k] = tmp[NQ * P + k];
-  lag[LAG_HHI * P + k] = tmp[2 * NQ * P + k];
-  dst[NQ * P + k] = 0.0f;
-  dst[2 * NQ * P + k] = 0.0f;
+  const size_t P = G.P, AS = G.AS;
+  const size_t s = sidx3(G, x, y, z);
+  dst[s] = tmp[s];
+  lag[LAG_GHI * P + s] = tmp[AS + s];
+  lag[LAG_HHI * P + s] = tmp[2 * AS + s];
+  dst[AS + s] = 0.0f;
+  dst[2 * AS + s] = 0.0f;
   for (int j = 1; j < NQ; ++j) {
     // destination of population j leaving the node; the face of its wall
     const int v[3] = {x + cx(j), y + cy(j), z + cz(j)};
@@ -171,14 +196,14 @@ __global__ __launch_bounds__(256) void k3_unstream(Geo3 G, Phys ph, const float*
       }
     }
     if (face < 0) {
-      const size_t dk = ((size_t)d[2] * G.n[1] + d[1]) * G.n[0] + d[0];
-      for (int b = 0; b < 3; ++b) dst[(b * NQ + j) * P + k] = tmp[(b * NQ + j) * P + dk];
+      const size_t dk = sidx3(G, d[0], d[1], d[2]);
+      for (int b = 0; b < 3; ++b) dst[b * AS + j * P + s] = tmp[b * AS + j * P + dk];
     } else {
       const int i = opp(j);   // the population the node pulls back
-      dst[j * P + k] = tmp[i * P + k];
-      dst[(NQ + j) * P + k] = tmp[(NQ + i) * P + k];
-      const float hb = tmp[(2 * NQ + i) * P + k];
-      dst[(2 * NQ + j) * P + k] =
+      dst[j * P + s] = tmp[i * P + s];
+      dst[AS + j * P + s] = tmp[AS + i * P + s];
+      const float hb = tmp[2 * AS + i * P + s];
+      dst[2 * AS + j * P + s] =
           ((G.tmask >> face) & 1) ? 2.0f * wgt(i) * ph.Eref * G.Tw[face] - hb : hb;
     }
   }
@@ -193,9 +218,10 @@ __global__ __launch_bounds__(256) void k3_moments(Geo3 G, Phys ph, BufArgs3 A, i
   const int k = ph.phi_src_flow ? node_in_strips(G, q) : q;
   int x, y, z;
   coords(G, k, x, y, z);
-  const Bufs3 B = make_bufs3(A, G.P);
+  const Bufs3 B = make_bufs3(A, G);
   Pull19 n;
   pull19(G, x, y, z, n);
+  const int s = (int)(n.k4 >> 2);   // storage index of the node
   float gv[NQ], hv[NQ];
   pull_gh3(G, ph, B, n, gv, hv);
   // the flow-divergence phase-field source: div u of the previous step, kept
@@ -203,11 +229,11 @@ __global__ __launch_bounds__(256) void k3_moments(Geo3 G, Phys ph, BufArgs3 A, i
   float dl = 0.0f;
   if (ph.phi_src_flow) {
     dl = div3(G, B, n);
-    lbf::stp(B.mom, MOM_DIVU, G.P, k, dl);
+    lbf::stp(B.mom, MOM_DIVU, G.PL, k, dl);
   }
   Mom m;
-  node_moments3(G, ph, B, (uint32_t)k, gv, hv, lbf::ldp(B.stat, ST_PHI0, G.P, k), m, dl);
-  st_rec(B.mom, (uint32_t)k * 16u, m.phi, m.fs, m.rho, lbf::ldp(B.lin, LAG_P, G.P, k));
+  node_moments3(G, ph, B, (uint32_t)s, gv, hv, lbf::ldp(B.stat, ST_PHI0, G.P, s), m, dl);
+  st_rec(B.mom, (uint32_t)k * 16u, m.phi, m.fs, m.rho, lbf::ldp(B.lin, LAG_P, G.P, s));
 }
 
 // Step pass (READOUT = false) or read-out of the fields with FP64 block sums
@@ -222,52 +248,53 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
   if (act) {
     int x, y, z;
     coords(G, k, x, y, z);
-    const Bufs3 B = make_bufs3(A, G.P);
-    const size_t P = G.P;
+    const Bufs3 B = make_bufs3(A, G);
+    const size_t PL = G.PL;
     Pull19 n;
     pull19(G, x, y, z, n);
+    const int s = (int)(n.k4 >> 2);   // storage index of the node
     float gv[NQ], hv[NQ], fv[NQ];
     pull_gh3(G, ph, B, n, gv, hv);
-    const float phi0 = lbf::ldp(B.stat, ST_PHI0, G.P, k);
-    const float dl = ph.phi_src_flow ? lbf::ldp(B.mom, MOM_DIVU, G.P, k) : 0.0f;
+    const float phi0 = lbf::ldp(B.stat, ST_PHI0, G.P, s);
+    const float dl = ph.phi_src_flow ? lbf::ldp(B.mom, MOM_DIVU, G.PL, k) : 0.0f;
     Mom m;
-    node_moments3(G, ph, B, (uint32_t)k, gv, hv, phi0, m, dl);
+    node_moments3(G, ph, B, (uint32_t)s, gv, hv, phi0, m, dl);
     Stencil3 S;
     stencils3(G, B, n, m.phi, m.fs, S);
     pull_f3(G, B, n, fv);
-    const float jprev[3] = {lbf::ldp(B.lin, LAG_JX, G.P, k), lbf::ldp(B.lin, LAG_JY, G.P, k),
-                            lbf::ldp(B.lin, LAG_JZ, G.P, k)};
-    const float ref_h = lbf::ldp(B.lin, LAG_HHI, G.P, k);
+    const float jprev[3] = {lbf::ldp(B.lin, LAG_JX, G.P, s), lbf::ldp(B.lin, LAG_JY, G.P, s),
+                            lbf::ldp(B.lin, LAG_JZ, G.P, s)};
+    const float ref_h = lbf::ldp(B.lin, LAG_HHI, G.P, s);
     Post3 o;
-    collide3(ph, m, S, phi0, lbf::ldp(B.stat, ST_CTH, G.P, k), lbf::ldp(B.stat, ST_LAP0, G.P, k),
+    collide3(ph, m, S, phi0, lbf::ldp(B.stat, ST_CTH, G.P, s), lbf::ldp(B.stat, ST_LAP0, G.P, s),
              jprev, ref_h, fv, gv, hv, o);
     if (!READOUT) {
 #pragma unroll
       for (int i = 0; i < NQ; ++i) {
-        lbf::stp(B.fout, i, G.P, k, fv[i]);
-        lbf::stp(B.gout, i, G.P, k, gv[i]);
-        lbf::stp(B.hout, i, G.P, k, hv[i]);
+        lbf::stp(B.fout, i, G.P, s, fv[i]);
+        lbf::stp(B.gout, i, G.P, s, gv[i]);
+        lbf::stp(B.hout, i, G.P, s, hv[i]);
       }
-      lbf::stp(B.lout, LAG_FS, G.P, k, m.fs);
-      lbf::stp(B.lout, LAG_Q, G.P, k, o.Q);
-      lbf::stp(B.lout, LAG_JX, G.P, k, o.j[0]);
-      lbf::stp(B.lout, LAG_JY, G.P, k, o.j[1]);
-      lbf::stp(B.lout, LAG_JZ, G.P, k, o.j[2]);
-      lbf::stp(B.lout, LAG_P, G.P, k, o.p);
-      lbf::stp(B.lout, LAG_GHI, G.P, k, o.ghi);
-      lbf::stp(B.lout, LAG_HHI, G.P, k, o.hhi);
+      lbf::stp(B.lout, LAG_FS, G.P, s, m.fs);
+      lbf::stp(B.lout, LAG_Q, G.P, s, o.Q);
+      lbf::stp(B.lout, LAG_JX, G.P, s, o.j[0]);
+      lbf::stp(B.lout, LAG_JY, G.P, s, o.j[1]);
+      lbf::stp(B.lout, LAG_JZ, G.P, s, o.j[2]);
+      lbf::stp(B.lout, LAG_P, G.P, s, o.p);
+      lbf::stp(B.lout, LAG_GHI, G.P, s, o.ghi);
+      lbf::stp(B.lout, LAG_HHI, G.P, s, o.hhi);
       if (ph.phi_src_flow) {
-        lbf::stp(B.lout, LAG_UX, G.P, k, o.u[0]);
-        lbf::stp(B.lout, LAG_UY, G.P, k, o.u[1]);
-        lbf::stp(B.lout, LAG_UZ, G.P, k, o.u[2]);
+        lbf::stp(B.lout, LAG_UX, G.P, s, o.u[0]);
+        lbf::stp(B.lout, LAG_UY, G.P, s, o.u[1]);
+        lbf::stp(B.lout, LAG_UZ, G.P, s, o.u[2]);
       }
     } else {
-      const float mu = lbf::chem_pot(ph, m.phi, S.lphi, phi0, lbf::ldp(B.stat, ST_CTH, G.P, k),
-                                     lbf::ldp(B.stat, ST_LAP0, G.P, k), m.fs, S.lfs);
+      const float mu = lbf::chem_pot(ph, m.phi, S.lphi, phi0, lbf::ldp(B.stat, ST_CTH, G.P, s),
+                                     lbf::ldp(B.stat, ST_LAP0, G.P, s), m.fs, S.lfs);
       const float out[NFIELD] = {m.phi, m.T, 1.0f - m.fs, m.fs, o.u[0], o.u[1], o.u[2], o.p,
                                  m.rhoH, mu, m.C, m.chi, m.rho, m.ref_g + m.sg};
 #pragma unroll
-      for (int f = 0; f < NFIELD; ++f) fields[f * P + k] = out[f];
+      for (int f = 0; f < NFIELD; ++f) fields[f * PL + k] = out[f];
       const float um = sqrtf(o.u[0] * o.u[0] + o.u[1] * o.u[1] + o.u[2] * o.u[2]);
       v[0] = (double)m.ref_g + (double)m.sg;
       v[1] = (double)ref_h + (double)m.sh;
@@ -319,6 +346,15 @@ __global__ void k3_reduce_final(const double* part, int nblocks, double* out) {
   }
 }
 
+// Every byte offset a kernel forms fits 32 bits: 19 planes of the
+// plane-major layout, or one whole f, g or h array of row blocks.
+bool fits3(int nx, int ny, int nz, int pad, int rb) {
+  const long long n = (long long)nx * ny * nz;
+  if (n > kMaxNodes3 || (long long)up3((size_t)n, 64) + pad > kMaxNodes3) return false;
+  if (!rb) return true;
+  return make_layout3(nx, ny, nz, pad, rb).AS * 4ull <= 0xFFFFFFFFull;
+}
+
 int validate3(const lbf3_params* p) {
   if (!p) return fail(LBF_EINVAL, "params is NULL");
   if (p->nx < 1 || p->ny < 1 || p->nz < 1)
@@ -326,9 +362,11 @@ int validate3(const lbf3_params* p) {
   if (p->plane_pad < 0 || p->plane_pad > lbfi::kMaxPlanePad || p->plane_pad % 64)
     return fail(LBF_EINVAL, "plane_pad %d (a multiple of 64 in [0, %d])", p->plane_pad,
                 lbfi::kMaxPlanePad);
-  if ((long long)up3((size_t)p->nx * p->ny * p->nz, 64) + p->plane_pad > kMaxNodes3)
-    return fail(LBF_EINVAL, "lattice of %lld nodes exceeds the %lld-node limit",
-                (long long)p->nx * p->ny * p->nz, kMaxNodes3);
+  if (!valid_row_block3(p->row_block))
+    return fail(LBF_EINVAL, "row_block %d (0, 1, 2, 4, 8, 16, 32 or 64)", p->row_block);
+  if (!fits3(p->nx, p->ny, p->nz, p->plane_pad, p->row_block))
+    return fail(LBF_EINVAL, "lattice of %lld nodes exceeds the 32-bit offset limit of its layout "
+                "(row_block %d)", (long long)p->nx * p->ny * p->nz, p->row_block);
   const double pos[] = {p->rho_l, p->rho_g, p->rho_s, p->mu_l, p->mu_g, p->mu_s, p->lam_l,
                         p->lam_g, p->lam_s, p->cp_l, p->cp_g, p->cp_s, p->eps, p->mobility,
                         p->rho_ref};
@@ -421,6 +459,48 @@ BufArgs3 args3(lbf3_sim* s, int c) {
   return A;
 }
 
+// Copy one plane between a plain array of nx ny nz values (`flat`) and the
+// plane that starts at `plane` in a state or static array, on the
+// simulation's stream; `to_plane` gives the direction.
+int plane_copy3(lbf3_sim* s, float* plane, float* flat, bool to_plane, hipMemcpyKind kind) {
+  const size_t n = (size_t)N3(s);
+  if (s->L.nblk == 1) {
+    HIP_TRY(hipMemcpyAsync(to_plane ? plane : flat, to_plane ? flat : plane, n * sizeof(float),
+                           kind, s->stream));
+    return LBF_OK;
+  }
+  const size_t nx = s->G.n[0], rb = (size_t)s->G.rmask + 1, rows = n / nx;
+  const size_t full = rows / rb, rem = rows - full * rb;
+  const size_t w = rb * nx * sizeof(float), pitch = s->L.GS * sizeof(float);
+  if (full)
+    HIP_TRY(hipMemcpy2DAsync(to_plane ? plane : flat, to_plane ? pitch : w,
+                             to_plane ? flat : plane, to_plane ? w : pitch, w, full, kind,
+                             s->stream));
+  if (rem) {
+    float* pb = plane + full * s->L.GS;
+    float* fb = flat + full * rb * nx;
+    HIP_TRY(hipMemcpyAsync(to_plane ? pb : fb, to_plane ? fb : pb, rem * nx * sizeof(float), kind,
+                           s->stream));
+  }
+  return LBF_OK;
+}
+
+// Start of plane j (0 .. 56 distributions, then 57 .. 67 lagged) of state
+// buffer c.
+float* state_plane3(lbf3_sim* s, int c, int j) {
+  if (j < NDIST)
+    return fp3(s, s->L.dist[c]) + (size_t)(j / NQ) * s->L.AS + (size_t)(j % NQ) * s->L.P;
+  return fp3(s, s->L.lag[c]) + (size_t)(j - NDIST) * s->L.P;
+}
+
+// Zero the lagged planes of state buffer c (every block).
+int zero_lags3(lbf3_sim* s, int c) {
+  const size_t w = NLAG * s->L.P * sizeof(float);
+  HIP_TRY(hipMemset2DAsync(fp3(s, s->L.lag[c]), s->L.nblk > 1 ? s->L.GS * sizeof(float) : w, 0, w,
+                           (size_t)s->L.nblk, s->stream));
+  return LBF_OK;
+}
+
 int copy3(lbf3_sim* s, void* dst, const void* src, size_t bytes, int on_device) {
   if (hipMemcpyAsync(dst, src, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
                      s->stream) != hipSuccess)
@@ -449,12 +529,12 @@ int launch_pair(lbf3_sim* s, bool readout) {
 
 extern "C" {
 
-size_t lbf3_workspace_bytes(int32_t nx, int32_t ny, int32_t nz, int32_t plane_pad) {
+size_t lbf3_workspace_bytes(int32_t nx, int32_t ny, int32_t nz, int32_t plane_pad,
+                            int32_t row_block) {
   if (nx < 1 || ny < 1 || nz < 1) return 0;
   if (plane_pad < 0 || plane_pad > lbfi::kMaxPlanePad || plane_pad % 64) return 0;
-  if ((long long)nx * ny * nz > kMaxNodes3) return 0;
-  if ((long long)up3((size_t)nx * ny * nz, 64) + plane_pad > kMaxNodes3) return 0;
-  return make_layout3(nx, ny, nz, plane_pad).total;
+  if (!valid_row_block3(row_block) || !fits3(nx, ny, nz, plane_pad, row_block)) return 0;
+  return make_layout3(nx, ny, nz, plane_pad, row_block).total;
 }
 
 int lbf3_create(const lbf3_params* params, void* stream, void* workspace, size_t workspace_bytes,
@@ -475,8 +555,22 @@ int lbf3_create(const lbf3_params* params, void* stream, void* workspace, size_t
     s->G.Tw[f] = (float)params->wall_T[f];
   }
   fill_phys3(params, s->ph);
-  s->L = make_layout3(params->nx, params->ny, params->nz, params->plane_pad);
+  const int rb = params->row_block;
+  s->L = make_layout3(params->nx, params->ny, params->nz, params->plane_pad, rb);
   s->G.P = (int)s->L.P;
+  s->G.rbs = 31;
+  s->G.gss = 31;
+  if (rb) {
+    for (s->G.rbs = 0; (1 << s->G.rbs) < rb; ++s->G.rbs) {
+    }
+    for (s->G.gss = 0; ((size_t)1 << s->G.gss) < s->L.GS; ++s->G.gss) {
+    }
+  }
+  s->G.rmask = rb ? rb - 1 : 0x7fffffff;
+  s->G.nblk = s->L.nblk;
+  s->G.RBN = rb * params->nx;
+  s->G.AS = (int)s->L.AS;
+  s->G.PL = (int)s->L.PL;
   s->stream = (hipStream_t)stream;
   if (workspace) {
     if (workspace_bytes < s->L.total || (uintptr_t)workspace % kAlign3) {
@@ -514,12 +608,13 @@ void lbf3_destroy(lbf3_sim* s) {
 
 int lbf3_set_geometry(lbf3_sim* s, const float* phi0, const float* cth, int32_t on_device) {
   if (!s || !phi0 || !cth) return fail(LBF_EINVAL, "NULL argument");
-  const size_t n = (size_t)N3(s);
   float* stat = fp3(s, s->L.stat);
-  int rc = copy3(s, stat + ST_PHI0 * s->L.P, phi0, n * sizeof(float), on_device);
+  const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  int rc = plane_copy3(s, stat + ST_PHI0 * s->L.P, const_cast<float*>(phi0), true, kind);
   if (rc) return rc;
-  rc = copy3(s, stat + ST_CTH * s->L.P, cth, n * sizeof(float), on_device);
+  rc = plane_copy3(s, stat + ST_CTH * s->L.P, const_cast<float*>(cth), true, kind);
   if (rc) return rc;
+  if (!on_device) HIP_TRY(hipStreamSynchronize(s->stream));
   hipLaunchKernelGGL(k3_lap_static, dim3(s->L.nblocks), dim3(256), 0, s->stream, s->G, stat,
                      N3(s));
   HIP_TRY(hipGetLastError());
@@ -535,14 +630,19 @@ int lbf3_init_fields(lbf3_sim* s, const float* phi, const float* T, int32_t on_d
   float* stage = fp3(s, s->L.fields);
   int rc = copy3(s, stage, phi, n * sizeof(float), on_device);
   if (rc) return rc;
-  rc = copy3(s, stage + s->L.P, T, n * sizeof(float), on_device);
+  rc = copy3(s, stage + s->L.PL, T, n * sizeof(float), on_device);
   if (rc) return rc;
   s->cur = 0;
   float* tmp = fp3(s, s->L.dist[1]);
   hipLaunchKernelGGL(k3_init_eq, dim3(s->L.nblocks), dim3(256), 0, s->stream, s->G, s->ph,
                      (const float*)fp3(s, s->L.stat), (const float*)stage, tmp, N3(s));
   HIP_TRY(hipGetLastError());
-  HIP_TRY(hipMemsetAsync(fp3(s, s->L.lag[0]), 0, NLAG * s->L.P * sizeof(float), s->stream));
+  // both buffers' lagged planes start at zero, so a saved state does not
+  // depend on what the workspace held
+  for (int c = 0; c < 2; ++c) {
+    rc = zero_lags3(s, c);
+    if (rc) return rc;
+  }
   hipLaunchKernelGGL(k3_unstream, dim3(s->L.nblocks), dim3(256), 0, s->stream, s->G, s->ph,
                      (const float*)tmp, fp3(s, s->L.dist[0]), fp3(s, s->L.lag[0]), N3(s));
   HIP_TRY(hipGetLastError());
@@ -580,7 +680,7 @@ int lbf3_read_fields(lbf3_sim* s, float* dst, int32_t dst_on_device) {
   if (rc) return rc;
   const size_t n = (size_t)N3(s);
   for (int f = 0; f < NFIELD; ++f)
-    HIP_TRY(hipMemcpyAsync(dst + f * n, fp3(s, s->L.fields) + f * s->L.P, n * sizeof(float),
+    HIP_TRY(hipMemcpyAsync(dst + f * n, fp3(s, s->L.fields) + f * s->L.PL, n * sizeof(float),
                            dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
                            s->stream));
   HIP_TRY(hipStreamSynchronize(s->stream));
@@ -623,12 +723,13 @@ int lbf3_save_state(lbf3_sim* s, void* dst, size_t cap) {
   const size_t need = lbf3_state_bytes(s);
   if (cap < need) return fail(LBF_ENOMEM, "state needs %zu bytes", need);
   char* d = (char*)dst;
-  const size_t nb = (size_t)N3(s) * sizeof(float), pb = s->L.P * sizeof(float);
+  const size_t n = (size_t)N3(s), nb = n * sizeof(float);
   const size_t db = NDIST * nb, lb = NLAG * nb;
-  HIP_TRY(hipMemcpy2DAsync(d, nb, s->ws + s->L.dist[s->cur], pb, nb, NDIST,
-                           hipMemcpyDeviceToDevice, s->stream));
-  HIP_TRY(hipMemcpy2DAsync(d + db, nb, s->ws + s->L.lag[s->cur], pb, nb, NLAG,
-                           hipMemcpyDeviceToDevice, s->stream));
+  for (int j = 0; j < NDIST + NLAG; ++j) {
+    int rc = plane_copy3(s, state_plane3(s, s->cur, j), (float*)d + j * n, false,
+                         hipMemcpyDeviceToDevice);
+    if (rc) return rc;
+  }
   long long hdr[8] = {kState3Magic, s->step, s->G.n[0], s->G.n[1], s->G.n[2], 0, 0, 0};
   HIP_TRY(hipMemcpyAsync(d + db + lb, hdr, sizeof hdr, hipMemcpyHostToDevice, s->stream));
   HIP_TRY(hipStreamSynchronize(s->stream));
@@ -641,7 +742,7 @@ int lbf3_load_state(lbf3_sim* s, const void* src, size_t bytes) {
   if (bytes < need) return fail(LBF_EINVAL, "state of %zu bytes, %zu needed", bytes, need);
   if (!s->have_geo) return fail(LBF_ESTATE, "lbf3_set_geometry must precede lbf3_load_state");
   const char* d = (const char*)src;
-  const size_t nb = (size_t)N3(s) * sizeof(float), pb = s->L.P * sizeof(float);
+  const size_t n = (size_t)N3(s), nb = n * sizeof(float);
   const size_t db = NDIST * nb, lb = NLAG * nb;
   long long hdr[8];
   HIP_TRY(hipMemcpyAsync(hdr, d + db + lb, sizeof hdr, hipMemcpyDeviceToHost, s->stream));
@@ -649,10 +750,11 @@ int lbf3_load_state(lbf3_sim* s, const void* src, size_t bytes) {
   if (hdr[0] != kState3Magic || hdr[2] != s->G.n[0] || hdr[3] != s->G.n[1] ||
       hdr[4] != s->G.n[2])
     return fail(LBF_EINVAL, "state buffer does not match this lattice");
-  HIP_TRY(hipMemcpy2DAsync(s->ws + s->L.dist[s->cur], pb, d, nb, nb, NDIST,
-                           hipMemcpyDeviceToDevice, s->stream));
-  HIP_TRY(hipMemcpy2DAsync(s->ws + s->L.lag[s->cur], pb, d + db, nb, nb, NLAG,
-                           hipMemcpyDeviceToDevice, s->stream));
+  for (int j = 0; j < NDIST + NLAG; ++j) {
+    int rc = plane_copy3(s, state_plane3(s, s->cur, j), (float*)d + j * n, true,
+                         hipMemcpyDeviceToDevice);
+    if (rc) return rc;
+  }
   HIP_TRY(hipStreamSynchronize(s->stream));
   s->step = hdr[1];
   s->have_init = true;

@@ -1,7 +1,13 @@
 // Device-side building blocks of the three-dimensional (D3Q19) coupled step.
 //
-// Layout in HBM (structure of arrays, FP32, plane stride P floats, node
-// (x, y, z) at element (z ny + y) nx + x):
+// Layout in HBM (structure of arrays, FP32).  Rows of nx nodes are numbered
+// z ny + y; the state arrays (f, g, h, lagged, static) group them in blocks
+// of rb rows holding every plane of the array, each plane's rows back to
+// back (plane stride P floats inside a block, block stride GS, a power of
+// two), so node (x, y, z) has storage index (row >> log2 rb) GS +
+// (row mod rb) nx + x in all of them; rb = ny nz (one block) is plane-major.
+// The moments records and the read-out planes are indexed by the linear node
+// id (z ny + y) nx + x, plane stride PL.
 //   distributions 57 planes: f_0..f_18, g_0..g_18, h_0..h_18, post-collision,
 //                 stored at the node that wrote them (pull scheme); the rest
 //                 populations g_0, h_0 hold the low parts of float-float
@@ -58,9 +64,26 @@ struct Geo3 {
   int per[3];        // periodic flags
   int tmask;         // bit f: face f is Dirichlet (0 x-low .. 5 z-high)
   int strip;         // rows per strip of the step pass's node order (>= ny: x-fastest)
-  int P;             // plane stride (floats)
+  int P;             // plane stride inside a block (floats)
+  int rbs, rmask;    // log2 and rb - 1 of the rows per block (31, 0x7fffffff: one block)
+  int gss;           // log2 of the block stride GS (31: one block)
+  int nblk;          // blocks
+  int RBN;           // nodes per block (rb nx)
+  int AS;            // floats from one state array to the next (f, g, h)
+  int PL;            // plane stride of the linear arrays (records, read-out)
   float Tw[6];       // face temperatures
 };
+
+// Storage index of node (x, y, z) in the state and static arrays.
+__host__ __device__ __forceinline__ uint32_t sidx3(const Geo3& G, int x, int y, int z) {
+  const int row = z * G.n[1] + y;
+  return ((uint32_t)(row >> G.rbs) << G.gss) + (uint32_t)(row & G.rmask) * G.n[0] + x;
+}
+
+// Linear node id of a storage index.
+__host__ __device__ __forceinline__ uint32_t lin_of(const Geo3& G, uint32_t s) {
+  return (s >> G.gss) * (uint32_t)G.RBN + (s & ((1u << G.gss) - 1u));
+}
 
 struct Bufs3 {
   Rsrc fin, gin, hin, fout, gout, hout, lin, lout, stat, mom;
@@ -77,19 +100,26 @@ struct BufArgs3 {
                      // written by the moments pass
 };
 
-__device__ __forceinline__ Bufs3 make_bufs3(const BufArgs3& a, int P) {
-  const uint32_t pb = (uint32_t)P * 4u;
+// Bytes from a state array's base to its end when its last block holds
+// `planes` planes.
+__device__ __forceinline__ uint32_t extent3(const Geo3& G, int planes) {
+  return (uint32_t)((((size_t)(G.nblk - 1) << G.gss) + (size_t)planes * G.P) * 4u);
+}
+
+__device__ __forceinline__ Bufs3 make_bufs3(const BufArgs3& a, const Geo3& G) {
+  const size_t AS = (size_t)G.AS;
+  const uint32_t e = extent3(G, NQ);
   Bufs3 B;
-  B.fin = lbf::make_rsrc(a.din, NQ * pb);
-  B.gin = lbf::make_rsrc(a.din + NQ * (size_t)P, NQ * pb);
-  B.hin = lbf::make_rsrc(a.din + 2 * NQ * (size_t)P, NQ * pb);
-  B.fout = lbf::make_rsrc(a.dout, a.dout ? NQ * pb : 0u);
-  B.gout = lbf::make_rsrc(a.dout ? a.dout + NQ * (size_t)P : nullptr, a.dout ? NQ * pb : 0u);
-  B.hout = lbf::make_rsrc(a.dout ? a.dout + 2 * NQ * (size_t)P : nullptr, a.dout ? NQ * pb : 0u);
-  B.lin = lbf::make_rsrc(a.lin, NLAG * pb);
-  B.lout = lbf::make_rsrc(a.lout, a.lout ? NLAG * pb : 0u);
-  B.stat = lbf::make_rsrc(a.stat, NSTAT * pb);
-  B.mom = lbf::make_rsrc(a.mom, 5 * pb);
+  B.fin = lbf::make_rsrc(a.din, e);
+  B.gin = lbf::make_rsrc(a.din + AS, e);
+  B.hin = lbf::make_rsrc(a.din + 2 * AS, e);
+  B.fout = lbf::make_rsrc(a.dout, a.dout ? e : 0u);
+  B.gout = lbf::make_rsrc(a.dout ? a.dout + AS : nullptr, a.dout ? e : 0u);
+  B.hout = lbf::make_rsrc(a.dout ? a.dout + 2 * AS : nullptr, a.dout ? e : 0u);
+  B.lin = lbf::make_rsrc(a.lin, extent3(G, NLAG));
+  B.lout = lbf::make_rsrc(a.lout, a.lout ? extent3(G, NLAG) : 0u);
+  B.stat = lbf::make_rsrc(a.stat, extent3(G, NSTAT));
+  B.mom = lbf::make_rsrc(a.mom, 5u * (uint32_t)G.PL * 4u);
   return B;
 }
 
@@ -130,7 +160,7 @@ __device__ __forceinline__ int src_axis(int v, int c, int n, int periodic, bool&
 }
 
 __device__ __forceinline__ void pull19(const Geo3& G, int x, int y, int z, Pull19& p) {
-  const uint32_t k = ((uint32_t)z * G.n[1] + y) * G.n[0] + x;
+  const uint32_t k = sidx3(G, x, y, z);
   p.k4 = k * 4u;
   p.wmask = 0u;
 #pragma unroll
@@ -140,7 +170,7 @@ __device__ __forceinline__ void pull19(const Geo3& G, int x, int y, int z, Pull1
     const int sy = src_axis(y, cy(i), G.n[1], G.per[1], oy);
     const int sz = src_axis(z, cz(i), G.n[2], G.per[2], oz);
     const bool w = ox || oy || oz;
-    p.off[i] = w ? p.k4 : (((uint32_t)sz * G.n[1] + sy) * G.n[0] + sx) * 4u;
+    p.off[i] = w ? p.k4 : sidx3(G, sx, sy, sz) * 4u;
     p.wmask |= (uint32_t)w << i;
   }
   p.x = x;
@@ -238,7 +268,7 @@ __device__ __forceinline__ float div3(const Geo3& G, const Bufs3& B, const Pull1
       const int xx = nb3(n.x + cx(i), G.n[0], G.per[0]);
       const int yy = nb3(n.y + cy(i), G.n[1], G.per[1]);
       const int zz = nb3(n.z + cz(i), G.n[2], G.per[2]);
-      o = (((uint32_t)zz * G.n[1] + yy) * G.n[0] + xx) * 4u;
+      o = sidx3(G, xx, yy, zz) * 4u;
     }
     float c = 0.0f;
     if (cx(i)) c = c + (float)cx(i) * lbf::ldo(B.lin, o, LAG_UX, G.P);
@@ -287,15 +317,16 @@ __device__ __forceinline__ void stencils3(const Geo3& G, const Bufs3& B, const P
   float gph[3] = {0, 0, 0}, gr[3] = {0, 0, 0}, gp[3] = {0, 0, 0}, lphi = 0, lfs = 0;
 #pragma unroll
   for (int i = 1; i < NQ; ++i) {
-    uint32_t o = n.off[opp(i)];
+    // linear id of the neighbour (the records are linear)
+    uint32_t kn = lin_of(G, n.off[opp(i)] >> 2);
     if ((n.wmask >> opp(i)) & 1u) {
       const int xx = nb3(n.x + cx(i), G.n[0], G.per[0]);
       const int yy = nb3(n.y + cy(i), G.n[1], G.per[1]);
       const int zz = nb3(n.z + cz(i), G.n[2], G.per[2]);
-      o = (((uint32_t)zz * G.n[1] + yy) * G.n[0] + xx) * 4u;
+      kn = ((uint32_t)zz * G.n[1] + yy) * G.n[0] + xx;
     }
     // one 16-byte record per neighbour: phi, f_s, rho, p_prev
-    const MomRec r = ld_rec(B.mom, o * 4u);
+    const MomRec r = ld_rec(B.mom, kn * 16u);
     const float vphi = r.v[0], vfs = r.v[1], vrho = r.v[2], vp = r.v[3];
     const float w = wgt(i);
     const float c[3] = {(float)cx(i), (float)cy(i), (float)cz(i)};

@@ -557,7 +557,7 @@ class Params3(C.Structure):
             "cp_l", "cp_g", "cp_s", "latent", "T_m", "sigma", "eps", "mobility", "cos_psi",
             "rho_ref", "T_substrate", "pcm_floor")] + [
         ("wall_T", C.c_double * 6), ("grav", C.c_double * 3), ("u_solid", C.c_double * 3),
-        ("phi_src_mdot", C.c_int32), ("reserved", C.c_int32)]
+        ("phi_src_mdot", C.c_int32), ("row_block", C.c_int32)]
 
 
 def _declare3(L):
@@ -565,7 +565,7 @@ def _declare3(L):
         return
     vp, i32 = C.c_void_p, C.c_int32
     L.lbf3_workspace_bytes.restype = C.c_size_t
-    L.lbf3_workspace_bytes.argtypes = [i32, i32, i32, i32]
+    L.lbf3_workspace_bytes.argtypes = [i32, i32, i32, i32, i32]
     L.lbf3_create.argtypes = [C.POINTER(Params3), vp, vp, C.c_size_t, C.POINTER(vp)]
     L.lbf3_set_geometry.argtypes = [vp, vp, vp, i32]
     L.lbf3_init_fields.argtypes = [vp, vp, vp, i32]
@@ -609,9 +609,12 @@ def make_params3(case) -> Params3:
 
 class Sim3:
     """One D3Q19 lattice on the current HIP device (workspace: a torch tensor);
-    `plane_pad` as for `Sim` (`autotune.lookup_pad(nx, ny, nz)`)."""
+    `row_block` the state's memory layout (0 plane-major; 1 .. 64 rows of nx
+    nodes per block of all planes, lbf3_params.row_block) and `plane_pad` its
+    padding, as for `Sim` (`autotune.lookup_layout3(nx, ny, nz)`)."""
 
-    def __init__(self, case, device: str = "cuda", stream=None, plane_pad: int = 0):
+    def __init__(self, case, device: str = "cuda", stream=None, plane_pad: int = 0,
+                 row_block: int = 32):
         torch = _torch()
         L = load()
         _declare3(L)
@@ -619,11 +622,14 @@ class Sim3:
         self.shape = (case.nz, case.ny, case.nx)
         self.params = make_params3(case)
         self.params.plane_pad = int(plane_pad)
+        self.params.row_block = int(row_block)
         self.device = torch.device(device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
-        nbytes = L.lbf3_workspace_bytes(case.nx, case.ny, case.nz, self.params.plane_pad)
+        nbytes = L.lbf3_workspace_bytes(case.nx, case.ny, case.nz, self.params.plane_pad,
+                                        self.params.row_block)
         if nbytes == 0:
-            raise LbfError(-1, f"bad lattice size {self.shape} or plane_pad {plane_pad}")
+            raise LbfError(-1, f"bad lattice size {self.shape}, plane_pad {plane_pad} or "
+                               f"row_block {row_block}")
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         h = C.c_void_p()
         check(L.lbf3_create(C.byref(self.params), C.c_void_p(self.stream.cuda_stream),

@@ -91,7 +91,9 @@ int main() {
     EXPECT(lbf_ch_smooth_noalloc(nullptr, img, out, 1, nullptr) == LBF_EINVAL);
   }
   // 3D refusals
-  EXPECT(lbf3_workspace_bytes(0, 1, 1, 0) == 0);
+  EXPECT(lbf3_workspace_bytes(0, 1, 1, 0, 0) == 0);
+  EXPECT(lbf3_workspace_bytes(8, 8, 8, 0, 16) > 0);
+  EXPECT(lbf3_workspace_bytes(8, 8, 8, 0, 5) == 0);
   // error text is per thread
   std::thread t([] { lbf_step(nullptr, -1); });
   t.join();

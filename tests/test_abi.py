@@ -176,19 +176,29 @@ def test_null_arguments(L):
     L.lbf3_destroy(None)
 
 
-def test_workspace3_bytes_and_limits(L):
+@pytest.mark.parametrize("rb", [0, 1, 4, 16, 64])
+def test_workspace3_bytes_and_limits(L, rb):
     lbf._declare3(L)
-    assert L.lbf3_workspace_bytes(0, 4, 4, 0) == 0
-    assert L.lbf3_workspace_bytes(4, 4, -1, 0) == 0
+    assert L.lbf3_workspace_bytes(0, 4, 4, 0, rb) == 0
+    assert L.lbf3_workspace_bytes(4, 4, -1, 0, rb) == 0
     for bad in (-64, 32, 65536 + 64):
-        assert L.lbf3_workspace_bytes(4, 4, 4, bad) == 0
-    assert L.lbf3_workspace_bytes(16, 16, 16, 64) > L.lbf3_workspace_bytes(16, 16, 16, 0)
-    a, b = L.lbf3_workspace_bytes(16, 16, 16, 0), L.lbf3_workspace_bytes(32, 32, 32, 0)
+        assert L.lbf3_workspace_bytes(4, 4, 4, bad, rb) == 0
+    assert L.lbf3_workspace_bytes(16, 16, 16, 64, rb) > L.lbf3_workspace_bytes(16, 16, 16, 0, rb)
+    a, b = L.lbf3_workspace_bytes(16, 16, 16, 0, rb), L.lbf3_workspace_bytes(32, 32, 32, 0, rb)
     assert 0 < a < b
-    assert L.lbf3_workspace_bytes(1024, 1024, 1024, 0) == 0      # above the addressing limit
-    kmax = (0xFFFFFFFF // (4 * 19)) // 64 * 64             # nodes addressable per block
-    assert L.lbf3_workspace_bytes(kmax - 64, 1, 1, 64) > 0
-    assert L.lbf3_workspace_bytes(kmax - 64, 1, 1, 128) == 0  # the pad counts against it
+    assert L.lbf3_workspace_bytes(1024, 1024, 1024, 0, rb) == 0      # above the addressing limit
+    assert L.lbf3_workspace_bytes(256, 256, 256, 0, rb) > 0           # the benchmark box
+    if rb == 0:
+        kmax = (0xFFFFFFFF // (4 * 19)) // 64 * 64             # nodes addressable per block
+        assert L.lbf3_workspace_bytes(kmax - 64, 1, 1, 64, 0) > 0
+        assert L.lbf3_workspace_bytes(kmax - 64, 1, 1, 128, 0) == 0  # the pad counts against it
+    else:
+        # row blocks: one f, g or h array within 32-bit offsets (its block
+        # stride a power of two: 260 x 400 x 400 fits plane-major, not here)
+        assert L.lbf3_workspace_bytes(260, 400, 400, 0, rb) == 0
+        assert L.lbf3_workspace_bytes(260, 400, 400, 0, 0) > 0
+    for bad in (-1, 3, 128):
+        assert L.lbf3_workspace_bytes(16, 16, 16, 0, bad) == 0
 
 
 @pytest.mark.parametrize("mutate, needle", [

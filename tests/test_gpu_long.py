@@ -164,7 +164,8 @@ def test_d3q19_fracture_at_stated_length(lbf_mod):
     import torch
     from paper_2510_18688_amd import autotune, workloads3 as W3
     case = W3.fracture()
-    sim = lbf_mod.Sim3(case, plane_pad=autotune.lookup_pad(case.nx, case.ny, case.nz))
+    rb, pad = autotune.lookup_layout3(case.nx, case.ny, case.nz)
+    sim = lbf_mod.Sim3(case, plane_pad=pad, row_block=rb)
     done, hist = 0, []
     while done < case.steps:
         sim.step(2500)
@@ -183,7 +184,8 @@ def test_d3q19_cube256_against_oracle(lbf_mod):
     from oracle import oracle3 as O3
     from paper_2510_18688_amd import autotune, workloads3 as W3
     case = W3.sphere_drop(256, 64.0)
-    sim = lbf_mod.Sim3(case, plane_pad=autotune.lookup_pad(case.nx, case.ny, case.nz))
+    rb, pad = autotune.lookup_layout3(case.nx, case.ny, case.nz)
+    sim = lbf_mod.Sim3(case, plane_pad=pad, row_block=rb)
     orc = O3.Oracle3(case)
     sim.step(5)
     orc.step(5)

@@ -111,7 +111,8 @@ def test_fracture_full_size(lbf_mod, O3):
     padding) after 5 steps, and the freezing fields after 300."""
     from paper_2510_18688_amd import autotune
     case = W3.fracture()
-    sim = lbf_mod.Sim3(case, plane_pad=autotune.lookup_pad(case.nx, case.ny, case.nz))
+    rb, pad = autotune.lookup_layout3(case.nx, case.ny, case.nz)
+    sim = lbf_mod.Sim3(case, plane_pad=pad, row_block=rb)
     orc = O3.Oracle3(case)
     sim.step(5)
     orc.step(5)
