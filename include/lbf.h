@@ -271,7 +271,8 @@ int lbf_get_tile(const lbf_sim* sim, int32_t* tile_x, int32_t* tile_y);
 /* Bytes of the checkpointable dynamic state and copy of it to / from `buf`
  * (device memory).  The buffer holds each plane's nx * ny values back to
  * back, so a state loads into any simulation of the same lattice size
- * whatever its plane_pad.  A loaded state continues bit-identically. */
+ * whatever its plane_pad and row_block.  A loaded state continues
+ * bit-identically. */
 size_t lbf_state_bytes(const lbf_sim* sim);
 int lbf_save_state(lbf_sim* sim, void* dst_device, size_t cap);
 int lbf_load_state(lbf_sim* sim, const void* src_device, size_t bytes);
@@ -357,7 +358,7 @@ typedef struct lbf_tape lbf_tape;
  * 34 planes, two buffers of `segment` recomputed states and their moments
  * (one segment is recomputed on a second stream while the other is
  * reversed), and the adjoint work planes, all with the simulation's plane
- * stride (its plane_pad).  segment <= 0 selects
+ * stride (its plane_pad; the tape needs row_block 0).  segment <= 0 selects
  * ceil(sqrt(nsteps)). */
 size_t lbf_tape_bytes(int32_t nx, int32_t ny, int32_t plane_pad, int32_t nsteps,
                       int32_t segment);

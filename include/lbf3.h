@@ -110,7 +110,7 @@ int lbf3_reduce(lbf3_sim* sim, double* out);
  * step count) and its copy to / from `buf` (device memory, at least
  * lbf3_state_bytes).  The buffer holds each plane's nodes back to back, so a
  * state loads into any simulation of the same lattice size whatever its
- * plane_pad.  Loading needs the geometry set and a state of the same lattice
+ * plane_pad and row_block.  Loading needs the geometry set and a state of the same lattice
  * size (LBF_EINVAL otherwise); a loaded state continues bit-identically.
  * Synchronises the simulation's stream. */
 size_t lbf3_state_bytes(const lbf3_sim* sim);
