@@ -126,13 +126,15 @@ LAYOUT_CANDIDATES: Tuple[Tuple[int, int], ...] = tuple(
 
 
 def lookup_layout(nx: int, ny: int) -> Tuple[int, int]:
-    """Tuned (row_block, plane_pad) of a 2D lattice size; (4, 0) if that size
-    was not measured."""
+    """Tuned (row_block, plane_pad) of a 2D lattice size; for a size not
+    measured, rows of every plane in blocks of one row up to 512 columns
+    (the batch of 64 lattices 64 .. 512 wide: 0.321 ms per step against 0.351
+    in 4-row blocks) and of four rows above (2048^2), without pad."""
     v = _load().get(_key(nx, ny))
     if v and "layout" in v:
         rb, pad = v["layout"]
         return int(rb), int(pad)
-    return 4, 0
+    return (1 if nx <= 512 else 4), 0
 
 
 def lookup_layout3(nx: int, ny: int, nz: int) -> Tuple[int, int]:

@@ -172,20 +172,24 @@ class Sim:
     block of all planes, lbf_params.row_block) and `plane_pad` the padding
     between its planes in floats (a multiple of 64); they change speed only,
     and `autotune.lookup` / `autotune.lookup_layout` return the tuned values
-    for a lattice size.  The adjoint (`Tape`) needs row_block 0.
+    for a lattice size (row_block None takes the latter's).  The adjoint
+    (`Tape`) needs row_block 0.
     `check_every`: `step` raises LbfError(LBF_EUNSTABLE) after a step that
     starts at a time level divisible by it found a non-finite or too fast
     state (0: no checks)."""
 
     def __init__(self, case, tile: Optional[Sequence[int]] = None, device: str = "cuda",
                  stream=None, plane_pad: int = 0, check_every: int = 1000,
-                 row_block: int = 4):
+                 row_block: Optional[int] = None):
         torch = _torch()
         L = load()
         self.case = case
         self.nx, self.ny = case.nx, case.ny
         self.params = make_params(case)
         self.params.plane_pad = int(plane_pad)
+        if row_block is None:
+            from . import autotune
+            row_block = autotune.lookup_layout(self.nx, self.ny)[0]
         self.params.row_block = int(row_block)
         self.params.check_every = int(check_every)
         self.device = torch.device(device)

@@ -38,7 +38,8 @@ def test_tuning_table_is_well_formed():
     for size in ((2048, 2048), (4096, 2048)):
         rb, pad = autotune.lookup_layout(*size)
         assert rb in (0, 1, 2, 4, 8, 16, 32) and pad % 64 == 0
-    assert autotune.lookup_layout(123, 45) == (4, 0)
+    assert autotune.lookup_layout(123, 45) == (1, 0)
+    assert autotune.lookup_layout(1000, 45) == (4, 0)
     for size in ((256, 128, 30), (256, 256, 256)):
         rb, pad = autotune.lookup_layout3(*size)
         assert rb in (0, 1, 2, 4, 8, 16, 32, 64) and pad % 64 == 0
