@@ -255,6 +255,8 @@ def d3q19(lbf, torch, steps):
                         ("sphere_drop_256x256x256", W3.sphere_drop(256, 64.0))):
         rb, pad = autotune.lookup_layout3(case.nx, case.ny, case.nz)
         sim = lbf.Sim3(case, plane_pad=pad, row_block=rb)
+        strip = autotune.lookup_strip3(case.nx, case.ny, case.nz)
+        sim.set_strip(strip)
         sim.step(max(steps // 10, 5))
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -272,7 +274,7 @@ def d3q19(lbf, torch, steps):
         n = case.nodes
         gbs = (BYTES3_MOMENTS + BYTES3_STEP) * n / (ms * 1e-3) / 1e9
         out[label] = {
-            "nodes": n, "steps": steps, "plane_pad": pad, "row_block": rb,
+            "nodes": n, "steps": steps, "plane_pad": pad, "row_block": rb, "strip": strip,
             "mlups": round(n * steps / wall / 1e6, 1),
             "ms_per_step": round(wall / steps * 1e3, 5),
             "kernel_ms_per_step": round(ms, 5),

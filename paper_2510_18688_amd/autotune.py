@@ -147,6 +147,13 @@ def lookup_layout3(nx: int, ny: int, nz: int) -> Tuple[int, int]:
     return 32, 0
 
 
+def lookup_strip3(nx: int, ny: int, nz: int) -> int:
+    """Tuned rows per strip of the D3Q19 step pass's node order
+    (lbf3_set_strip); 16 if that size was not measured."""
+    v = _load().get(_key(nx, ny, nz))
+    return int(v.get("strip", 16)) if v else 16
+
+
 def tune_layout(case, tile: Optional[Sequence[int]] = None, steps: int = 100, repeats: int = 3,
                 candidates: Iterable[Sequence[int]] = LAYOUT_CANDIDATES, save: bool = True
                 ) -> Tuple[Tuple[int, int], dict]:

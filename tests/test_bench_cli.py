@@ -44,4 +44,6 @@ def test_tuning_table_is_well_formed():
         rb, pad = autotune.lookup_layout3(*size)
         assert rb in (0, 1, 2, 4, 8, 16, 32, 64) and pad % 64 == 0
     assert autotune.lookup_layout3(7, 8, 9) == (32, 0)
+    assert autotune.lookup_strip3(256, 256, 256) in (8, 16, 32, 64)
+    assert autotune.lookup_strip3(7, 8, 9) == 16
     assert autotune.lookup(2000, 2000) == autotune.lookup(2048, 2048)

@@ -166,6 +166,7 @@ def test_d3q19_fracture_at_stated_length(lbf_mod):
     case = W3.fracture()
     rb, pad = autotune.lookup_layout3(case.nx, case.ny, case.nz)
     sim = lbf_mod.Sim3(case, plane_pad=pad, row_block=rb)
+    sim.set_strip(autotune.lookup_strip3(case.nx, case.ny, case.nz))
     done, hist = 0, []
     while done < case.steps:
         sim.step(2500)
@@ -186,6 +187,7 @@ def test_d3q19_cube256_against_oracle(lbf_mod):
     case = W3.sphere_drop(256, 64.0)
     rb, pad = autotune.lookup_layout3(case.nx, case.ny, case.nz)
     sim = lbf_mod.Sim3(case, plane_pad=pad, row_block=rb)
+    sim.set_strip(autotune.lookup_strip3(case.nx, case.ny, case.nz))
     orc = O3.Oracle3(case)
     sim.step(5)
     orc.step(5)

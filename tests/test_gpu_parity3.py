@@ -113,6 +113,7 @@ def test_fracture_full_size(lbf_mod, O3):
     case = W3.fracture()
     rb, pad = autotune.lookup_layout3(case.nx, case.ny, case.nz)
     sim = lbf_mod.Sim3(case, plane_pad=pad, row_block=rb)
+    sim.set_strip(autotune.lookup_strip3(case.nx, case.ny, case.nz))
     orc = O3.Oracle3(case)
     sim.step(5)
     orc.step(5)
