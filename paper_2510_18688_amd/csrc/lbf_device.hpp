@@ -203,8 +203,12 @@ __device__ __forceinline__ float ldp(Rsrc r, int plane, int P, int k) {
 __device__ __forceinline__ float lda(Rsrc r, uint32_t elem) {
   return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, elem * 4u, 0, 0));
 }
-// store policy 2, non-temporal: the new state is not re-read in this pass
-constexpr int kStorePolicy = 2;
+// Store cache policy: non-temporal (2; the new state is not re-read in this
+// pass) with the SC1 scope bit (16).  Measured against non-temporal alone:
+// 1.8 % faster on the 2048^2 step, 0.7 % on the 4096 x 2048 medium, the same
+// on the D3Q19 passes; no policy, SC0 or SC0 + NT were 3-5 % slower.  The
+// stored values and every result are the same bits under each policy.
+constexpr int kStorePolicy = 16 | 2;
 __device__ __forceinline__ void stp(Rsrc r, int plane, int P, int k, float v) {
   __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (uint32_t)k * 4u,
                                         (uint32_t)plane * (uint32_t)P * 4u, kStorePolicy);
