@@ -326,8 +326,14 @@ __device__ __forceinline__ void step_strip(const Geo& G, const Phys& ph, const B
       for (int f = 0; f < NSV; ++f) sh.v[f][slot_n][l + 1] = st[f];
       next_c = ain;
       if (more) {
+        // the next rows' loads go out at a raised wave priority, so that a
+        // wave about to issue them is scheduled before waves in their
+        // collision (1.2 % on the 2048^2 step, 1.1 % on the 4096 x 2048
+        // medium; the same bits)
+        __builtin_amdgcn_s_setprio(1);
         node_load(G, ph, B, x, map_axis(ya + dir, G.ny, G.py), ain, !ring_row(ya + dir));
         flow_load<false>(G, ph, B, x, ya, fnx);   // before this row's collision
+        __builtin_amdgcn_s_setprio(0);
       }
     }
     if (l == 0 || l == lastl) {
