@@ -211,6 +211,9 @@ __device__ __forceinline__ void step_strip(const Geo& G, const Phys& ph, const B
   double a_sphi = 0, a_heat = 0, a_flux = 0, a_reset = 0;
 
   // halo columns x0 - 1 and x0 + lastl + 1 for rows y0 - 1 .. y1, one node per lane
+  // (the prologue's loads, up to the first rows', at the raised priority of
+  // a load phase: see the main loop)
+  __builtin_amdgcn_s_setprio(1);
   {
     const int xl = map_axis(x0 - 1, G.nx, G.px);
     const int xr = map_axis(x0 + lastl + 1, G.nx, G.px);
@@ -267,6 +270,7 @@ __device__ __forceinline__ void step_strip(const Geo& G, const Phys& ph, const B
     node_load(G, ph, B, x, ys, cin);
     node_load(G, ph, B, x, map_axis(ys + dir, G.ny, G.py), ain, !ring_row(ys + dir));
     flow_load<false>(G, ph, B, x, ys, fin);
+    __builtin_amdgcn_s_setprio(0);
     node_finish(ph, bin, m, st);
     st[4] = bin.phi0;
 #pragma unroll
@@ -316,8 +320,11 @@ __device__ __forceinline__ void step_strip(const Geo& G, const Phys& ph, const B
         }
         if (more) {
           urow_store(sh, l, lastl, y + 3 * dir, un);
-          if (it + 2 < nrow)
+          if (it + 2 < nrow) {
+            __builtin_amdgcn_s_setprio(1);   // a load phase (see below)
             urow_load(G, B, x, xl, xr, map_axis(y + 4 * dir, G.ny, G.py), l == 0, l == lastl, un);
+            __builtin_amdgcn_s_setprio(0);
+          }
         }
       }
       node_finish(ph, ain, am, st);
@@ -328,8 +335,9 @@ __device__ __forceinline__ void step_strip(const Geo& G, const Phys& ph, const B
       if (more) {
         // the next rows' loads go out at a raised wave priority, so that a
         // wave about to issue them is scheduled before waves in their
-        // collision (1.2 % on the 2048^2 step, 1.1 % on the 4096 x 2048
-        // medium; the same bits)
+        // collision (with the velocity ring's and the prologue's loads
+        // raised too: 2048^2 step 0.2372 -> 0.2317 ms, 4096 x 2048 medium
+        // 0.5332 -> 0.5224 ms; the same bits)
         __builtin_amdgcn_s_setprio(1);
         node_load(G, ph, B, x, map_axis(ya + dir, G.ny, G.py), ain, !ring_row(ya + dir));
         flow_load<false>(G, ph, B, x, ya, fnx);   // before this row's collision
